@@ -1,0 +1,1258 @@
+/*
+ * FP64 CPU oracle for the p-multigrid method with an ILUT smoother of
+ * Tielen, Moeller, Goeddeke and Vuik, "A p-multigrid method enhanced with an
+ * ILUT smoother and its comparison to h-multigrid methods within
+ * Isogeometric Analysis" (arXiv:1901.01685).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the library, and the library
+ * never calls it.
+ *
+ * Everything is FP64, single-threaded, and compiled with -ffp-contract=off
+ * (no FMA contraction), so every sum below is evaluated exactly in the order
+ * written.  Each function names the passage of the paper it follows; where
+ * the paper is silent or ambiguous the reading taken is stated inline and
+ * listed in the design notes of the repository.
+ *
+ * Parity status of each part (what pins it, see tests/test_oracle_*.py):
+ *   basis, quadrature, geometry, assembly, lumping, transfers, P1 hierarchy,
+ *   smoother algebra, V-cycle identities, CG ........ pinned
+ *   ILUT with tau = 1e-12, m = 1 (values) ........... parity unpinned: only
+ *     invariants and the exact-LU limit (tau = 0, unlimited fill) are fixed
+ *     by the paper and by mathematics; the values for the paper's constants
+ *     are the oracle's own reading of the two dropping rules.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOMEM 2
+#define ORC_EZEROPIVOT 4
+#define ORC_EDIVERGED 5
+#define ORC_EMAXIT 6
+#define ORC_ENAN 7
+
+#define MAXLEV 24
+
+/* ------------------------------------------------------------------------ */
+/* Compressed sparse row storage (rows sorted by column).                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int nrows, ncols;
+  int64_t nnz;
+  int64_t *rp;  /* nrows + 1 */
+  int *ci;      /* nnz */
+  double *v;    /* nnz */
+} ocsr;
+
+static void csr_free(ocsr *m) {
+  free(m->rp);
+  free(m->ci);
+  free(m->v);
+  memset(m, 0, sizeof(*m));
+}
+
+/* y = A x */
+static void csr_mv(const ocsr *A, const double *x, double *y) {
+  for (int i = 0; i < A->nrows; ++i) {
+    double s = 0.0;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s += A->v[k] * x[A->ci[k]];
+    y[i] = s;
+  }
+}
+
+/* position of column j in row i, -1 if absent (binary search) */
+static int64_t csr_find(const ocsr *A, int i, int j) {
+  int64_t lo = A->rp[i], hi = A->rp[i + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (A->ci[mid] == j) return mid;
+    if (A->ci[mid] < j) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+static int csr_transpose(const ocsr *A, ocsr *T) {
+  T->nrows = A->ncols;
+  T->ncols = A->nrows;
+  T->nnz = A->nnz;
+  T->rp = calloc((size_t)T->nrows + 1, sizeof(int64_t));
+  T->ci = malloc((size_t)(A->nnz > 0 ? A->nnz : 1) * sizeof(int));
+  T->v = malloc((size_t)(A->nnz > 0 ? A->nnz : 1) * sizeof(double));
+  if (!T->rp || !T->ci || !T->v) return ORC_ENOMEM;
+  for (int64_t k = 0; k < A->nnz; ++k) T->rp[A->ci[k] + 1]++;
+  for (int i = 0; i < T->nrows; ++i) T->rp[i + 1] += T->rp[i];
+  int64_t *pos = malloc((size_t)(T->nrows > 0 ? T->nrows : 1) * sizeof(int64_t));
+  if (!pos) return ORC_ENOMEM;
+  memcpy(pos, T->rp, (size_t)T->nrows * sizeof(int64_t));
+  for (int i = 0; i < A->nrows; ++i)
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      int64_t d = pos[A->ci[k]]++;
+      T->ci[d] = i;
+      T->v[d] = A->v[k];
+    }
+  free(pos);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre quadrature on [-1, 1] ("standard Gauss quadrature" of the  */
+/* cost discussion in Section 3).  Nodes are roots of the Legendre            */
+/* polynomial P_n found by Newton's method from the Chebyshev-like guess     */
+/* cos(pi (i + 3/4) / (n + 1/2)); weights 2 / ((1 - x^2) P_n'(x)^2).          */
+/* Nodes are returned in increasing order.                                   */
+/* ------------------------------------------------------------------------ */
+int orc_gauss(int n, double *x, double *w) {
+  if (n < 1 || n > 64) return ORC_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      /* three-term recurrence (k+1) P_{k+1} = (2k+1) z P_k - k P_{k-1} */
+      double pk = 1.0, pkm1 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double pkp1 = ((2.0 * k + 1.0) * z * pk - k * pkm1) / (k + 1.0);
+        pkm1 = pk;
+        pk = pkp1;
+      }
+      /* P_n = pk, P_{n-1} = pkm1; P_n'(z) = n (z P_n - P_{n-1}) / (z^2 - 1) */
+      dp = n * (z * pk - pkm1) / (z * z - 1.0);
+      double dz = pk / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    /* recompute derivative at the converged root */
+    double pk = 1.0, pkm1 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double pkp1 = ((2.0 * k + 1.0) * z * pk - k * pkm1) / (k + 1.0);
+      pkm1 = pk;
+      pk = pkp1;
+    }
+    dp = n * (z * pk - pkm1) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Knot vectors and B-splines (Section 2, "B-spline basis functions").       */
+/* Open uniform knot vector of degree p on n_el elements of size h = 1/n_el: */
+/* p+1 zeros, the interior knots k/n_el, p+1 ones; N = n_el + p functions.   */
+/* ------------------------------------------------------------------------ */
+int orc_knots(int p, int nel, double *t) {
+  if (p < 0 || nel < 1) return ORC_EINVAL;
+  int nk = nel + 2 * p + 1;
+  for (int i = 0; i <= p; ++i) t[i] = 0.0;
+  for (int k = 1; k < nel; ++k) t[p + k] = (double)k / (double)nel;
+  for (int i = 0; i <= p; ++i) t[nk - 1 - i] = 1.0;
+  return ORC_OK;
+}
+
+/* Values and first derivatives of all N = nk - p - 1 B-splines of degree p
+ * at xi, by the Cox-de Boor recursion, raised one degree at a time over the
+ * whole knot vector:
+ *   phi_{i,0}(xi) = 1 on [t_i, t_{i+1}), 0 elsewhere,
+ *   phi_{i,k} = (xi - t_i)/(t_{i+k} - t_i) phi_{i,k-1}
+ *             + (t_{i+k+1} - xi)/(t_{i+k+1} - t_{i+1}) phi_{i+1,k-1},
+ *   phi'_{i,p} = p phi_{i,p-1}/(t_{i+p} - t_i) - p phi_{i+1,p-1}/(t_{i+p+1} - t_{i+1}),
+ * with any quotient whose denominator vanishes taken as 0.  At the right end
+ * xi = t_last the last non-empty interval is taken as closed, so the basis
+ * interpolates at both ends.  ders may be NULL. */
+int orc_basis(const double *t, int nk, int p, double xi, double *vals, double *ders) {
+  int nb = nk - p - 1;
+  if (nb < 1 || p < 0) return ORC_EINVAL;
+  double *b = calloc((size_t)nk, sizeof(double));
+  double *prev = calloc((size_t)nk, sizeof(double));
+  if (!b || !prev) { free(b); free(prev); return ORC_ENOMEM; }
+  /* degree 0 */
+  int last = -1;
+  for (int i = 0; i + 1 < nk; ++i)
+    if (t[i] < t[i + 1]) last = i;
+  for (int i = 0; i + 1 < nk; ++i) {
+    if (t[i] < t[i + 1] && ((xi >= t[i] && xi < t[i + 1]) || (i == last && xi == t[i + 1])))
+      b[i] = 1.0;
+    else
+      b[i] = 0.0;
+  }
+  for (int k = 1; k <= p; ++k) {
+    memcpy(prev, b, (size_t)nk * sizeof(double));
+    for (int i = 0; i + k + 1 < nk; ++i) {
+      double left = 0.0, right = 0.0;
+      double d1 = t[i + k] - t[i];
+      double d2 = t[i + k + 1] - t[i + 1];
+      if (d1 != 0.0) left = (xi - t[i]) / d1 * prev[i];
+      if (d2 != 0.0) right = (t[i + k + 1] - xi) / d2 * prev[i + 1];
+      b[i] = left + right;
+    }
+    for (int i = nk - k - 1; i < nk; ++i) b[i] = 0.0;
+    if (k == p && ders) {
+      for (int i = 0; i < nb; ++i) {
+        double dl = 0.0, dr = 0.0;
+        double d1 = t[i + p] - t[i];
+        double d2 = t[i + p + 1] - t[i + 1];
+        if (d1 != 0.0) dl = p * prev[i] / d1;
+        if (d2 != 0.0) dr = p * prev[i + 1] / d2;
+        ders[i] = dl - dr;
+      }
+    }
+  }
+  if (p == 0 && ders)
+    for (int i = 0; i < nb; ++i) ders[i] = 0.0;
+  for (int i = 0; i < nb; ++i) vals[i] = b[i];
+  free(b);
+  free(prev);
+  return ORC_OK;
+}
+
+/* One-dimensional tables on a uniform mesh: for element e and quadrature
+ * point q, the p+1 B-splines of degree p that are non-zero on element e are
+ * those with (0-based, full) index e .. e+p. */
+typedef struct {
+  int p, nel, nq;
+  double *xi;  /* [nel][nq] parameter coordinate */
+  double *wt;  /* [nel][nq] weight including the element half-length */
+  double *val; /* [nel][nq][p+1] */
+  double *der; /* [nel][nq][p+1] */
+} tab1d;
+
+static int tab1d_make(tab1d *T, int p, int nel, int nq) {
+  T->p = p; T->nel = nel; T->nq = nq;
+  int nk = nel + 2 * p + 1, nb = nel + p;
+  T->xi = malloc(sizeof(double) * (size_t)nel * nq);
+  T->wt = malloc(sizeof(double) * (size_t)nel * nq);
+  T->val = malloc(sizeof(double) * (size_t)nel * nq * (p + 1));
+  T->der = malloc(sizeof(double) * (size_t)nel * nq * (p + 1));
+  double *t = malloc(sizeof(double) * nk), *gx = malloc(sizeof(double) * nq),
+         *gw = malloc(sizeof(double) * nq), *bv = malloc(sizeof(double) * nb),
+         *bd = malloc(sizeof(double) * nb);
+  if (!T->xi || !T->wt || !T->val || !T->der || !t || !gx || !gw || !bv || !bd) return ORC_ENOMEM;
+  orc_knots(p, nel, t);
+  orc_gauss(nq, gx, gw);
+  for (int e = 0; e < nel; ++e) {
+    double a = t[p + e], b = t[p + e + 1];
+    double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+    for (int q = 0; q < nq; ++q) {
+      double xi = mid + half * gx[q];
+      T->xi[e * nq + q] = xi;
+      T->wt[e * nq + q] = gw[q] * half;
+      orc_basis(t, nk, p, xi, bv, bd);
+      for (int l = 0; l <= p; ++l) {
+        T->val[((size_t)e * nq + q) * (p + 1) + l] = bv[e + l];
+        T->der[((size_t)e * nq + q) * (p + 1) + l] = bd[e + l];
+      }
+    }
+  }
+  free(t); free(gx); free(gw); free(bv); free(bd);
+  return ORC_OK;
+}
+
+static void tab1d_free(tab1d *T) {
+  free(T->xi); free(T->wt); free(T->val); free(T->der);
+  memset(T, 0, sizeof(*T));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry map F: parameter domain (0,1)^d -> physical domain (Section 2).  */
+/*  geom 0: unit square / unit cube, F = identity (benchmarks 2 and 4).      */
+/*  geom 1: quarter annulus with radii 1 and 2 (benchmark 1).  The paper     */
+/*    gives no parameterisation; the reading taken is                         */
+/*    F(xi, eta) = (1 + xi) C(eta), C the rational quadratic quarter circle   */
+/*    with control points (1,0), (1,1), (0,1) and weights (1, sqrt(2)/2, 1), */
+/*    so xi is radial and eta angular.                                       */
+/* ------------------------------------------------------------------------ */
+static void geom_eval(int geom, int dim, const double *xi, double *X, double J[3][3], double *detJ) {
+  if (geom == 0) {
+    for (int a = 0; a < 3; ++a) {
+      X[a] = a < dim ? xi[a] : 0.0;
+      for (int b = 0; b < 3; ++b) J[a][b] = (a == b) ? 1.0 : 0.0;
+    }
+    *detJ = 1.0;
+    return;
+  }
+  /* quarter annulus, dim == 2 */
+  double r = 1.0 + xi[0], s = xi[1];
+  double w1 = sqrt(2.0) / 2.0;
+  double B0 = (1.0 - s) * (1.0 - s), B1 = 2.0 * s * (1.0 - s), B2 = s * s;
+  double dB0 = -2.0 * (1.0 - s), dB1 = 2.0 - 4.0 * s, dB2 = 2.0 * s;
+  double W = B0 + w1 * B1 + B2, dW = dB0 + w1 * dB1 + dB2;
+  double Nx = B0 + w1 * B1, dNx = dB0 + w1 * dB1;
+  double Ny = w1 * B1 + B2, dNy = w1 * dB1 + dB2;
+  double Cx = Nx / W, Cy = Ny / W;
+  double dCx = (dNx * W - Nx * dW) / (W * W), dCy = (dNy * W - Ny * dW) / (W * W);
+  X[0] = r * Cx;
+  X[1] = r * Cy;
+  X[2] = 0.0;
+  memset(J, 0, sizeof(double) * 9);
+  J[0][0] = Cx; J[0][1] = r * dCx;
+  J[1][0] = Cy; J[1][1] = r * dCy;
+  J[2][2] = 1.0;
+  *detJ = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+}
+
+/* inverse of the dim x dim Jacobian (cofactor formula) */
+static void inv_jac(int dim, double J[3][3], double det, double Ji[3][3]) {
+  memset(Ji, 0, sizeof(double) * 9);
+  if (dim == 2) {
+    Ji[0][0] = J[1][1] / det; Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+  } else {
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  }
+}
+
+int orc_geom(int geom, int dim, const double *xi, double *X, double *detJ) {
+  double J[3][3];
+  geom_eval(geom, dim, xi, X, J, detJ);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Manufactured solutions and right-hand sides (Section 2, benchmarks).      */
+/*  rhs 0: u = prod_a sin(k_a pi x_a) on the box, f = -Lap u                  */
+/*         = pi^2 (sum k_a^2) u  (benchmark 4 and the Poisson reading of     */
+/*         benchmark 2's solution; k = 1 gives the paper's u).               */
+/*  rhs 1: u = -(x^2+y^2-1)(x^2+y^2-4) x y^2 (benchmark 1); with s = x^2+y^2, */
+/*         -Lap u = 40 x y^2 (s - 2) + 2 x (s^2 - 5 s + 4).                  */
+/* ------------------------------------------------------------------------ */
+double orc_exact_u(int rhs, int dim, const int *k, const double *X) {
+  if (rhs == 0) {
+    double u = 1.0;
+    for (int a = 0; a < dim; ++a) u *= sin(k[a] * M_PI * X[a]);
+    return u;
+  }
+  double x = X[0], y = X[1], s = x * x + y * y;
+  return -(s - 1.0) * (s - 4.0) * x * y * y;
+}
+
+double orc_rhs_f(int rhs, int dim, const int *k, const double *X) {
+  if (rhs == 0) {
+    double ks = 0.0;
+    for (int a = 0; a < dim; ++a) ks += (double)k[a] * (double)k[a];
+    return M_PI * M_PI * ks * orc_exact_u(0, dim, k, X);
+  }
+  double x = X[0], y = X[1], s = x * x + y * y;
+  return 40.0 * x * y * y * (s - 2.0) + 2.0 * x * (s * s - 5.0 * s + 4.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Index maps.  Tensor functions carry a multi-index (i_x, i_y[, i_z]); the  */
+/* paper's global-index formula is garbled, the reading taken is the 0-based */
+/* x-fastest lexicographic order.  Dirichlet conditions are imposed by       */
+/* eliminating every function with index 0 or N-1 in some direction         */
+/* (Section 5, experimental set-up), leaving (N-2)^d unknowns.               */
+/* ------------------------------------------------------------------------ */
+static int gidx(int dim, const int *m, int nb, int elim) {
+  int g = 0, stride = 1;
+  for (int a = 0; a < dim; ++a) {
+    int i = m[a];
+    if (elim) {
+      if (i == 0 || i == nb - 1) return -1;
+      i -= 1;
+      g += i * stride;
+      stride *= (nb - 2);
+    } else {
+      g += i * stride;
+      stride *= nb;
+    }
+  }
+  return g;
+}
+
+static int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+static void unflat(int idx, int base, int dim, int *m) {
+  for (int a = 0; a < dim; ++a) { m[a] = idx % base; idx /= base; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Element-loop Galerkin assembly (Section 2, discrete system; Section 3,    */
+/* mass and transfer matrices).  kind 0: stiffness int grad(F_i).grad(F_j);  */
+/* kind 1: mass / transfer int F_i F_j.  Row functions have degree pr, column */
+/* functions degree pc, both on the same uniform knot mesh of n_el elements; */
+/* nq Gauss points per direction and element.  The sparsity pattern is every */
+/* pair of functions whose supports share an element.  Element contributions */
+/* are added in element order (x fastest), quadrature points in order.       */
+/* ------------------------------------------------------------------------ */
+typedef struct { int dim, geom, nel; } omesh;
+
+static int assemble(const omesh *M, int kind, int pr, int pc, int nq, int elim, ocsr *out) {
+  int dim = M->dim, nel = M->nel;
+  int nbr = nel + pr, nbc = nel + pc;
+  int nr1 = elim ? nbr - 2 : nbr, nc1 = elim ? nbc - 2 : nbc;
+  int nrows = ipow(nr1, dim), ncols = ipow(nc1, dim);
+  tab1d Tr, Tc;
+  if (tab1d_make(&Tr, pr, nel, nq) || tab1d_make(&Tc, pc, nel, nq)) return ORC_ENOMEM;
+  int nlr = ipow(pr + 1, dim), nlc = ipow(pc + 1, dim), nqt = ipow(nq, dim), net = ipow(nel, dim);
+  int cap = ipow(pr + pc + 2, dim);
+  /* pass 1: pattern */
+  int *cnt = calloc((size_t)nrows, sizeof(int));
+  int *cols = malloc(sizeof(int) * (size_t)nrows * cap);
+  int *lr = malloc(sizeof(int) * nlr), *lc = malloc(sizeof(int) * nlc);
+  if (!cnt || !cols || !lr || !lc) return ORC_ENOMEM;
+  int em[3], am[3], fm[3], qm[3];
+  for (int e = 0; e < net; ++e) {
+    unflat(e, nel, dim, em);
+    for (int l = 0; l < nlr; ++l) {
+      unflat(l, pr + 1, dim, am);
+      for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
+      lr[l] = gidx(dim, fm, nbr, elim);
+    }
+    for (int l = 0; l < nlc; ++l) {
+      unflat(l, pc + 1, dim, am);
+      for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
+      lc[l] = gidx(dim, fm, nbc, elim);
+    }
+    for (int a = 0; a < nlr; ++a) {
+      int i = lr[a];
+      if (i < 0) continue;
+      int *row = cols + (size_t)i * cap;
+      for (int b = 0; b < nlc; ++b) {
+        int j = lc[b];
+        if (j < 0) continue;
+        /* sorted unique insertion */
+        int n = cnt[i], pos = n;
+        int found = 0;
+        for (int s = 0; s < n; ++s) {
+          if (row[s] == j) { found = 1; break; }
+          if (row[s] > j) { pos = s; break; }
+        }
+        if (found) continue;
+        for (int s = n; s > pos; --s) row[s] = row[s - 1];
+        row[pos] = j;
+        cnt[i] = n + 1;
+      }
+    }
+  }
+  out->nrows = nrows;
+  out->ncols = ncols;
+  out->rp = malloc(sizeof(int64_t) * ((size_t)nrows + 1));
+  out->rp[0] = 0;
+  for (int i = 0; i < nrows; ++i) out->rp[i + 1] = out->rp[i] + cnt[i];
+  out->nnz = out->rp[nrows];
+  out->ci = malloc(sizeof(int) * (size_t)(out->nnz > 0 ? out->nnz : 1));
+  out->v = calloc((size_t)(out->nnz > 0 ? out->nnz : 1), sizeof(double));
+  for (int i = 0; i < nrows; ++i)
+    memcpy(out->ci + out->rp[i], cols + (size_t)i * cap, sizeof(int) * cnt[i]);
+  free(cols);
+  free(cnt);
+  /* pass 2: values */
+  double *vr = malloc(sizeof(double) * nlr), *vc = malloc(sizeof(double) * nlc);
+  double *gr = malloc(sizeof(double) * nlr * 3), *gc = malloc(sizeof(double) * nlc * 3);
+  for (int e = 0; e < net; ++e) {
+    unflat(e, nel, dim, em);
+    for (int l = 0; l < nlr; ++l) {
+      unflat(l, pr + 1, dim, am);
+      for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
+      lr[l] = gidx(dim, fm, nbr, elim);
+    }
+    for (int l = 0; l < nlc; ++l) {
+      unflat(l, pc + 1, dim, am);
+      for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
+      lc[l] = gidx(dim, fm, nbc, elim);
+    }
+    for (int q = 0; q < nqt; ++q) {
+      unflat(q, nq, dim, qm);
+      double xi[3] = {0, 0, 0}, wq = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        xi[a] = Tr.xi[em[a] * nq + qm[a]];
+        wq *= Tr.wt[em[a] * nq + qm[a]];
+      }
+      double X[3], J[3][3], det, Ji[3][3];
+      geom_eval(M->geom, dim, xi, X, J, &det);
+      inv_jac(dim, J, det, Ji);
+      double dw = wq * det;
+      /* values and physical gradients of the local functions */
+      for (int side = 0; side < 2; ++side) {
+        const tab1d *T = side == 0 ? &Tr : &Tc;
+        int p = T->p, nl = side == 0 ? nlr : nlc;
+        double *vv = side == 0 ? vr : vc, *gg = side == 0 ? gr : gc;
+        for (int l = 0; l < nl; ++l) {
+          unflat(l, p + 1, dim, am);
+          double val = 1.0, gh[3];
+          for (int b = 0; b < dim; ++b) {
+            size_t o = ((size_t)em[b] * nq + qm[b]) * (p + 1) + am[b];
+            val *= T->val[o];
+          }
+          for (int c = 0; c < dim; ++c) {
+            double g = 1.0;
+            for (int b = 0; b < dim; ++b) {
+              size_t o = ((size_t)em[b] * nq + qm[b]) * (p + 1) + am[b];
+              g *= (b == c) ? T->der[o] : T->val[o];
+            }
+            gh[c] = g;
+          }
+          vv[l] = val;
+          for (int c = 0; c < dim; ++c) {
+            double g = 0.0;
+            for (int b = 0; b < dim; ++b) g += Ji[b][c] * gh[b];
+            gg[l * 3 + c] = g;
+          }
+        }
+      }
+      for (int a = 0; a < nlr; ++a) {
+        int i = lr[a];
+        if (i < 0) continue;
+        for (int b = 0; b < nlc; ++b) {
+          int j = lc[b];
+          if (j < 0) continue;
+          double integrand;
+          if (kind == 0) {
+            double d = 0.0;
+            for (int c = 0; c < dim; ++c) d += gr[a * 3 + c] * gc[b * 3 + c];
+            integrand = d;
+          } else {
+            integrand = vr[a] * vc[b];
+          }
+          int64_t k = csr_find(out, i, j);
+          out->v[k] += dw * integrand;
+        }
+      }
+    }
+  }
+  free(vr); free(vc); free(gr); free(gc); free(lr); free(lc);
+  tab1d_free(&Tr);
+  tab1d_free(&Tc);
+  return ORC_OK;
+}
+
+/* Load vector f_i = int f Phi_i over the interior functions of degree p. */
+static int assemble_load(const omesh *M, int p, int nq, int rhs, const int *k, double *f) {
+  int dim = M->dim, nel = M->nel, nb = nel + p;
+  int n = ipow(nb - 2, dim);
+  memset(f, 0, sizeof(double) * (size_t)n);
+  tab1d T;
+  if (tab1d_make(&T, p, nel, nq)) return ORC_ENOMEM;
+  int nl = ipow(p + 1, dim), nqt = ipow(nq, dim), net = ipow(nel, dim);
+  int em[3], am[3], fm[3], qm[3];
+  for (int e = 0; e < net; ++e) {
+    unflat(e, nel, dim, em);
+    for (int q = 0; q < nqt; ++q) {
+      unflat(q, nq, dim, qm);
+      double xi[3] = {0, 0, 0}, wq = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        xi[a] = T.xi[em[a] * nq + qm[a]];
+        wq *= T.wt[em[a] * nq + qm[a]];
+      }
+      double X[3], J[3][3], det;
+      geom_eval(M->geom, dim, xi, X, J, &det);
+      double fx = orc_rhs_f(rhs, dim, k, X);
+      for (int l = 0; l < nl; ++l) {
+        unflat(l, p + 1, dim, am);
+        for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
+        int i = gidx(dim, fm, nb, 1);
+        if (i < 0) continue;
+        double val = 1.0;
+        for (int b = 0; b < dim; ++b) val *= T.val[((size_t)em[b] * nq + qm[b]) * (p + 1) + am[b]];
+        f[i] += wq * det * fx * val;
+      }
+    }
+  }
+  tab1d_free(&T);
+  return ORC_OK;
+}
+
+/* Row-sum lumping (Section 3, "Prolongation and restriction"):
+ * M^L_ii = sum_j M_ij.  The reading taken: the sum runs over all columns of
+ * the full mass matrix (boundary functions included, before elimination),
+ * and only the interior rows are kept.  Returns the interior diagonal. */
+static int lumped_mass(const omesh *M, int p, int nq, double *ml) {
+  ocsr Mf = {0};
+  int rc = assemble(M, 1, p, p, nq, 0, &Mf);
+  if (rc) return rc;
+  int nb = M->nel + p, dim = M->dim;
+  int m[3];
+  for (int g = 0; g < Mf.nrows; ++g) {
+    int t = g;
+    for (int a = 0; a < dim; ++a) { m[a] = t % nb; t /= nb; }
+    int i = gidx(dim, m, nb, 1);
+    if (i < 0) continue;
+    double s = 0.0;
+    for (int64_t k = Mf.rp[g]; k < Mf.rp[g + 1]; ++k) s += Mf.v[k];
+    ml[i] = s;
+  }
+  csr_free(&Mf);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Canonical prolongation between nested degree-1 spaces on meshes of n_c and */
+/* 2 n_c elements (Section 3, coarse solve by h-multigrid): the coarse hat    */
+/* at knot I is the fine hat at 2I plus half the fine hats at 2I-1 and 2I+1;  */
+/* tensor products of these 1-D weights.  Interior indices only.             */
+/* ------------------------------------------------------------------------ */
+static int canonical_prolongation(int dim, int nc, ocsr *P) {
+  int nf = 2 * nc;
+  int nci = nc - 1, nfi = nf - 1;
+  int nrows = ipow(nfi, dim), ncols = ipow(nci, dim);
+  /* 1-D matrix: fine interior f (full f+1) x coarse interior c (full c+1) */
+  double *P1 = calloc((size_t)nfi * nci, sizeof(double));
+  for (int c = 0; c < nci; ++c) {
+    int I = c + 1;
+    int f0 = 2 * I - 1; /* fine interior index of full knot 2I */
+    P1[(size_t)f0 * nci + c] = 1.0;
+    P1[(size_t)(f0 - 1) * nci + c] = 0.5;
+    P1[(size_t)(f0 + 1) * nci + c] = 0.5;
+  }
+  P->nrows = nrows;
+  P->ncols = ncols;
+  P->rp = malloc(sizeof(int64_t) * ((size_t)nrows + 1));
+  int cap = ipow(2, dim);
+  P->ci = malloc(sizeof(int) * (size_t)nrows * cap);
+  P->v = malloc(sizeof(double) * (size_t)nrows * cap);
+  int64_t nz = 0;
+  P->rp[0] = 0;
+  int fm[3], cm[3];
+  int nlc = ipow(nci, dim);
+  for (int r = 0; r < nrows; ++r) {
+    unflat(r, nfi, dim, fm);
+    for (int c = 0; c < nlc; ++c) {
+      unflat(c, nci, dim, cm);
+      double w = 1.0;
+      for (int a = 0; a < dim; ++a) w *= P1[(size_t)fm[a] * nci + cm[a]];
+      if (w != 0.0) { P->ci[nz] = c; P->v[nz] = w; nz++; }
+    }
+    P->rp[r + 1] = nz;
+  }
+  P->nnz = nz;
+  free(P1);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ILUT(tau, m) (Section 3, "Smoother"), dual threshold incomplete LU of a   */
+/* square CSR matrix, computed row by row (i-k-j order, pivots k taken in    */
+/* increasing order).  For row i with work row w = a_i:                      */
+/*   tau_i = tau * (sum_j |a_ij|) / nnz_i   (rule 1: "tau times the average   */
+/*           magnitude of the elements of the row", read over the stored      */
+/*           entries of the original row);                                    */
+/*   for k < i in increasing order with w_k != 0:                             */
+/*       w_k <- w_k / u_kk; if |w_k| < tau_i drop it, else w <- w - w_k u_k;  */
+/*   drop every remaining |w_j| < tau_i except the diagonal;                  */
+/*   rule 2: keep the M largest entries in the strict lower part and the M    */
+/*   largest in the strict upper part, M = floor(m nnz(A) / n) (mode 0, "per  */
+/*   part"), or the M largest off-diagonal entries in total (mode 1, "per     */
+/*   row"); ties by |value| are broken by the smaller column; exact zeros are */
+/*   never stored.                                                            */
+/* L is returned as the strict lower part (unit diagonal implied), U as the  */
+/* upper part with the diagonal first in each row.  A zero or non-finite     */
+/* pivot is an error (no substitution).  fill <= 0 means "no limit".         */
+/* ------------------------------------------------------------------------ */
+typedef struct { int j; double v; } ent;
+
+static int ent_cmp_mag(const void *a, const void *b) {
+  const ent *x = a, *y = b;
+  double ax = fabs(x->v), ay = fabs(y->v);
+  if (ax > ay) return -1;
+  if (ax < ay) return 1;
+  return (x->j < y->j) ? -1 : (x->j > y->j);
+}
+
+static int ent_cmp_col(const void *a, const void *b) {
+  const ent *x = a, *y = b;
+  return (x->j < y->j) ? -1 : (x->j > y->j);
+}
+
+int orc_ilut_raw(int n, const int64_t *rp, const int *ci, const double *v, double tau, double fill,
+                 int mode, ocsr *L, ocsr *U, int *bad_row) {
+  int64_t nnzA = rp[n];
+  int64_t M = fill > 0 ? (int64_t)floor(fill * (double)nnzA / (double)n) : (int64_t)n;
+  if (M < 0) M = 0;
+  double *w = calloc((size_t)n, sizeof(double));
+  char *used = calloc((size_t)n, 1);
+  int *touched = malloc(sizeof(int) * (size_t)n);
+  ent *cand = malloc(sizeof(ent) * (size_t)n);
+  /* growable outputs */
+  int64_t capL = nnzA + n, capU = nnzA + n;
+  L->rp = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  U->rp = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  L->ci = malloc(sizeof(int) * capL); L->v = malloc(sizeof(double) * capL);
+  U->ci = malloc(sizeof(int) * capU); U->v = malloc(sizeof(double) * capU);
+  if (!w || !used || !touched || !cand || !L->rp || !U->rp || !L->ci || !L->v || !U->ci || !U->v)
+    return ORC_ENOMEM;
+  L->nrows = L->ncols = U->nrows = U->ncols = n;
+  L->rp[0] = U->rp[0] = 0;
+  int64_t nzL = 0, nzU = 0;
+  for (int i = 0; i < n; ++i) {
+    int nt = 0;
+    double rs = 0.0;
+    int minc = i;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      int j = ci[k];
+      w[j] = v[k];
+      if (!used[j]) { used[j] = 1; touched[nt++] = j; }
+      rs += fabs(v[k]);
+      if (j < minc) minc = j;
+    }
+    int64_t nzi = rp[i + 1] - rp[i];
+    double taui = nzi > 0 ? tau * (rs / (double)nzi) : 0.0;
+    /* elimination with the already-factored rows k < i, in increasing k */
+    for (int k = minc; k < i; ++k) {
+      if (!used[k] || w[k] == 0.0) continue;
+      double ukk = U->v[U->rp[k]]; /* diagonal stored first */
+      double lk = w[k] / ukk;
+      if (fabs(lk) < taui) { w[k] = 0.0; continue; }
+      w[k] = lk;
+      for (int64_t s = U->rp[k] + 1; s < U->rp[k + 1]; ++s) {
+        int j = U->ci[s];
+        if (!used[j]) { used[j] = 1; touched[nt++] = j; w[j] = 0.0; }
+        w[j] -= lk * U->v[s];
+      }
+    }
+    /* pivot */
+    double d = used[i] ? w[i] : 0.0;
+    if (!(d != 0.0) || !isfinite(d)) {
+      if (bad_row) *bad_row = i;
+      for (int t = 0; t < nt; ++t) { used[touched[t]] = 0; w[touched[t]] = 0.0; }
+      free(w); free(used); free(touched); free(cand);
+      return ORC_EZEROPIVOT;
+    }
+    /* rule 1 on the final row, then rule 2 */
+    int nlo = 0, nup = 0;
+    ent *lo = cand;
+    /* collect candidates */
+    int nc = 0;
+    for (int t = 0; t < nt; ++t) {
+      int j = touched[t];
+      if (j == i) continue;
+      double x = w[j];
+      if (x == 0.0 || fabs(x) < taui) continue;
+      cand[nc].j = j;
+      cand[nc].v = x;
+      nc++;
+    }
+    int64_t keepL = 0, keepU = 0;
+    if (mode == 0) {
+      /* split into lower / upper, sort each by magnitude */
+      int a = 0;
+      for (int t = 0; t < nc; ++t)
+        if (cand[t].j < i) { ent tmp = cand[a]; cand[a] = cand[t]; cand[t] = tmp; a++; }
+      nlo = a;
+      nup = nc - a;
+      qsort(cand, (size_t)nlo, sizeof(ent), ent_cmp_mag);
+      qsort(cand + nlo, (size_t)nup, sizeof(ent), ent_cmp_mag);
+      keepL = nlo < M ? nlo : M;
+      keepU = nup < M ? nup : M;
+      /* move the kept upper entries right after the kept lower ones */
+      memmove(cand + keepL, cand + nlo, sizeof(ent) * (size_t)keepU);
+    } else {
+      qsort(cand, (size_t)nc, sizeof(ent), ent_cmp_mag);
+      int64_t keep = nc < M ? nc : M;
+      /* stable split of the kept set into lower and upper */
+      ent *tmp = malloc(sizeof(ent) * (size_t)(keep > 0 ? keep : 1));
+      int64_t a = 0;
+      for (int64_t t = 0; t < keep; ++t) if (cand[t].j < i) tmp[a++] = cand[t];
+      keepL = a;
+      for (int64_t t = 0; t < keep; ++t) if (cand[t].j > i) tmp[a++] = cand[t];
+      keepU = a - keepL;
+      memcpy(cand, tmp, sizeof(ent) * (size_t)a);
+      free(tmp);
+    }
+    lo = cand;
+    qsort(lo, (size_t)keepL, sizeof(ent), ent_cmp_col);
+    qsort(lo + keepL, (size_t)keepU, sizeof(ent), ent_cmp_col);
+    if (nzL + keepL > capL) {
+      while (nzL + keepL > capL) capL *= 2;
+      L->ci = realloc(L->ci, sizeof(int) * capL);
+      L->v = realloc(L->v, sizeof(double) * capL);
+    }
+    if (nzU + keepU + 1 > capU) {
+      while (nzU + keepU + 1 > capU) capU *= 2;
+      U->ci = realloc(U->ci, sizeof(int) * capU);
+      U->v = realloc(U->v, sizeof(double) * capU);
+    }
+    for (int64_t t = 0; t < keepL; ++t) { L->ci[nzL] = lo[t].j; L->v[nzL] = lo[t].v; nzL++; }
+    U->ci[nzU] = i; U->v[nzU] = d; nzU++;
+    for (int64_t t = 0; t < keepU; ++t) { U->ci[nzU] = lo[keepL + t].j; U->v[nzU] = lo[keepL + t].v; nzU++; }
+    L->rp[i + 1] = nzL;
+    U->rp[i + 1] = nzU;
+    for (int t = 0; t < nt; ++t) { used[touched[t]] = 0; w[touched[t]] = 0.0; }
+  }
+  L->nnz = nzL;
+  U->nnz = nzU;
+  free(w); free(used); free(touched); free(cand);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solver state                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double tau, fill;
+  int limit_mode, coarse_cycles, gs_variant, coarse_min, nu1, nu2;
+} orc_opts;
+
+typedef struct {
+  int dim, p, nel, geom, rhs;
+  int freq[3];
+  orc_opts o;
+  int n, n1;
+  ocsr A, L, U;
+  ocsr R;   /* P_p^1 : n1 x n (restriction matrix) */
+  ocsr Pr;  /* P_1^p : n x n1 (prolongation matrix) */
+  double *f, *mlp, *ml1;
+  int nlev;
+  int lnel[MAXLEV], ln[MAXLEV];
+  ocsr A1[MAXLEV];
+  ocsr Ph[MAXLEV];  /* Ph[l]: level l (fine) x level l+1 (coarse) */
+  ocsr Rh[MAXLEV];  /* transpose */
+  double *chol;     /* dense lower Cholesky factor of the coarsest level */
+  /* work */
+  double *r, *y, *r1, *e1;
+  double *hv_b[MAXLEV], *hv_e[MAXLEV], *hv_r[MAXLEV];
+  int status;
+  int bad_row;
+} orc;
+
+void orc_default_opts(orc_opts *o) {
+  o->tau = 1e-12;   /* Section 3: drop tolerance 1e-12 */
+  o->fill = 1.0;    /* Section 3: fill factor m = 1 */
+  o->limit_mode = 0;
+  o->coarse_cycles = 2; /* Section 3: two h-multigrid V-cycles at p = 1 */
+  o->gs_variant = 0;    /* multicolour Gauss-Seidel */
+  o->coarse_min = 8;
+  o->nu1 = 1;
+  o->nu2 = 1;
+}
+
+static int dense_cholesky(const ocsr *A, double **out) {
+  int n = A->nrows;
+  double *C = calloc((size_t)n * n, sizeof(double));
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) C[(size_t)i * n + A->ci[k]] = A->v[k];
+  for (int j = 0; j < n; ++j) {
+    double s = C[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
+    if (!(s > 0.0)) { free(C); return ORC_EZEROPIVOT; }
+    double d = sqrt(s);
+    C[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = C[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
+      C[(size_t)i * n + j] = t / d;
+    }
+    for (int i = 0; i < j; ++i) C[(size_t)i * n + j] = 0.0;
+  }
+  *out = C;
+  return ORC_OK;
+}
+
+static void dense_chol_solve(const double *C, int n, const double *b, double *x) {
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= C[(size_t)i * n + k] * x[k];
+    x[i] = s / C[(size_t)i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int k = i + 1; k < n; ++k) s -= C[(size_t)k * n + i] * x[k];
+    x[i] = s / C[(size_t)i * n + i];
+  }
+}
+
+void orc_free(orc *s) {
+  if (!s) return;
+  csr_free(&s->A); csr_free(&s->L); csr_free(&s->U); csr_free(&s->R); csr_free(&s->Pr);
+  for (int l = 0; l < MAXLEV; ++l) {
+    csr_free(&s->A1[l]); csr_free(&s->Ph[l]); csr_free(&s->Rh[l]);
+    free(s->hv_b[l]); free(s->hv_e[l]); free(s->hv_r[l]);
+  }
+  free(s->f); free(s->mlp); free(s->ml1); free(s->chol);
+  free(s->r); free(s->y); free(s->r1); free(s->e1);
+  free(s);
+}
+
+/* Builds every operator of the method for one problem:
+ *   A_p, f_p        Galerkin system at degree p, (p+1)^d Gauss points;
+ *   M_p^L, M_1^L    lumped masses; P_1^p and P_p^1 = (P_1^p)^T;
+ *   A_{2^k h, 1}    rediscretised degree-1 operators (Section 3, "Coarse
+ *                   grid operator"), 2^d Gauss points, mesh halved until
+ *                   n_el <= coarse_min (or odd), direct solve there;
+ *   L, U            ILUT(tau, m) of A_p in the natural order.
+ * stage_mask bit 0 skips ILUT (assembly-only use in tests). */
+orc *orc_create(int dim, int p, int nel, int geom, int rhs, const int *freq, const orc_opts *o,
+                int stage_mask, int *status) {
+  *status = ORC_OK;
+  if ((dim != 2 && dim != 3) || p < 1 || nel < 2 || (geom == 1 && dim != 2) || nel + p - 2 < 1) {
+    *status = ORC_EINVAL;
+    return NULL;
+  }
+  orc *s = calloc(1, sizeof(orc));
+  s->dim = dim; s->p = p; s->nel = nel; s->geom = geom; s->rhs = rhs;
+  for (int a = 0; a < 3; ++a) s->freq[a] = freq ? freq[a] : 1;
+  if (o) s->o = *o; else orc_default_opts(&s->o);
+  omesh M = {dim, geom, nel};
+  s->n = ipow(nel + p - 2, dim);
+  s->n1 = ipow(nel - 1, dim);
+  int rc = assemble(&M, 0, p, p, p + 1, 1, &s->A);
+  s->f = malloc(sizeof(double) * s->n);
+  if (!rc) rc = assemble_load(&M, p, p + 1, rhs, s->freq, s->f);
+  s->mlp = malloc(sizeof(double) * s->n);
+  s->ml1 = malloc(sizeof(double) * (s->n1 > 0 ? s->n1 : 1));
+  if (!rc) rc = lumped_mass(&M, p, p + 1, s->mlp);
+  if (!rc && s->n1 > 0) rc = lumped_mass(&M, 1, 2, s->ml1);
+  if (!rc && s->n1 > 0) rc = assemble(&M, 1, p, 1, p + 1, 1, &s->Pr);
+  if (!rc && s->n1 > 0) rc = csr_transpose(&s->Pr, &s->R);
+  /* P1 hierarchy */
+  int l = 0, ne = nel;
+  while (!rc) {
+    omesh Ml = {dim, geom, ne};
+    s->lnel[l] = ne;
+    s->ln[l] = ipow(ne - 1, dim);
+    rc = assemble(&Ml, 0, 1, 1, 2, 1, &s->A1[l]);
+    if (rc) break;
+    if (ne <= s->o.coarse_min || (ne % 2) != 0 || l + 1 >= MAXLEV) break;
+    rc = canonical_prolongation(dim, ne / 2, &s->Ph[l]);
+    if (!rc) rc = csr_transpose(&s->Ph[l], &s->Rh[l]);
+    ne /= 2;
+    l++;
+  }
+  s->nlev = l + 1;
+  if (!rc && s->n1 > 0) rc = dense_cholesky(&s->A1[s->nlev - 1], &s->chol);
+  if (!rc && !(stage_mask & 1)) {
+    s->bad_row = -1;
+    rc = orc_ilut_raw(s->n, s->A.rp, s->A.ci, s->A.v, s->o.tau, s->o.fill, s->o.limit_mode, &s->L,
+                      &s->U, &s->bad_row);
+  }
+  s->r = calloc(s->n, sizeof(double));
+  s->y = calloc(s->n, sizeof(double));
+  s->r1 = calloc(s->n1 > 0 ? s->n1 : 1, sizeof(double));
+  s->e1 = calloc(s->n1 > 0 ? s->n1 : 1, sizeof(double));
+  for (int k = 0; k < s->nlev; ++k) {
+    s->hv_b[k] = calloc(s->ln[k] > 0 ? s->ln[k] : 1, sizeof(double));
+    s->hv_e[k] = calloc(s->ln[k] > 0 ? s->ln[k] : 1, sizeof(double));
+    s->hv_r[k] = calloc(s->ln[k] > 0 ? s->ln[k] : 1, sizeof(double));
+  }
+  if (rc) {
+    *status = rc;
+    s->status = rc;
+  }
+  return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solve phase.                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* r = b - A x (the defect of Section 3, step 2) */
+static void residual(const ocsr *A, const double *b, const double *x, double *r) {
+  for (int i = 0; i < A->nrows; ++i) {
+    double s = 0.0;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s += A->v[k] * x[A->ci[k]];
+    r[i] = b[i] - s;
+  }
+}
+
+static double norm2(const double *v, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += v[i] * v[i];
+  return sqrt(s);
+}
+
+/* One ILUT smoothing step (Section 3, "Smoother"): given r = f - A u,
+ * e = U^{-1} L^{-1} r by forward then backward substitution, u <- u + e. */
+static void ilut_smooth(const orc *s, const double *r, double *x, double *y) {
+  int n = s->n;
+  for (int i = 0; i < n; ++i) {
+    double t = r[i];
+    for (int64_t k = s->L.rp[i]; k < s->L.rp[i + 1]; ++k) t -= s->L.v[k] * y[s->L.ci[k]];
+    y[i] = t;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = y[i];
+    int64_t k0 = s->U.rp[i];
+    for (int64_t k = k0 + 1; k < s->U.rp[i + 1]; ++k) t -= s->U.v[k] * y[s->U.ci[k]];
+    y[i] = t / s->U.v[k0];
+  }
+  for (int i = 0; i < n; ++i) x[i] += y[i];
+}
+
+/* Gauss-Seidel sweep on A_l e = b (Section 3: the smoother of the h-multigrid
+ * coarse solve).  Variant 0 (reading taken): multicolour, colour of an
+ * interior degree-1 node = parity of each of its indices, colours swept in
+ * increasing order; nodes of one colour are not coupled by the 3^d-point
+ * stencil, so their order does not matter.  Variant 1: lexicographic. */
+static void gs_sweep(const orc *s, int l, const double *b, double *e) {
+  const ocsr *A = &s->A1[l];
+  int n1d = s->lnel[l] - 1, dim = s->dim;
+  int ncol = s->o.gs_variant == 0 ? ipow(2, dim) : 1;
+  int m[3];
+  for (int c = 0; c < ncol; ++c) {
+    for (int i = 0; i < A->nrows; ++i) {
+      if (s->o.gs_variant == 0) {
+        unflat(i, n1d, dim, m);
+        int col = 0;
+        for (int a = 0; a < dim; ++a) col += (m[a] & 1) << a;
+        if (col != c) continue;
+      }
+      double t = b[i], d = 0.0;
+      for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+        int j = A->ci[k];
+        if (j == i) d = A->v[k];
+        else t -= A->v[k] * e[j];
+      }
+      e[i] = t / d;
+    }
+  }
+}
+
+/* One h-multigrid V-cycle on A_l e = b (Figure 1, lower part; Section 3):
+ * pre-smoothing, residual, restriction R = P^T, recursion with zero initial
+ * guess, prolongation and correction, post-smoothing; direct solve on the
+ * coarsest level. */
+static void hcycle(orc *s, int l, const double *b, double *e) {
+  if (l == s->nlev - 1) {
+    dense_chol_solve(s->chol, s->ln[l], b, e);
+    return;
+  }
+  double *r = s->hv_r[l];
+  for (int k = 0; k < s->o.nu1; ++k) gs_sweep(s, l, b, e);
+  residual(&s->A1[l], b, e, r);
+  double *bc = s->hv_b[l + 1], *ec = s->hv_e[l + 1];
+  csr_mv(&s->Rh[l], r, bc);
+  memset(ec, 0, sizeof(double) * s->ln[l + 1]);
+  hcycle(s, l + 1, bc, ec);
+  for (int i = 0; i < s->ln[l]; ++i) {
+    double t = 0.0;
+    for (int64_t k = s->Ph[l].rp[i]; k < s->Ph[l].rp[i + 1]; ++k) t += s->Ph[l].v[k] * ec[s->Ph[l].ci[k]];
+    e[i] += t;
+  }
+  for (int k = 0; k < s->o.nu2; ++k) gs_sweep(s, l, b, e);
+}
+
+/* Coarse correction at p = 1: e1 = 0, then coarse_cycles h-multigrid
+ * V-cycles on A_{h,1} e1 = r1. */
+void orc_coarse(orc *s, const double *r1, double *e1) {
+  memset(e1, 0, sizeof(double) * s->n1);
+  for (int c = 0; c < s->o.coarse_cycles; ++c) hcycle(s, 0, r1, e1);
+}
+
+/* One p-multigrid V-cycle with direct projection to p = 1 (Section 3,
+ * two-grid correction steps 1-5 and Figure 1, upper part):
+ *   nu1 ILUT pre-smoothing steps, r = f - A u,
+ *   r1 = (M_1^L)^{-1} P_p^1 r                 (lumped L2 restriction),
+ *   e1 ~ A_{h,1}^{-1} r1                       (coarse_cycles h-MG V-cycles),
+ *   u += (M_p^L)^{-1} P_1^p e1                 (lumped L2 prolongation),
+ *   nu2 ILUT post-smoothing steps.
+ * On entry r must hold f - A u; on exit it holds f - A u for the new u. */
+void orc_vcycle(orc *s, const double *b, double *x, double *r) {
+  int n = s->n, n1 = s->n1;
+  for (int k = 0; k < s->o.nu1; ++k) {
+    ilut_smooth(s, r, x, s->y);
+    residual(&s->A, b, x, r);
+  }
+  if (n1 > 0) {
+    csr_mv(&s->R, r, s->r1);
+    for (int i = 0; i < n1; ++i) s->r1[i] = s->r1[i] / s->ml1[i];
+    orc_coarse(s, s->r1, s->e1);
+    for (int i = 0; i < n; ++i) {
+      double t = 0.0;
+      for (int64_t k = s->Pr.rp[i]; k < s->Pr.rp[i + 1]; ++k) t += s->Pr.v[k] * s->e1[s->Pr.ci[k]];
+      x[i] += t / s->mlp[i];
+    }
+    residual(&s->A, b, x, r);
+  }
+  for (int k = 0; k < s->o.nu2; ++k) {
+    ilut_smooth(s, r, x, s->y);
+    residual(&s->A, b, x, r);
+  }
+}
+
+/* Stand-alone solver (Section 5, experimental set-up): V-cycles until the
+ * 2-norm of the residual has dropped by tol relative to the initial one;
+ * diverged once it exceeds 1e10 times the initial one.  hist[k] receives
+ * ||r_k|| / ||r_0|| for k = 0..iters (length maxit + 1). */
+int orc_solve(orc *s, const double *b, double *x, double tol, int maxit, double *hist, int *iters) {
+  double *r = s->r;
+  residual(&s->A, b, x, r);
+  double r0 = norm2(r, s->n);
+  *iters = 0;
+  if (hist) hist[0] = 1.0;
+  if (!isfinite(r0)) return ORC_ENAN;
+  if (r0 == 0.0) return ORC_OK;
+  for (int it = 1; it <= maxit; ++it) {
+    orc_vcycle(s, b, x, r);
+    double rel = norm2(r, s->n) / r0;
+    *iters = it;
+    if (hist) hist[it] = rel;
+    if (!isfinite(rel) || rel > 1e10) return ORC_EDIVERGED;
+    if (rel <= tol) return ORC_OK;
+  }
+  return ORC_EMAXIT;
+}
+
+/* Conjugate gradients on A u = f (an independent FP64 reference solution);
+ * jacobi != 0 uses diag(A) as preconditioner.  Stops at ||r|| <= tol ||f||. */
+int orc_cg(orc *s, const double *b, double *x, double tol, int maxit, int jacobi, int *iters) {
+  int n = s->n;
+  double *r = calloc(n, sizeof(double)), *z = calloc(n, sizeof(double)),
+         *pv = calloc(n, sizeof(double)), *q = calloc(n, sizeof(double)),
+         *dg = calloc(n, sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    int64_t k = csr_find(&s->A, i, i);
+    dg[i] = s->A.v[k];
+  }
+  residual(&s->A, b, x, r);
+  double bn = norm2(b, n);
+  if (bn == 0.0) bn = 1.0;
+  for (int i = 0; i < n; ++i) z[i] = jacobi ? r[i] / dg[i] : r[i];
+  memcpy(pv, z, sizeof(double) * n);
+  double rz = 0.0;
+  for (int i = 0; i < n; ++i) rz += r[i] * z[i];
+  int it = 0, rc = ORC_EMAXIT;
+  if (norm2(r, n) <= tol * bn) rc = ORC_OK;
+  while (rc != ORC_OK && it < maxit) {
+    csr_mv(&s->A, pv, q);
+    double pq = 0.0;
+    for (int i = 0; i < n; ++i) pq += pv[i] * q[i];
+    double al = rz / pq;
+    for (int i = 0; i < n; ++i) { x[i] += al * pv[i]; r[i] -= al * q[i]; }
+    it++;
+    if (norm2(r, n) <= tol * bn) { rc = ORC_OK; break; }
+    for (int i = 0; i < n; ++i) z[i] = jacobi ? r[i] / dg[i] : r[i];
+    double rz2 = 0.0;
+    for (int i = 0; i < n; ++i) rz2 += r[i] * z[i];
+    double be = rz2 / rz;
+    rz = rz2;
+    for (int i = 0; i < n; ++i) pv[i] = z[i] + be * pv[i];
+  }
+  *iters = it;
+  free(r); free(z); free(pv); free(q); free(dg);
+  return rc;
+}
+
+/* L2 error sqrt(int (u - u_h)^2) with (p+3)^d Gauss points per element (the
+ * paper does not say how its L2 errors are computed; this is the reading). */
+double orc_l2_error(orc *s, const double *uh) {
+  int dim = s->dim, p = s->p, nel = s->nel, nb = nel + p, nq = p + 3;
+  tab1d T;
+  tab1d_make(&T, p, nel, nq);
+  int nl = ipow(p + 1, dim), nqt = ipow(nq, dim), net = ipow(nel, dim);
+  int em[3], am[3], fm[3], qm[3];
+  double err = 0.0;
+  for (int e = 0; e < net; ++e) {
+    unflat(e, nel, dim, em);
+    for (int q = 0; q < nqt; ++q) {
+      unflat(q, nq, dim, qm);
+      double xi[3] = {0, 0, 0}, wq = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        xi[a] = T.xi[em[a] * nq + qm[a]];
+        wq *= T.wt[em[a] * nq + qm[a]];
+      }
+      double X[3], J[3][3], det;
+      geom_eval(s->geom, dim, xi, X, J, &det);
+      double u = 0.0;
+      for (int l = 0; l < nl; ++l) {
+        unflat(l, p + 1, dim, am);
+        for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
+        int i = gidx(dim, fm, nb, 1);
+        if (i < 0) continue;
+        double val = 1.0;
+        for (int b = 0; b < dim; ++b) val *= T.val[((size_t)em[b] * nq + qm[b]) * (p + 1) + am[b]];
+        u += uh[i] * val;
+      }
+      double d = orc_exact_u(s->rhs, dim, s->freq, X) - u;
+      err += wq * det * d * d;
+    }
+  }
+  tab1d_free(&T);
+  return sqrt(err);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Export interface for the tests.                                           */
+/* ------------------------------------------------------------------------ */
+enum { OM_A = 0, OM_L, OM_U, OM_R, OM_P, OM_A1, OM_PH, OM_RH };
+enum { OV_F = 0, OV_MLP, OV_ML1, OV_CHOL };
+
+int orc_info(const orc *s, int64_t *out) {
+  out[0] = s->n; out[1] = s->n1; out[2] = s->nlev; out[3] = s->A.nnz;
+  out[4] = s->L.nnz; out[5] = s->U.nnz; out[6] = s->R.nnz; out[7] = s->status;
+  out[8] = s->bad_row;
+  for (int l = 0; l < s->nlev && l < 8; ++l) { out[9 + l] = s->ln[l]; out[17 + l] = s->lnel[l]; }
+  return ORC_OK;
+}
+
+static const ocsr *pick(const orc *s, int which, int lev) {
+  switch (which) {
+    case OM_A: return &s->A;
+    case OM_L: return &s->L;
+    case OM_U: return &s->U;
+    case OM_R: return &s->R;
+    case OM_P: return &s->Pr;
+    case OM_A1: return (lev >= 0 && lev < s->nlev) ? &s->A1[lev] : NULL;
+    case OM_PH: return (lev >= 0 && lev + 1 < s->nlev) ? &s->Ph[lev] : NULL;
+    case OM_RH: return (lev >= 0 && lev + 1 < s->nlev) ? &s->Rh[lev] : NULL;
+  }
+  return NULL;
+}
+
+/* dims[0..2] = nrows, ncols, nnz; copies arrays when the pointers are set */
+int orc_get_csr(const orc *s, int which, int lev, int64_t *dims, int64_t *rp, int *ci, double *v) {
+  const ocsr *m = pick(s, which, lev);
+  if (!m) return ORC_EINVAL;
+  dims[0] = m->nrows; dims[1] = m->ncols; dims[2] = m->nnz;
+  if (rp) memcpy(rp, m->rp, sizeof(int64_t) * ((size_t)m->nrows + 1));
+  if (ci) memcpy(ci, m->ci, sizeof(int) * (size_t)m->nnz);
+  if (v) memcpy(v, m->v, sizeof(double) * (size_t)m->nnz);
+  return ORC_OK;
+}
+
+int orc_get_vec(const orc *s, int which, double *out) {
+  switch (which) {
+    case OV_F: memcpy(out, s->f, sizeof(double) * s->n); return ORC_OK;
+    case OV_MLP: memcpy(out, s->mlp, sizeof(double) * s->n); return ORC_OK;
+    case OV_ML1: memcpy(out, s->ml1, sizeof(double) * s->n1); return ORC_OK;
+    case OV_CHOL: {
+      int nc = s->ln[s->nlev - 1];
+      memcpy(out, s->chol, sizeof(double) * (size_t)nc * nc);
+      return ORC_OK;
+    }
+  }
+  return ORC_EINVAL;
+}
+
+/* Building blocks exposed for the pins. */
+void orc_residual(const orc *s, const double *b, const double *x, double *r) { residual(&s->A, b, x, r); }
+void orc_smooth(orc *s, const double *r, double *x) { ilut_smooth(s, r, x, s->y); }
+void orc_hcycle(orc *s, const double *b, double *e) { hcycle(s, 0, b, e); }
+void orc_gs(orc *s, int lev, const double *b, double *e) { gs_sweep(s, lev, b, e); }
+
+/* Assembly of one operator on its own, for the pins: kind 0 stiffness,
+ * 1 mass/transfer; elim 0 keeps the boundary functions. */
+orc *orc_assemble_only(int dim, int geom, int nel, int kind, int pr, int pc, int nq, int elim,
+                       int *status) {
+  orc *s = calloc(1, sizeof(orc));
+  omesh M = {dim, geom, nel};
+  s->dim = dim; s->geom = geom; s->nel = nel;
+  *status = assemble(&M, kind, pr, pc, nq, elim, &s->A);
+  s->nlev = 0;
+  return s;
+}
+
+/* ILUT of an arbitrary CSR matrix, for the pins; results land in s->L, s->U. */
+orc *orc_ilut_csr(int n, const int64_t *rp, const int *ci, const double *v, double tau, double fill,
+                  int mode, int *status) {
+  orc *s = calloc(1, sizeof(orc));
+  s->n = n;
+  s->bad_row = -1;
+  *status = orc_ilut_raw(n, rp, ci, v, tau, fill, mode, &s->L, &s->U, &s->bad_row);
+  return s;
+}

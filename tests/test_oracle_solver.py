@@ -1,0 +1,204 @@
+"""Pins of the oracle's solve phase (Section 3, two-grid correction and V-cycle;
+Section 4, iteration matrix; Section 5, stand-alone solver) against
+mathematics: exact-LU smoothing, affine linearity and the fixed point of the
+V-cycle, the dense two-grid error propagator, Gauss-Seidel as a triangular
+solve (scipy), CG against a direct solve (scipy), h-independence of the
+h-multigrid coarse solver and of the p-multigrid iteration counts."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_vcycles.json")
+
+
+def test_exact_lu_smoother_converges_in_one_cycle():
+    o = O.Oracle(2, 3, 16, opts=O.Options(tau=0.0, fill=0.0))
+    x, st, it, hist = o.solve(o.f(), tol=1e-8)
+    assert st == 0 and it == 1 and hist[1] < 1e-12
+
+
+@pytest.mark.parametrize("geom,dim,p,nel", [(0, 2, 2, 16), (1, 2, 3, 16), (0, 3, 2, 8)])
+def test_vcycle_affine_linearity_and_fixed_point(geom, dim, p, nel):
+    o = O.Oracle(dim, p, nel, geom=geom, rhs=geom)
+    rng = np.random.default_rng(5)
+    n = o.n
+    f1, f2 = rng.standard_normal(n), rng.standard_normal(n)
+    u1, u2 = rng.standard_normal(n), rng.standard_normal(n)
+    a, b = 0.7, -1.3
+    x1, _ = o.vcycle(f1, u1)
+    x2, _ = o.vcycle(f2, u2)
+    x3, _ = o.vcycle(a * f1 + b * f2, a * u1 + b * u2)
+    assert np.abs(x3 - (a * x1 + b * x2)).max() < 1e-12 * np.abs(x3).max()
+    # fixed point V(f, A^-1 f) = A^-1 f
+    A = o.A().tocsc()
+    f = o.f()
+    u = spla.spsolve(A, f)
+    xv, rv = o.vcycle(f, u)
+    assert np.abs(xv - u).max() < 1e-10 * np.abs(u).max()
+    assert np.abs(rv - (f - A @ xv)).max() < 1e-13 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("geom,p", [(0, 2), (1, 3)])
+def test_two_grid_error_propagator(geom, p):
+    """n_el = 8: the degree-1 problem is solved directly, so the V-cycle is the
+    exact two-grid method.  Its error propagator, built column by column from
+    unit initial guesses with f = 0 (Section 4), must equal
+    S (I - diag(M_p^L)^-1 P_1^p A_1^-1 diag(M_1^L)^-1 P_p^1 A) S,
+    S = I - (L U)^-1 A, from the oracle's own operators."""
+    o = O.Oracle(2, p, 8, geom=geom, rhs=geom)
+    assert o.nlev == 1
+    n = o.n
+    A = o.A().toarray()
+    L = o.L().toarray() + np.eye(n)
+    U = o.U().toarray()
+    P = o.P().toarray()
+    A1 = o.A1(0).toarray()
+    S = np.eye(n) - np.linalg.solve(U, np.linalg.solve(L, A))
+    C = np.eye(n) - (P / o.mlp()[:, None]) @ np.linalg.solve(A1, (P.T / o.ml1()[:, None]) @ A)
+    E_ref = S @ C @ S
+    E = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n); e[j] = 1.0
+        E[:, j], _ = o.vcycle(np.zeros(n), e)
+    assert np.abs(E - E_ref).max() < 1e-10
+
+
+def _spectral_radius(o):
+    n = o.n
+    E = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n); e[j] = 1.0
+        E[:, j], _ = o.vcycle(np.zeros(n), e)
+    return np.abs(np.linalg.eigvals(E)).max()
+
+
+def test_spectral_radius_small_like_table_2a():
+    """Table 2a: p-multigrid with ILUT on benchmark 1 has spectral radii
+    between 0.003 and 0.058 for h = 2^-4..2^-6, p = 2..4.  The paper's ILUT
+    uses an unstated permutation, so only the order of magnitude is pinned."""
+    gold = json.load(open(GOLD))["spectral_radius_annulus"]
+    for p in (2, 3, 4):
+        o = O.Oracle(2, p, 16, geom=1, rhs=1)
+        rho = _spectral_radius(o)
+        assert rho < 0.1, (p, rho)
+        assert rho < 10 * max(r[gold["p"].index(p)] for r in gold["rho"])
+
+
+def test_gs_lexicographic_is_triangular_solve():
+    o = O.Oracle(2, 2, 16, opts=O.Options(gs_variant=1))
+    A = o.A1(0)
+    rng = np.random.default_rng(7)
+    b, e = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    DL = sp.tril(A, 0, format="csr")
+    Us = sp.triu(A, 1, format="csr")
+    ref = spla.spsolve_triangular(DL, b - Us @ e, lower=True)
+    assert np.abs(o.gs(0, b, e) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gs_multicolour_is_permuted_triangular_solve(dim):
+    nel = 16 if dim == 2 else 8
+    o = O.Oracle(dim, 2, nel)
+    A = o.A1(0).tocsr()
+    n1 = nel - 1
+    idx = np.arange(A.shape[0])
+    m = [(idx // n1 ** a) % n1 for a in range(dim)]
+    colour = sum((m[a] % 2) << a for a in range(dim))
+    perm = np.argsort(colour, kind="stable")
+    Ap = A[perm][:, perm]
+    # same-colour nodes are uncoupled
+    for c in range(2 ** dim):
+        sel = np.where(colour[perm] == c)[0]
+        blk = Ap[sel][:, sel].toarray()
+        assert np.count_nonzero(blk - np.diag(np.diag(blk))) == 0
+    rng = np.random.default_rng(8)
+    b, e = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    DL = sp.tril(Ap, 0, format="csr")
+    Us = sp.triu(Ap, 1, format="csr")
+    ref_p = spla.spsolve_triangular(DL, b[perm] - Us @ e[perm], lower=True)
+    ref = np.empty_like(ref_p); ref[perm] = ref_p
+    assert np.abs(o.gs(0, b, e) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_hmg_convergence_factor_is_h_independent():
+    rhos = []
+    for nel in (16, 32, 64, 128, 256):
+        o = O.Oracle(2, 2, nel, ilut=False)
+        A1 = o.A1(0)
+        rng = np.random.default_rng(9)
+        b = rng.standard_normal(A1.shape[0])
+        e = np.zeros_like(b)
+        res = [np.linalg.norm(b)]
+        for _ in range(6):
+            e = o.hcycle(b, e)
+            res.append(np.linalg.norm(b - A1 @ e))
+        rhos.append((res[-1] / res[-3]) ** 0.5)
+    assert max(rhos) < 0.5 and max(rhos) - min(rhos) < 0.05, rhos
+
+
+def test_cg_matches_direct_solve():
+    for (dim, p, nel, g) in [(2, 3, 32, 0), (2, 4, 16, 1), (3, 2, 8, 0)]:
+        o = O.Oracle(dim, p, nel, geom=g, rhs=g, ilut=False)
+        A = o.A().tocsc()
+        f = o.f()
+        u = spla.spsolve(A, f)
+        x, st, it = o.cg(f, tol=1e-14, maxit=100000)
+        assert st == 0
+        assert np.linalg.norm(x - u) <= 1e-11 * np.linalg.norm(u)
+
+
+def test_solver_converges_to_direct_solution():
+    o = O.Oracle(2, 4, 32, geom=1, rhs=1)
+    f = o.f()
+    x, st, it, hist = o.solve(f, tol=1e-12)
+    u = spla.spsolve(o.A().tocsc(), f)
+    assert st == 0 and hist[-1] <= 1e-12
+    assert np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+
+
+def test_iteration_counts_h_and_p_independent_annulus():
+    """Section 5: with ILUT the counts are essentially independent of h and p
+    (Table 4, quarter annulus: 3-5).  Random initial guess in [-1, 1]."""
+    gold = json.load(open(GOLD))["annulus"]
+    counts = {}
+    for p in (2, 3, 4, 5):
+        for nel in (16, 32, 64):
+            o = O.Oracle(2, p, nel, geom=1, rhs=1)
+            x0 = np.random.default_rng(0).uniform(-1, 1, o.n)
+            _, st, it, _ = o.solve(o.f(), x0=x0, tol=1e-8)
+            assert st == 0
+            counts[(p, nel)] = it
+    for p in (2, 3, 4, 5):
+        c = [counts[(p, n)] for n in (16, 32, 64)]
+        assert max(c) - min(c) <= 2, (p, c)
+        assert all(1 <= v <= 10 for v in c)
+        paper = gold["ilut"][0][gold["p"].index(p)]          # h = 2^-6 row
+        assert abs(counts[(p, 64)] - paper) <= 2, (p, counts[(p, 64)], paper)
+
+
+def test_iteration_counts_cube():
+    gold = json.load(open(GOLD))["cube"]
+    for p, nel in ((2, 8), (2, 16), (3, 8)):
+            o = O.Oracle(3, p, nel)
+            x0 = np.random.default_rng(0).uniform(-1, 1, o.n)
+            _, st, it, _ = o.solve(o.f(), x0=x0, tol=1e-8)
+            paper = gold["ilut"][gold["h"].index(nel)][gold["p"].index(p)]
+            assert st == 0 and abs(it - paper) <= 2, (p, nel, it, paper)
+
+
+def test_status_codes():
+    o = O.Oracle(2, 2, 16)
+    f = o.f()
+    _, st, it, _ = o.solve(f, tol=1e-30, maxit=2)
+    assert st == O.EMAXIT and it == 2
+    bad = f.copy(); bad[3] = np.nan
+    _, st, it, _ = o.solve(bad, tol=1e-8)
+    assert st == O.ENAN
+    x, st, it, _ = o.solve(np.zeros(o.n), tol=1e-8)
+    assert st == 0 and it == 0 and not x.any()
