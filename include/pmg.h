@@ -1,0 +1,197 @@
+/*
+ * pmg.h -- C ABI of the MI355X p-multigrid library.
+ *
+ * Solves the B-spline Galerkin (isogeometric) discretisation of Poisson's
+ * equation -Lap u = f with homogeneous Dirichlet conditions by the
+ * p-multigrid method with an ILUT smoother of Tielen, Moeller, Goeddeke and
+ * Vuik (arXiv:1901.01685):
+ *   - problem statement: Section 2 (model problem, B-spline basis, geometry
+ *     map F, Galerkin system A_{h,p} u = f_{h,p}); benchmarks 1 (quarter
+ *     annulus) and 4 (unit cube), and the unit square;
+ *   - solve phase: Section 3 (two-grid correction steps 1-5, V-cycle with
+ *     direct projection to p = 1, lumped L2 transfers, ILUT smoothing,
+ *     h-multigrid coarse solve) and Section 5 (stand-alone solver protocol).
+ *
+ * Conventions (every entry point):
+ *   - Vectors b, x, r, r1, e1 are DEVICE pointers (hipMalloc'd or torch CUDA
+ *     tensors) to FP64 arrays owned by the caller.  Degree-p vectors have
+ *     length info.n, degree-1 vectors length info.n1.  Unknowns are the
+ *     interior tensor B-splines (boundary functions eliminated), numbered
+ *     0-based with x fastest: i = ix + n*iy (+ n*n*iz), n = n_elem + p - 2.
+ *   - stream is a hipStream_t (NULL = the null stream).  Calls are ordered
+ *     on that stream; pmg_solve and any call returning a norm synchronise it.
+ *   - A handle owns all device operators and work buffers; it is used by one
+ *     host thread at a time, and calls on one handle must not overlap.
+ *   - Errors are return codes; nothing is thrown across the ABI.  A
+ *     thread-local message is available from pmg_last_error().  On a failed
+ *     pmg_setup *out is set to NULL.
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmg_handle_s *pmg_handle;
+
+typedef enum {
+  PMG_OK = 0,
+  PMG_EINVAL = 1,     /* invalid argument or unsupported configuration */
+  PMG_ENOMEM = 2,     /* host or device allocation failed */
+  PMG_EDEVICE = 3,    /* HIP runtime error, or no device for a device call */
+  PMG_EZEROPIVOT = 4, /* ILUT met a zero or non-finite pivot */
+  PMG_EDIVERGED = 5,  /* relative residual above the divergence ratio */
+  PMG_EMAXIT = 6,     /* max_iter V-cycles without reaching tol */
+  PMG_ENAN = 7,       /* non-finite initial residual (NaN/Inf in b or x) */
+  PMG_EBUDGET = 8     /* device-memory budget exceeded (serving) */
+} pmg_status;
+
+enum { PMG_GEOM_BOX = 0, PMG_GEOM_QUARTER_ANNULUS = 1 };
+enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1 };
+enum { PMG_FP64 = 0, PMG_FP32_IN_FP64 = 1 };
+enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1 };
+enum { PMG_GS_MULTICOLOR = 0 };
+
+/* The problem (Section 2): -Lap u = f on Omega = F((0,1)^dim), u = 0 on the
+ * boundary, discretised with tensor B-splines of degree `degree` on the open
+ * uniform knot vector with n_elem elements per direction (h = 1/n_elem).
+ *   geometry PMG_GEOM_BOX: unit square / cube (F = identity);
+ *   geometry PMG_GEOM_QUARTER_ANNULUS (dim 2): radii 1 and 2, F(xi, eta) =
+ *     (1 + xi) C(eta), C the rational quadratic quarter circle (benchmark 1).
+ *   rhs_kind PMG_RHS_SINE: f = pi^2 (sum_a k_a^2) prod_a sin(k_a pi x_a),
+ *     k = freq[0..dim-1] (manufactured u = prod sin(k_a pi x_a));
+ *   rhs_kind PMG_RHS_ANNULUS: f = -Lap u for benchmark 1's
+ *     u = -(x^2+y^2-1)(x^2+y^2-4) x y^2. */
+typedef struct {
+  int32_t dim;      /* 2 or 3 */
+  int32_t degree;   /* p >= 1 (polynomial degree, C^{p-1} splines) */
+  int32_t n_elem;   /* elements per direction, >= 2 */
+  int32_t geometry; /* PMG_GEOM_* */
+  int32_t rhs_kind; /* PMG_RHS_* */
+  int32_t freq[3];  /* sine frequencies (>= 1) */
+} pmg_problem;
+
+/* Solver options.  Defaults (pmg_default_options) are the paper's constants
+ * (Section 3: tau = 1e-12, m = 1, two h-multigrid V-cycles as the p = 1
+ * solve; Section 5: nu1 = nu2 = 1, divergence above 1e10). */
+typedef struct {
+  double ilut_tau;          /* ILUT drop tolerance tau (rule 1) */
+  double ilut_fill;         /* ILUT fill factor m (rule 2); <= 0: unlimited */
+  int32_t ilut_limit_mode;  /* PMG_LIMIT_PER_PART (M per L and per U) or PER_ROW */
+  int32_t nu1, nu2;         /* pre/post ILUT smoothing steps */
+  int32_t coarse_cycles;    /* h-multigrid V-cycles at p = 1 */
+  int32_t coarse_min_elems; /* direct solve once n_elem <= this (or odd) */
+  int32_t gs_variant;       /* PMG_GS_MULTICOLOR */
+  int32_t precision;        /* PMG_FP64 or PMG_FP32_IN_FP64 (defect correction) */
+  int32_t max_iter;         /* V-cycles (outer steps in mixed precision) */
+  double diverge_ratio;     /* PMG_EDIVERGED above this relative residual */
+  int32_t device;           /* HIP device ordinal; -1 = host-only setup (export) */
+  int32_t setup_threads;    /* host threads for setup; 0 = hardware concurrency */
+} pmg_options;
+
+typedef struct {
+  int32_t status;     /* pmg_status of the solve */
+  int32_t iterations; /* V-cycles (FP64) or outer defect-correction steps */
+  double r0;          /* ||b - A x0||_2 */
+  double relres;      /* final ||b - A x||_2 / r0, FP64 */
+  double seconds;     /* wall time of the solve on the host clock */
+} pmg_result;
+
+typedef struct {
+  int64_t n, n1;              /* unknowns at degree p and at p = 1 */
+  int64_t nnz_a, nnz_l, nnz_u, nnz_r, nnz_p;
+  int32_t nlev;               /* levels of the p = 1 hierarchy incl. the direct one */
+  int32_t n_coarsest;         /* unknowns of the direct solve */
+  int64_t nnz_a1;             /* nnz of the finest p = 1 operator */
+  int32_t segments;           /* lines of the triangular-solve schedule */
+  int32_t seg_len;            /* rows per line */
+  int32_t dag_levels_l, dag_levels_u; /* depth of the L and U dependency DAGs */
+  int64_t bytes_vcycle;       /* algorithmic HBM bytes of one FP64 V-cycle */
+  int64_t bytes_spmv, bytes_trisolve_l, bytes_trisolve_u, bytes_restrict, bytes_prolong,
+      bytes_coarse;
+  int64_t device_bytes;       /* device memory held by the handle */
+  double t_assembly, t_ilut, t_upload; /* setup phase times, seconds */
+} pmg_info;
+
+/* Fills *o with the defaults listed above. */
+pmg_status pmg_default_options(pmg_options *o);
+
+/* Setup (timed separately, not the hot path): host assembly of A_p, f_p,
+ * the lumped masses M_p^L and M_1^L, the transfer matrix P_1^p (Section 3,
+ * "Prolongation and restriction"), the rediscretised degree-1 hierarchy
+ * ("Coarse grid operator"), ILUT(tau, m) of A_p in the natural order
+ * ("Smoother"), the triangular-solve schedule, then upload to device
+ * `o->device`.  With o->device == -1 nothing touches a GPU and only
+ * pmg_get_info / pmg_export work.  o may be NULL (defaults).
+ * Errors: EINVAL (bad problem/options), ENOMEM, EZEROPIVOT, EDEVICE. */
+pmg_status pmg_setup(const pmg_problem *prob, const pmg_options *o, pmg_handle *out);
+
+/* Releases every resource of h (device memory included).  NULL is a no-op. */
+pmg_status pmg_destroy(pmg_handle h);
+
+/* Copies the load vector f_{h,p} (Section 2) into b (device, length n). */
+pmg_status pmg_rhs(pmg_handle h, double *b, void *stream);
+
+/* Step a1: r = b - A_{h,p} x (Section 3, step 2 defect); if rnorm != NULL the
+ * 2-norm of r is written there (host) and the stream is synchronised. */
+pmg_status pmg_residual(pmg_handle h, const double *b, const double *x, double *r, double *rnorm,
+                        void *stream);
+
+/* Steps a2 + a3: one ILUT smoothing step (Section 3, "Smoother"):
+ * x <- x + U^{-1} L^{-1} r, r given (normally b - A x).  r is not modified. */
+pmg_status pmg_smooth(pmg_handle h, const double *r, double *x, void *stream);
+
+/* Step a4: r1 = (M_1^L)^{-1} P_p^1 r (lumped L2 restriction, Section 3). */
+pmg_status pmg_restrict(pmg_handle h, const double *r, double *r1, void *stream);
+
+/* Step a5: e1 = coarse_cycles h-multigrid V-cycles on A_{h,1} e1 = r1 from
+ * e1 = 0 (multicolour Gauss-Seidel, canonical transfers, direct solve on the
+ * coarsest mesh; Section 3 and Figure 1).  r1, e1 device, length n1. */
+pmg_status pmg_coarse(pmg_handle h, const double *r1, double *e1, void *stream);
+
+/* Step a6: x <- x + (M_p^L)^{-1} P_1^p e1 (lumped L2 prolongation, Section 3). */
+pmg_status pmg_prolong(pmg_handle h, const double *e1, double *x, void *stream);
+
+/* One FP64 p-multigrid V-cycle (steps a1-a6): on entry r must hold b - A x
+ * (e.g. from pmg_residual); on exit x is updated and r = b - A x.  If rnorm
+ * != NULL, ||r||_2 is written there and the stream is synchronised. */
+pmg_status pmg_vcycle(pmg_handle h, const double *b, double *x, double *r, double *rnorm,
+                      void *stream);
+
+/* Stand-alone solver (Section 5): V-cycles from the initial guess in x until
+ * ||b - A x|| <= tol ||b - A x0|| (step a7).  With precision PMG_FP32_IN_FP64
+ * each outer step is an FP32 V-cycle on the FP64 residual (defect
+ * correction; outer residual, update and p = 1 solve in FP64).  x holds the
+ * last iterate also on EDIVERGED / EMAXIT.  hist (host, may be NULL,
+ * length max_iter + 1) receives ||r_k|| / ||r_0||.  res may be NULL.
+ * Returns the solve status (also in res->status); ENAN if r0 is not finite;
+ * r0 == 0 returns OK after 0 iterations. */
+pmg_status pmg_solve(pmg_handle h, const double *b, double *x, double tol, pmg_result *res,
+                     double *hist, void *stream);
+
+/* Sizes, DAG depths, algorithmic bytes and setup times. */
+pmg_status pmg_get_info(pmg_handle h, pmg_info *info);
+
+/* Host copies of setup operators (test hook).  which: 0 A_p, 1 L (strict
+ * lower), 2 U (diagonal first), 3 P_p^1 (n1 x n), 4 P_1^p (n x n1),
+ * 5 A_{2^k h,1} (level k), 6 canonical prolongation level k -> k+1.
+ * dims[0..2] = rows, cols, nnz are always written; rp (rows+1), ci, v are
+ * filled when non-NULL.  EINVAL for an unknown operator or level. */
+pmg_status pmg_export(pmg_handle h, int32_t which, int32_t level, int64_t *dims, int64_t *rp,
+                      int32_t *ci, double *v);
+
+/* Host copies of setup vectors: 0 f_p (n), 1 M_p^L (n), 2 M_1^L (n1),
+ * 3 inverse of the coarsest A_1 (n_coarsest^2, row-major). */
+pmg_status pmg_export_vec(pmg_handle h, int32_t which, double *out);
+
+const char *pmg_status_str(pmg_status s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char *pmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMG_H */

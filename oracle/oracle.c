@@ -649,17 +649,20 @@ static int canonical_prolongation(int dim, int nc, ocsr *P) {
 /*   rule 2: keep the M largest entries in the strict lower part and the M    */
 /*   largest in the strict upper part, M = floor(m nnz(A) / n) (mode 0, "per  */
 /*   part"), or the M largest off-diagonal entries in total (mode 1, "per     */
-/*   row"); ties by |value| are broken by the smaller column; exact zeros are */
-/*   never stored.                                                            */
+/*   row"); magnitudes are ranked in single precision and ties go to the     */
+/*   smaller column; exact zeros are never stored.                            */
 /* L is returned as the strict lower part (unit diagonal implied), U as the  */
 /* upper part with the diagonal first in each row.  A zero or non-finite     */
 /* pivot is an error (no substitution).  fill <= 0 means "no limit".         */
 /* ------------------------------------------------------------------------ */
 typedef struct { int j; double v; } ent;
 
+/* Rule 2 ranks magnitudes rounded to single precision, so that entries equal
+ * in exact arithmetic (mirror images on a symmetric grid) tie and go to the
+ * smaller column instead of being ordered by FP64 rounding noise. */
 static int ent_cmp_mag(const void *a, const void *b) {
   const ent *x = a, *y = b;
-  double ax = fabs(x->v), ay = fabs(y->v);
+  float ax = (float)fabs(x->v), ay = (float)fabs(y->v);
   if (ax > ay) return -1;
   if (ax < ay) return 1;
   return (x->j < y->j) ? -1 : (x->j > y->j);

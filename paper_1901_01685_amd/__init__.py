@@ -1,0 +1,234 @@
+"""Python binding of the MI355X p-multigrid library (include/pmg.h).
+
+Argument marshalling only: every step of the solve phase runs in the HIP
+kernels of libpmg.so.  Vectors are torch CUDA tensors (float64, contiguous)
+or raw device pointers; streams default to torch's current stream.  The
+library must be built in-tree (``python -m paper_1901_01685_amd._build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpmg.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EZEROPIVOT, EDIVERGED, EMAXIT, ENAN, EBUDGET = range(9)
+GEOM_BOX, GEOM_QUARTER_ANNULUS = 0, 1
+RHS_SINE, RHS_ANNULUS = 0, 1
+FP64, FP32_IN_FP64 = 0, 1
+OP_A, OP_L, OP_U, OP_R, OP_P, OP_A1, OP_PH = range(7)
+VEC_F, VEC_MLP, VEC_ML1, VEC_COARSE_INV = range(4)
+
+
+class PmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pmg status {status}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("n_elem", C.c_int32),
+                ("geometry", C.c_int32), ("rhs_kind", C.c_int32), ("freq", C.c_int32 * 3)]
+
+
+class Options(C.Structure):
+    _fields_ = [("ilut_tau", C.c_double), ("ilut_fill", C.c_double), ("ilut_limit_mode", C.c_int32),
+                ("nu1", C.c_int32), ("nu2", C.c_int32), ("coarse_cycles", C.c_int32),
+                ("coarse_min_elems", C.c_int32), ("gs_variant", C.c_int32), ("precision", C.c_int32),
+                ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
+                ("setup_threads", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("r0", C.c_double),
+                ("relres", C.c_double), ("seconds", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n1", C.c_int64), ("nnz_a", C.c_int64), ("nnz_l", C.c_int64),
+                ("nnz_u", C.c_int64), ("nnz_r", C.c_int64), ("nnz_p", C.c_int64), ("nlev", C.c_int32),
+                ("n_coarsest", C.c_int32), ("nnz_a1", C.c_int64), ("segments", C.c_int32),
+                ("seg_len", C.c_int32), ("dag_levels_l", C.c_int32), ("dag_levels_u", C.c_int32),
+                ("bytes_vcycle", C.c_int64), ("bytes_spmv", C.c_int64), ("bytes_trisolve_l", C.c_int64),
+                ("bytes_trisolve_u", C.c_int64), ("bytes_restrict", C.c_int64),
+                ("bytes_prolong", C.c_int64), ("bytes_coarse", C.c_int64), ("device_bytes", C.c_int64),
+                ("t_assembly", C.c_double), ("t_ilut", C.c_double), ("t_upload", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# exported symbols and their signatures (the tests check them against include/pmg.h)
+_VP, _DP, _I64P, _I32P = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+SIGNATURES = {
+    "pmg_default_options": (C.c_int, [C.POINTER(Options)]),
+    "pmg_setup": (C.c_int, [C.POINTER(Problem), C.POINTER(Options), C.POINTER(_VP)]),
+    "pmg_destroy": (C.c_int, [_VP]),
+    "pmg_rhs": (C.c_int, [_VP, _VP, _VP]),
+    "pmg_residual": (C.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
+    "pmg_smooth": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_restrict": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_coarse": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_prolong": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_vcycle": (C.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
+    "pmg_solve": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(Result), _DP, _VP]),
+    "pmg_get_info": (C.c_int, [_VP, C.POINTER(Info)]),
+    "pmg_export": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _I64P, _I32P, _DP]),
+    "pmg_export_vec": (C.c_int, [_VP, C.c_int32, _DP]),
+    "pmg_status_str": (C.c_char_p, [C.c_int]),
+    "pmg_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libpmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_1901_01685_amd._build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        raise PmgError(st, lib().pmg_last_error().decode())
+    return st
+
+
+def _ptr(t):
+    """Device pointer of a torch CUDA tensor (float64, contiguous) or a raw int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _check(lib().pmg_default_options(C.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def make_problem(dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1)):
+    fr = list(freq) + [1] * (3 - len(freq))
+    return Problem(dim, degree, n_elem, geometry, rhs_kind, (C.c_int32 * 3)(*fr))
+
+
+class Solver:
+    """One set-up problem (pmg_setup handle) with the solve-phase entry points."""
+
+    def __init__(self, dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE,
+                 freq=(1, 1, 1), **opts):
+        self.problem = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq)
+        self.options = default_options(**opts)
+        h = C.c_void_p()
+        _check(lib().pmg_setup(C.byref(self.problem), C.byref(self.options), C.byref(h)))
+        self._h = h
+        self.info = self.get_info()
+        self.n, self.n1 = int(self.info.n), int(self.info.n1)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pmg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_info(self) -> Info:
+        i = Info()
+        _check(lib().pmg_get_info(self._h, C.byref(i)))
+        return i
+
+    # ------------------------------------------------------------- solve phase
+    def rhs(self, b, stream=None):
+        _check(lib().pmg_rhs(self._h, _ptr(b), _stream(stream)))
+
+    def residual(self, b, x, r, norm=False, stream=None):
+        nv = C.c_double(0.0)
+        _check(lib().pmg_residual(self._h, _ptr(b), _ptr(x), _ptr(r), C.byref(nv) if norm else None,
+                                  _stream(stream)))
+        return nv.value if norm else None
+
+    def smooth(self, r, x, stream=None):
+        _check(lib().pmg_smooth(self._h, _ptr(r), _ptr(x), _stream(stream)))
+
+    def restrict(self, r, r1, stream=None):
+        _check(lib().pmg_restrict(self._h, _ptr(r), _ptr(r1), _stream(stream)))
+
+    def coarse(self, r1, e1, stream=None):
+        _check(lib().pmg_coarse(self._h, _ptr(r1), _ptr(e1), _stream(stream)))
+
+    def prolong(self, e1, x, stream=None):
+        _check(lib().pmg_prolong(self._h, _ptr(e1), _ptr(x), _stream(stream)))
+
+    def vcycle(self, b, x, r, norm=False, stream=None):
+        nv = C.c_double(0.0)
+        _check(lib().pmg_vcycle(self._h, _ptr(b), _ptr(x), _ptr(r), C.byref(nv) if norm else None,
+                                _stream(stream)))
+        return nv.value if norm else None
+
+    def solve(self, b, x, tol=1e-8, stream=None, check=True):
+        """Returns (status, iterations, relres, r0, seconds, hist)."""
+        res = Result()
+        hist = np.zeros(int(self.options.max_iter) + 1)
+        st = lib().pmg_solve(self._h, _ptr(b), _ptr(x), tol, C.byref(res),
+                             hist.ctypes.data_as(_DP), _stream(stream))
+        if check and st not in (OK, EMAXIT, EDIVERGED, ENAN):
+            _check(st)
+        return st, res.iterations, res.relres, res.r0, res.seconds, hist[: res.iterations + 1].copy()
+
+    # ------------------------------------------------------------- test hooks
+    def export(self, which, level=0):
+        import scipy.sparse as sp
+        dims = np.zeros(3, dtype=np.int64)
+        _check(lib().pmg_export(self._h, which, level, dims.ctypes.data_as(_I64P), None, None, None))
+        nr, nc, nnz = (int(v) for v in dims)
+        rp = np.zeros(nr + 1, dtype=np.int64)
+        ci = np.zeros(max(nnz, 1), dtype=np.int32)
+        v = np.zeros(max(nnz, 1), dtype=np.float64)
+        _check(lib().pmg_export(self._h, which, level, dims.ctypes.data_as(_I64P), rp.ctypes.data_as(_I64P),
+                                ci.ctypes.data_as(_I32P), v.ctypes.data_as(_DP)))
+        return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(nr, nc))
+
+    def export_vec(self, which):
+        n = {VEC_F: self.n, VEC_MLP: self.n, VEC_ML1: self.n1,
+             VEC_COARSE_INV: int(self.info.n_coarsest) ** 2}[which]
+        out = np.zeros(max(n, 1))
+        _check(lib().pmg_export_vec(self._h, which, out.ctypes.data_as(_DP)))
+        return out[:n]

@@ -1,0 +1,58 @@
+// Host-side setup of the p-multigrid solver: spline spaces, Galerkin
+// assembly, lumped transfers, the degree-1 hierarchy and ILUT.  Built with
+// -ffp-contract=off so every sum is evaluated in the order written.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pmg {
+
+// Host CSR with sorted columns.
+struct Csr {
+  int nrows = 0, ncols = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+struct SetupParams {
+  int dim = 2, p = 2, nel = 16, geom = 0, rhs = 0;
+  int freq[3] = {1, 1, 1};
+  double tau = 1e-12, fill = 1.0;
+  int limit_mode = 0;
+  int coarse_min = 8;
+  int threads = 1;
+};
+
+struct HostOps {
+  int dim = 2, p = 2, nel = 16;
+  int n = 0, n1 = 0;           // interior unknowns at degree p and 1
+  Csr A, L, U;                 // U: diagonal first in each row
+  Csr R;                       // P_p^1 (n1 x n)
+  Csr P;                       // P_1^p (n x n1)
+  std::vector<double> f, mlp, ml1;
+  int nlev = 0;
+  std::vector<int> lnel, ln;   // elements / unknowns per degree-1 level
+  std::vector<Csr> A1;         // rediscretised degree-1 operators
+  std::vector<Csr> Ph, Rh;     // canonical prolongation level l <- l+1, and transpose
+  std::vector<double> coarse_inv;  // dense inverse of the coarsest A1 (row-major)
+  int n_coarse = 0;
+  double t_assembly = 0, t_ilut = 0;
+};
+
+// Gauss-Legendre rule on [-1,1], increasing nodes.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Builds everything but ILUT.  Returns 0 or a pmg_status code; msg on error.
+int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg);
+
+// ILUT(tau, m) of A in the natural order; returns 0, or PMG_EZEROPIVOT with
+// the failing row in bad_row.
+int ilut_factor(const Csr& A, double tau, double fill, int mode, int threads, Csr& L, Csr& U,
+                int& bad_row);
+
+Csr transpose(const Csr& A);
+
+}  // namespace pmg

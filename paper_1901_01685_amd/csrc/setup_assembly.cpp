@@ -1,0 +1,699 @@
+// Host setup: spline spaces and Galerkin assembly of every operator of the
+// p-multigrid solve phase.
+//
+//   Section 2: open uniform knot vectors, B-splines of degree p, tensor
+//     products, geometry map F, Galerkin matrix A_{h,p} and load vector.
+//   Section 3, "Prolongation and restriction": mass matrices M_p, M_1, the
+//     transfer matrix P_1^p (int phi_{i,p} phi_{j,1}), row-sum lumping.
+//   Section 3, "Coarse grid operator": degree-1 operators by
+//     rediscretisation on meshes h, 2h, 4h, ... (h-multigrid at p = 1).
+//
+// On the unit box every operator is a sum of Kronecker products of 1-D
+// matrices (tensor basis, separable integrand, tensor Gauss rule), which is
+// how it is assembled here; on the quarter annulus an element loop with the
+// geometry map is used.  Quadrature: p+1 Gauss points per direction for the
+// degree-p operators and the transfer matrix, 2 for degree-1 operators.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <thread>
+
+#include "pmg_host.hpp"
+
+namespace pmg {
+
+static void parallel_for(int64_t n, int threads, const std::function<void(int64_t, int64_t)>& fn) {
+  if (threads <= 1 || n < 2 * threads) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  int64_t chunk = (n + threads - 1) / threads;
+  for (int t = 0; t < threads; ++t) {
+    int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    pool.emplace_back([&, b, e] { fn(b, e); });
+  }
+  for (auto& th : pool) th.join();
+}
+
+// --------------------------------------------------------------- quadrature
+// Roots of P_n by Newton iteration from cos(pi (k - 1/4) / (n + 1/2)); the
+// Legendre values come from Bonnet's recursion; w = 2 / ((1 - x^2) P_n'^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int k = 1; k <= n; ++k) {
+    double z = std::cos(M_PI * (k - 0.25) / (n + 0.5));
+    double pn = 0, dpn = 0;
+    for (int it = 0; it < 100; ++it) {
+      double a = 1.0, b = 0.0;  // P_j, P_{j-1}
+      for (int j = 1; j <= n; ++j) {
+        double c = ((2 * j - 1) * z * a - (j - 1) * b) / j;
+        b = a;
+        a = c;
+      }
+      pn = a;
+      dpn = n * (z * a - b) / (z * z - 1.0);
+      double step = pn / dpn;
+      z -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    double a = 1.0, b = 0.0;
+    for (int j = 1; j <= n; ++j) {
+      double c = ((2 * j - 1) * z * a - (j - 1) * b) / j;
+      b = a;
+      a = c;
+    }
+    dpn = n * (z * a - b) / (z * z - 1.0);
+    x[n - k] = z;
+    w[n - k] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+  }
+}
+
+// ------------------------------------------------------------------ splines
+// Open uniform knot vector: p+1 zeros, k/nel, p+1 ones.
+static std::vector<double> open_knots(int p, int nel) {
+  std::vector<double> t(nel + 2 * p + 1);
+  for (int i = 0; i <= p; ++i) {
+    t[i] = 0.0;
+    t[nel + p + i] = 1.0;
+  }
+  for (int k = 1; k < nel; ++k) t[p + k] = (double)k / (double)nel;
+  return t;
+}
+
+// Non-zero B-splines of degree p on knot span s (t[s] <= u < t[s+1]):
+// N[j] = phi_{s-p+j,p}(u), j = 0..p, by the triangular scheme on the left
+// and right knot distances; dN[j] their first derivatives from the degree
+// p-1 values.
+static void span_basis(const std::vector<double>& t, int s, int p, double u, double* N, double* dN) {
+  double left[16], right[16], Nm[16];
+  auto run = [&](int q, double* out) {
+    out[0] = 1.0;
+    for (int j = 1; j <= q; ++j) {
+      left[j] = u - t[s + 1 - j];
+      right[j] = t[s + j] - u;
+      double saved = 0.0;
+      for (int r = 0; r < j; ++r) {
+        double tmp = out[r] / (right[r + 1] + left[j - r]);
+        out[r] = saved + right[r + 1] * tmp;
+        saved = left[j - r] * tmp;
+      }
+      out[j] = saved;
+    }
+  };
+  run(p, N);
+  if (!dN) return;
+  if (p == 0) {
+    dN[0] = 0.0;
+    return;
+  }
+  run(p - 1, Nm);  // Nm[j] = phi_{s-p+1+j, p-1}, j = 0..p-1
+  for (int j = 0; j <= p; ++j) {
+    int i = s - p + j;
+    double a = 0.0, b = 0.0;
+    if (j >= 1) {
+      double d = t[i + p] - t[i];
+      if (d > 0) a = p * Nm[j - 1] / d;
+    }
+    if (j <= p - 1) {
+      double d = t[i + p + 1] - t[i + 1];
+      if (d > 0) b = p * Nm[j] / d;
+    }
+    dN[j] = a - b;
+  }
+}
+
+// 1-D tables on a uniform mesh: for element e and Gauss point q the values and
+// derivatives of the p+1 functions e..e+p that live on it.
+struct Table1D {
+  int p = 0, nel = 0, nq = 0;
+  std::vector<double> u, wt, val, der;
+  double V(int e, int q, int a) const { return val[((size_t)e * nq + q) * (p + 1) + a]; }
+  double D(int e, int q, int a) const { return der[((size_t)e * nq + q) * (p + 1) + a]; }
+};
+
+static Table1D make_table(int p, int nel, int nq) {
+  Table1D T;
+  T.p = p;
+  T.nel = nel;
+  T.nq = nq;
+  std::vector<double> gx, gw;
+  gauss_legendre(nq, gx, gw);
+  auto t = open_knots(p, nel);
+  T.u.resize((size_t)nel * nq);
+  T.wt.resize((size_t)nel * nq);
+  T.val.resize((size_t)nel * nq * (p + 1));
+  T.der.resize((size_t)nel * nq * (p + 1));
+  for (int e = 0; e < nel; ++e) {
+    double a = t[p + e], b = t[p + e + 1];
+    double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+    for (int q = 0; q < nq; ++q) {
+      double u = mid + half * gx[q];
+      T.u[(size_t)e * nq + q] = u;
+      T.wt[(size_t)e * nq + q] = gw[q] * half;
+      span_basis(t, p + e, p, u, &T.val[((size_t)e * nq + q) * (p + 1)],
+                 &T.der[((size_t)e * nq + q) * (p + 1)]);
+    }
+  }
+  return T;
+}
+
+// Banded 1-D matrix over the full function range of two degrees.
+struct Band1D {
+  int nr = 0, nc = 0, lo = 0, width = 0;  // entry (i, j) at i*width + (j - i + lo)
+  std::vector<double> a;
+  double get(int i, int j) const {
+    int k = j - i + lo;
+    if (k < 0 || k >= width) return 0.0;
+    return a[(size_t)i * width + k];
+  }
+};
+
+// kind 0: int dphi_i dphi_j; kind 1: int phi_i phi_j.  Rows degree pr, cols
+// degree pc on the same mesh, nq Gauss points per element.
+static Band1D matrix_1d(int kind, int pr, int pc, int nel, int nq) {
+  Table1D Tr = make_table(pr, nel, nq), Tc = make_table(pc, nel, nq);
+  Band1D B;
+  B.nr = nel + pr;
+  B.nc = nel + pc;
+  B.lo = pr;
+  B.width = pr + pc + 1;
+  B.a.assign((size_t)B.nr * B.width, 0.0);
+  for (int e = 0; e < nel; ++e)
+    for (int q = 0; q < nq; ++q) {
+      double w = Tr.wt[(size_t)e * nq + q];
+      for (int a = 0; a <= pr; ++a)
+        for (int b = 0; b <= pc; ++b) {
+          double f = kind == 0 ? Tr.D(e, q, a) * Tc.D(e, q, b) : Tr.V(e, q, a) * Tc.V(e, q, b);
+          int i = e + a, j = e + b;
+          B.a[(size_t)i * B.width + (j - i + B.lo)] += w * f;
+        }
+    }
+  return B;
+}
+
+// int phi_i (degree p) over (0,1), and int g phi_i for g(x) = sin(k pi x).
+static std::vector<double> integrals_1d(int p, int nel, int nq, int k) {
+  Table1D T = make_table(p, nel, nq);
+  std::vector<double> s(nel + p, 0.0);
+  for (int e = 0; e < nel; ++e)
+    for (int q = 0; q < nq; ++q) {
+      double w = T.wt[(size_t)e * nq + q];
+      double g = k > 0 ? std::sin(k * M_PI * T.u[(size_t)e * nq + q]) : 1.0;
+      for (int a = 0; a <= p; ++a) s[e + a] += w * g * T.V(e, q, a);
+    }
+  return s;
+}
+
+// --------------------------------------------------------- tensor structure
+static int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// CSR pattern of all interior pairs (i, j) with |j_a - i_a| in [-lo_a, hi]
+// per direction, rows/cols numbered x fastest over interior indices.
+// Interior index c corresponds to full index c + 1.
+struct TensorPattern {
+  int dim, nr1, nc1;  // interior functions per direction (rows, cols)
+};
+
+// Kronecker assembly on the box: value(i, j) = sum over terms of the product
+// over directions of the 1-D entries (full indices), for interior rows/cols.
+// `terms` lists, per term, which 1-D matrix is used in each direction.
+static Csr kron_assemble(int dim, const std::vector<std::vector<const Band1D*>>& terms, int threads) {
+  const Band1D* B0 = terms[0][0];
+  int nr1 = B0->nr - 2, nc1 = B0->nc - 2;
+  int lo = B0->lo, hi = B0->width - 1 - B0->lo;  // j - i in [-lo, hi]
+  int64_t nrows = ipow(nr1, dim);
+  int64_t ncols = ipow(nc1, dim);
+  Csr M;
+  M.nrows = (int)nrows;
+  M.ncols = (int)ncols;
+  M.rp.assign(nrows + 1, 0);
+  auto range1 = [&](int i, int& j0, int& j1) {  // interior col range for interior row i
+    j0 = std::max(0, i - lo);
+    j1 = std::min(nc1 - 1, i + hi);
+  };
+  // counts
+  std::vector<int> cnt1(nr1);
+  for (int i = 0; i < nr1; ++i) {
+    int j0, j1;
+    range1(i, j0, j1);
+    cnt1[i] = std::max(0, j1 - j0 + 1);
+  }
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t t = r, c = 1;
+    for (int a = 0; a < dim; ++a) {
+      c *= cnt1[t % nr1];
+      t /= nr1;
+    }
+    M.rp[r + 1] = M.rp[r] + c;
+  }
+  M.ci.resize(M.rp[nrows]);
+  M.v.resize(M.rp[nrows]);
+  parallel_for(nrows, threads, [&](int64_t rb, int64_t re) {
+    for (int64_t r = rb; r < re; ++r) {
+      int im[3] = {0, 0, 0}, j0[3] = {0, 0, 0}, j1[3] = {0, 0, 0};
+      int64_t t = r;
+      for (int a = 0; a < dim; ++a) {
+        im[a] = (int)(t % nr1);
+        t /= nr1;
+        range1(im[a], j0[a], j1[a]);
+      }
+      int64_t pos = M.rp[r];
+      int jz0 = dim == 3 ? j0[2] : 0, jz1 = dim == 3 ? j1[2] : 0;
+      for (int jz = jz0; jz <= jz1; ++jz)
+        for (int jy = j0[1]; jy <= j1[1]; ++jy)
+          for (int jx = j0[0]; jx <= j1[0]; ++jx) {
+            int jm[3] = {jx, jy, jz};
+            double s = 0.0;
+            for (const auto& term : terms) {
+              double prod = 1.0;
+              for (int a = 0; a < dim; ++a) prod *= term[a]->get(im[a] + 1, jm[a] + 1);
+              s += prod;
+            }
+            int64_t col = jx + (int64_t)nc1 * (jy + (int64_t)nc1 * jz);
+            M.ci[pos] = (int32_t)col;
+            M.v[pos] = s;
+            pos++;
+          }
+    }
+  });
+  return M;
+}
+
+// ------------------------------------------------------------------ annulus
+// F(xi, eta) = (1 + xi) C(eta), C(eta) the rational quadratic arc from (1,0)
+// to (0,1) with middle control point (1,1) and weight sqrt(2)/2.
+struct GeoPt {
+  double x, y, det, ji[2][2];  // ji = J^{-1}
+};
+
+static GeoPt annulus_map(double xi, double eta) {
+  const double wm = std::sqrt(2.0) / 2.0;
+  double om = 1.0 - eta;
+  double b0 = om * om, b1 = 2.0 * eta * om, b2 = eta * eta;
+  double d0 = -2.0 * om, d1 = 2.0 - 4.0 * eta, d2 = 2.0 * eta;
+  double W = b0 + wm * b1 + b2, dW = d0 + wm * d1 + d2;
+  double nx = b0 + wm * b1, dnx = d0 + wm * d1;
+  double ny = wm * b1 + b2, dny = wm * d1 + d2;
+  double cx = nx / W, cy = ny / W;
+  double dcx = (dnx * W - nx * dW) / (W * W), dcy = (dny * W - ny * dW) / (W * W);
+  double r = 1.0 + xi;
+  GeoPt g;
+  g.x = r * cx;
+  g.y = r * cy;
+  double J00 = cx, J01 = r * dcx, J10 = cy, J11 = r * dcy;
+  g.det = J00 * J11 - J01 * J10;
+  g.ji[0][0] = J11 / g.det;
+  g.ji[0][1] = -J01 / g.det;
+  g.ji[1][0] = -J10 / g.det;
+  g.ji[1][1] = J00 / g.det;
+  return g;
+}
+
+static double annulus_f(double x, double y) {
+  double s = x * x + y * y;
+  return 40.0 * x * y * y * (s - 2.0) + 2.0 * x * (s * s - 5.0 * s + 4.0);
+}
+
+static double sine_f(int dim, const int* k, const double* X) {
+  double ks = 0.0, u = 1.0;
+  for (int a = 0; a < dim; ++a) {
+    ks += (double)k[a] * k[a];
+    u *= std::sin(k[a] * M_PI * X[a]);
+  }
+  return M_PI * M_PI * ks * u;
+}
+
+// Element-loop assembly in 2-D with a geometry map.  Rows are interior
+// degree-pr functions, columns interior degree-pc functions.  kind 0:
+// stiffness, 1: mass/transfer.  Rows are split over threads by their y
+// index; each thread visits the element rows that touch its functions and
+// adds only into its own rows, elements in increasing order.
+static Csr element_assemble_2d(int geom, int kind, int pr, int pc, int nel, int nq, int threads) {
+  Table1D Tr = make_table(pr, nel, nq), Tc = make_table(pc, nel, nq);
+  int nr1 = nel + pr - 2, nc1 = nel + pc - 2;
+  // pattern: interior col range per interior row, per direction (overlapping supports)
+  // degree-pr function i (full) lives on elements [i-pr, i]; degree-pc function
+  // j on [j-pc, j]; they overlap iff j in [i - pr, i + pc].
+  auto crange = [&](int ii, int& j0, int& j1) {  // interior indices
+    int i = ii + 1;
+    j0 = std::max(1, i - pr) - 1;
+    j1 = std::min(nel + pc - 2, i + pc) - 1;
+  };
+  Csr M;
+  M.nrows = nr1 * nr1;
+  M.ncols = nc1 * nc1;
+  M.rp.assign((size_t)M.nrows + 1, 0);
+  std::vector<int> c1(nr1);
+  for (int i = 0; i < nr1; ++i) {
+    int a, b;
+    crange(i, a, b);
+    c1[i] = b - a + 1;
+  }
+  for (int r = 0; r < M.nrows; ++r) M.rp[r + 1] = M.rp[r] + (int64_t)c1[r % nr1] * c1[r / nr1];
+  M.ci.resize(M.rp.back());
+  M.v.assign(M.rp.back(), 0.0);
+  for (int r = 0; r < M.nrows; ++r) {
+    int ix = r % nr1, iy = r / nr1, x0, x1, y0, y1;
+    crange(ix, x0, x1);
+    crange(iy, y0, y1);
+    int64_t pos = M.rp[r];
+    for (int jy = y0; jy <= y1; ++jy)
+      for (int jx = x0; jx <= x1; ++jx) M.ci[pos++] = jx + nc1 * jy;
+  }
+  int nlr = (pr + 1) * (pr + 1), nlc = (pc + 1) * (pc + 1);
+  parallel_for(nr1, threads, [&](int64_t yb, int64_t ye) {
+    std::vector<double> vr(nlr), gr(2 * nlr), vc(nlc), gc(2 * nlc);
+    // full y-index range of owned rows: [yb+1, ye]; elements ey in [yb+1-pr, ye]
+    int e0 = std::max(0, (int)yb + 1 - pr), e1 = std::min(nel - 1, (int)ye);
+    for (int ey = e0; ey <= e1; ++ey)
+      for (int ex = 0; ex < nel; ++ex)
+        for (int qy = 0; qy < nq; ++qy)
+          for (int qx = 0; qx < nq; ++qx) {
+            double u = Tr.u[(size_t)ex * nq + qx], v = Tr.u[(size_t)ey * nq + qy];
+            double wq = Tr.wt[(size_t)ex * nq + qx] * Tr.wt[(size_t)ey * nq + qy];
+            double ji[2][2] = {{1, 0}, {0, 1}}, det = 1.0;
+            if (geom == 1) {
+              GeoPt g = annulus_map(u, v);
+              det = g.det;
+              std::memcpy(ji, g.ji, sizeof(ji));
+            }
+            double dw = wq * det;
+            auto fill_side = [&](const Table1D& T, int p, double* vv, double* gg) {
+              for (int ay = 0; ay <= p; ++ay)
+                for (int ax = 0; ax <= p; ++ax) {
+                  int l = ax + (p + 1) * ay;
+                  double bx = T.V(ex, qx, ax), by = T.V(ey, qy, ay);
+                  double hx = T.D(ex, qx, ax) * by, hy = bx * T.D(ey, qy, ay);
+                  vv[l] = bx * by;
+                  gg[2 * l] = ji[0][0] * hx + ji[1][0] * hy;
+                  gg[2 * l + 1] = ji[0][1] * hx + ji[1][1] * hy;
+                }
+            };
+            fill_side(Tr, pr, vr.data(), gr.data());
+            fill_side(Tc, pc, vc.data(), gc.data());
+            for (int ay = 0; ay <= pr; ++ay) {
+              int fy = ey + ay;  // full y index of the row function
+              if (fy < yb + 1 || fy > ye) continue;
+              if (fy == 0 || fy == nel + pr - 1) continue;
+              for (int ax = 0; ax <= pr; ++ax) {
+                int fx = ex + ax;
+                if (fx == 0 || fx == nel + pr - 1) continue;
+                int row = (fx - 1) + nr1 * (fy - 1);
+                int la = ax + (pr + 1) * ay;
+                int cx0, cx1;
+                crange(fx - 1, cx0, cx1);
+                int rowlen = cx1 - cx0 + 1;
+                for (int by = 0; by <= pc; ++by) {
+                  int gy = ey + by;
+                  if (gy == 0 || gy == nel + pc - 1) continue;
+                  for (int bx = 0; bx <= pc; ++bx) {
+                    int gx = ex + bx;
+                    if (gx == 0 || gx == nel + pc - 1) continue;
+                    int lb = bx + (pc + 1) * by;
+                    double val = kind == 0 ? gr[2 * la] * gc[2 * lb] + gr[2 * la + 1] * gc[2 * lb + 1]
+                                           : vr[la] * vc[lb];
+                    int cy0, cy1;
+                    crange(fy - 1, cy0, cy1);
+                    int64_t pos = M.rp[row] + (int64_t)((gy - 1) - cy0) * rowlen + ((gx - 1) - cx0);
+                    M.v[pos] += dw * val;
+                  }
+                }
+              }
+            }
+          }
+  });
+  return M;
+}
+
+// Load vector and lumped mass (int Phi_i) by an element loop in 2-D.
+static void element_vectors_2d(int geom, int rhs, const int* k, int p, int nel, int nq,
+                               std::vector<double>* f, std::vector<double>* ml) {
+  Table1D T = make_table(p, nel, nq);
+  int n1 = nel + p - 2;
+  if (f) f->assign((size_t)n1 * n1, 0.0);
+  if (ml) ml->assign((size_t)n1 * n1, 0.0);
+  for (int ey = 0; ey < nel; ++ey)
+    for (int ex = 0; ex < nel; ++ex)
+      for (int qy = 0; qy < nq; ++qy)
+        for (int qx = 0; qx < nq; ++qx) {
+          double u = T.u[(size_t)ex * nq + qx], v = T.u[(size_t)ey * nq + qy];
+          double wq = T.wt[(size_t)ex * nq + qx] * T.wt[(size_t)ey * nq + qy];
+          double det = 1.0, X[3] = {u, v, 0};
+          if (geom == 1) {
+            GeoPt g = annulus_map(u, v);
+            det = g.det;
+            X[0] = g.x;
+            X[1] = g.y;
+          }
+          double fx = 0.0;
+          if (f) fx = rhs == 1 ? annulus_f(X[0], X[1]) : sine_f(2, k, X);
+          for (int ay = 0; ay <= p; ++ay) {
+            int fy = ey + ay;
+            if (fy == 0 || fy == nel + p - 1) continue;
+            for (int ax = 0; ax <= p; ++ax) {
+              int fxi = ex + ax;
+              if (fxi == 0 || fxi == nel + p - 1) continue;
+              double phi = T.V(ex, qx, ax) * T.V(ey, qy, ay);
+              int row = (fxi - 1) + n1 * (fy - 1);
+              if (f) (*f)[row] += wq * det * fx * phi;
+              if (ml) (*ml)[row] += wq * det * phi;
+            }
+          }
+        }
+}
+
+// Canonical prolongation between interior degree-1 nodes of meshes nc and
+// 2 nc: coarse hat I = fine hat 2I + (fine hats 2I-1 and 2I+1) / 2, tensor
+// product over directions.
+static Csr canonical_prolongation(int dim, int nc) {
+  int nci = nc - 1, nfi = 2 * nc - 1;
+  int64_t nrows = ipow(nfi, dim);
+  Csr P;
+  P.nrows = (int)nrows;
+  P.ncols = (int)ipow(nci, dim);
+  P.rp.assign(nrows + 1, 0);
+  // 1-D: fine f gets coarse c with weight 1 if f = 2c+1, 1/2 if f = 2c or 2c+2
+  auto w1 = [&](int f, int* cs, double* ws) {
+    int n = 0;
+    if (f % 2 == 1) {
+      cs[n] = (f - 1) / 2;
+      ws[n++] = 1.0;
+    } else {
+      if (f / 2 - 1 >= 0) {
+        cs[n] = f / 2 - 1;
+        ws[n++] = 0.5;
+      }
+      if (f / 2 < nci) {
+        cs[n] = f / 2;
+        ws[n++] = 0.5;
+      }
+    }
+    return n;
+  };
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t t = r, m = 1;
+    for (int a = 0; a < dim; ++a) {
+      int cs[2];
+      double ws[2];
+      m *= w1((int)(t % nfi), cs, ws);
+      t /= nfi;
+    }
+    P.rp[r + 1] = P.rp[r] + m;
+  }
+  P.ci.resize(P.rp.back());
+  P.v.resize(P.rp.back());
+  for (int64_t r = 0; r < nrows; ++r) {
+    int cs[3][2], nn[3] = {1, 1, 1};
+    double ws[3][2] = {{1, 0}, {1, 0}, {1, 0}};
+    cs[1][0] = cs[2][0] = 0;
+    int64_t t = r;
+    for (int a = 0; a < dim; ++a) {
+      nn[a] = w1((int)(t % nfi), cs[a], ws[a]);
+      t /= nfi;
+    }
+    int64_t pos = P.rp[r];
+    for (int c = 0; c < (dim == 3 ? nn[2] : 1); ++c)
+      for (int b = 0; b < nn[1]; ++b)
+        for (int a = 0; a < nn[0]; ++a) {
+          int64_t col = cs[0][a] + (int64_t)nci * (cs[1][b] + (int64_t)nci * (dim == 3 ? cs[2][c] : 0));
+          P.ci[pos] = (int32_t)col;
+          P.v[pos] = ws[0][a] * ws[1][b] * (dim == 3 ? ws[2][c] : 1.0);
+          pos++;
+        }
+  }
+  return P;
+}
+
+Csr transpose(const Csr& A) {
+  Csr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.rp.assign((size_t)T.nrows + 1, 0);
+  for (int64_t k = 0; k < A.nnz(); ++k) T.rp[A.ci[k] + 1]++;
+  for (int i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(A.nnz());
+  T.v.resize(A.nnz());
+  std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < A.nrows; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      int64_t d = pos[A.ci[k]]++;
+      T.ci[d] = i;
+      T.v[d] = A.v[k];
+    }
+  return T;
+}
+
+// Dense inverse of the (small, SPD) coarsest operator via Cholesky.
+static bool dense_spd_inverse(const Csr& A, std::vector<double>& inv) {
+  int n = A.nrows;
+  std::vector<double> C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) C[(size_t)i * n + A.ci[k]] = A.v[k];
+  for (int j = 0; j < n; ++j) {
+    double s = C[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
+    if (!(s > 0.0)) return false;
+    double d = std::sqrt(s);
+    C[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = C[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
+      C[(size_t)i * n + j] = t / d;
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> y(n), x(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= C[(size_t)i * n + k] * y[k];
+      y[i] = s / C[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < n; ++k) s -= C[(size_t)k * n + i] * x[k];
+      x[i] = s / C[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
+  }
+  return true;
+}
+
+int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int dim = sp.dim, p = sp.p, nel = sp.nel;
+  H.dim = dim;
+  H.p = p;
+  H.nel = nel;
+  H.n = (int)ipow(nel + p - 2, dim);
+  H.n1 = (int)ipow(nel - 1, dim);
+  const int th = std::max(1, sp.threads);
+  if (sp.geom == 0) {
+    // ---- unit box: Kronecker products of 1-D Galerkin matrices
+    Band1D K = matrix_1d(0, p, p, nel, p + 1), M = matrix_1d(1, p, p, nel, p + 1);
+    std::vector<std::vector<const Band1D*>> termsA;
+    for (int a = 0; a < dim; ++a) {
+      std::vector<const Band1D*> t(dim, &M);
+      t[a] = &K;
+      termsA.push_back(t);
+    }
+    H.A = kron_assemble(dim, termsA, th);
+    Band1D X = matrix_1d(1, p, 1, nel, p + 1);
+    H.P = kron_assemble(dim, {std::vector<const Band1D*>(dim, &X)}, th);
+    // lumped masses = int Phi_i = product of 1-D integrals; load vector
+    // f = pi^2 (sum k^2) prod_a int sin(k_a pi x) phi
+    auto ip = integrals_1d(p, nel, p + 1, 0), i1 = integrals_1d(1, nel, 2, 0);
+    H.mlp.resize(H.n);
+    H.ml1.resize(H.n1);
+    H.f.resize(H.n);
+    std::vector<std::vector<double>> sf(dim);
+    double ks = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      sf[a] = integrals_1d(p, nel, p + 1, sp.freq[a]);
+      ks += (double)sp.freq[a] * sp.freq[a];
+    }
+    int np1 = nel + p - 2, n11 = nel - 1;
+    for (int64_t r = 0; r < H.n; ++r) {
+      int64_t t = r;
+      double m = 1.0, s = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        int i = (int)(t % np1) + 1;
+        t /= np1;
+        m *= ip[i];
+        s *= sf[a][i];
+      }
+      H.mlp[r] = m;
+      H.f[r] = M_PI * M_PI * ks * s;
+    }
+    for (int64_t r = 0; r < H.n1; ++r) {
+      int64_t t = r;
+      double m = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        m *= i1[(int)(t % n11) + 1];
+        t /= n11;
+      }
+      H.ml1[r] = m;
+    }
+  } else {
+    if (dim != 2) {
+      msg = "the quarter annulus is two-dimensional";
+      return 1;
+    }
+    H.A = element_assemble_2d(1, 0, p, p, nel, p + 1, th);
+    H.P = element_assemble_2d(1, 1, p, 1, nel, p + 1, th);
+    element_vectors_2d(1, sp.rhs, sp.freq, p, nel, p + 1, &H.f, &H.mlp);
+    element_vectors_2d(1, sp.rhs, sp.freq, 1, nel, 2, nullptr, &H.ml1);
+  }
+  H.R = transpose(H.P);
+  // ---- degree-1 hierarchy by rediscretisation
+  int ne = nel;
+  H.A1.clear();
+  H.Ph.clear();
+  H.Rh.clear();
+  H.lnel.clear();
+  H.ln.clear();
+  for (;;) {
+    H.lnel.push_back(ne);
+    H.ln.push_back((int)ipow(ne - 1, dim));
+    if (sp.geom == 0) {
+      Band1D K1 = matrix_1d(0, 1, 1, ne, 2), M1 = matrix_1d(1, 1, 1, ne, 2);
+      std::vector<std::vector<const Band1D*>> t1;
+      for (int a = 0; a < dim; ++a) {
+        std::vector<const Band1D*> t(dim, &M1);
+        t[a] = &K1;
+        t1.push_back(t);
+      }
+      H.A1.push_back(kron_assemble(dim, t1, th));
+    } else {
+      H.A1.push_back(element_assemble_2d(1, 0, 1, 1, ne, 2, th));
+    }
+    if (ne <= sp.coarse_min || ne % 2 != 0 || H.A1.size() >= 24) break;
+    H.Ph.push_back(canonical_prolongation(dim, ne / 2));
+    H.Rh.push_back(transpose(H.Ph.back()));
+    ne /= 2;
+  }
+  H.nlev = (int)H.A1.size();
+  H.n_coarse = H.ln.back();
+  if (H.n_coarse > 1024) {
+    msg = "coarsest degree-1 level has " + std::to_string(H.n_coarse) +
+          " unknowns (limit 1024): use n_elem = 2^k * m with m <= coarse_min_elems";
+    return 1;
+  }
+  if (H.n_coarse > 0 && !dense_spd_inverse(H.A1.back(), H.coarse_inv)) {
+    msg = "coarsest degree-1 operator is not positive definite";
+    return 4;
+  }
+  H.t_assembly = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return 0;
+}
+
+}  // namespace pmg

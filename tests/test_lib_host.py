@@ -1,0 +1,111 @@
+"""CPU tests of the library: the C ABI is exported as declared in
+include/pmg.h, the host setup (assembly, lumping, transfers, degree-1
+hierarchy, ILUT) agrees with the independently written oracle, and the
+argument checks return the documented status codes.  No device is touched:
+handles are set up with device = -1 (host-only)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1901_01685_amd as P
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pmg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*(?:pmg_status|const char\s*\*)\s*(pmg_\w+)\s*\(", src, flags=re.M))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert "pmg_setup" in names and "pmg_solve" in names and len(names) >= 15
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert names == set(P.SIGNATURES), names ^ set(P.SIGNATURES)
+
+
+def _rel(a, b):
+    a = a.toarray() if hasattr(a, "toarray") else np.asarray(a)
+    b = b.toarray() if hasattr(b, "toarray") else np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _same_pattern(a, b):
+    a.sort_indices(); b.sort_indices()
+    return np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+
+
+SETUP_CASES = [(2, 2, 16, 0), (2, 3, 32, 0), (2, 5, 16, 1), (2, 4, 32, 1), (3, 2, 8, 0),
+               (3, 2, 16, 0), (3, 3, 12, 0), (2, 5, 64, 0)]
+
+
+@pytest.mark.parametrize("case", SETUP_CASES, ids=lambda c: "d%dp%dn%dg%d" % c)
+def test_host_setup_matches_oracle(case):
+    dim, p, nel, g = case
+    s = P.Solver(dim, p, nel, geometry=g, rhs_kind=g, device=-1)
+    o = O.Oracle(dim, p, nel, geom=g, rhs=g)
+    assert (s.n, s.n1, s.info.nlev) == (o.n, o.n1, o.nlev)
+    assert _same_pattern(s.export(P.OP_A), o.A()) and _rel(s.export(P.OP_A), o.A()) < 1e-13
+    assert _rel(s.export_vec(P.VEC_F), o.f()) < 1e-13
+    assert _rel(s.export_vec(P.VEC_MLP), o.mlp()) < 1e-13
+    assert _rel(s.export_vec(P.VEC_ML1), o.ml1()) < 1e-13
+    assert _same_pattern(s.export(P.OP_R), o.R()) and _rel(s.export(P.OP_R), o.R()) < 1e-13
+    assert _same_pattern(s.export(P.OP_P), o.P()) and _rel(s.export(P.OP_P), o.P()) < 1e-13
+    for lev in range(o.nlev):
+        assert _rel(s.export(P.OP_A1, lev), o.A1(lev)) < 1e-13
+    for lev in range(o.nlev - 1):
+        assert _rel(s.export(P.OP_PH, lev), o.Ph(lev)) == 0.0
+    C = o.chol()
+    inv = np.linalg.inv(C @ C.T)
+    nc = C.shape[0]
+    assert _rel(s.export_vec(P.VEC_COARSE_INV).reshape(nc, nc), inv) < 1e-12
+    # ILUT: identical patterns, values to rounding
+    for a, b in ((s.export(P.OP_L), o.L()), (s.export(P.OP_U), o.U())):
+        assert _same_pattern(a, b)
+        assert _rel(a, b) < 1e-12
+
+
+def test_ilut_independent_of_thread_count():
+    a = P.Solver(2, 4, 48, geometry=1, rhs_kind=1, device=-1, setup_threads=1)
+    b = P.Solver(2, 4, 48, geometry=1, rhs_kind=1, device=-1, setup_threads=7)
+    for op in (P.OP_L, P.OP_U):
+        x, y = a.export(op), b.export(op)
+        assert np.array_equal(x.indptr, y.indptr) and np.array_equal(x.indices, y.indices)
+        assert np.array_equal(x.data, y.data)
+
+
+def test_info_sizes_and_bytes():
+    s = P.Solver(2, 5, 64, device=-1)
+    i = s.info
+    assert i.n == (64 + 5 - 2) ** 2 and i.n1 == 63 ** 2
+    assert i.seg_len == 67 and i.segments == 67
+    # lower bound on the natural-order DAG depth of the ILU(0) pattern
+    assert i.dag_levels_l >= (5 + 2) * (67 - 1) + 1
+    assert i.bytes_spmv == 12 * i.nnz_a + 4 * (i.n + 1) + 24 * i.n
+    assert i.bytes_vcycle > 3 * i.bytes_spmv
+
+
+def test_status_codes_host():
+    with pytest.raises(P.PmgError) as e:
+        P.Solver(4, 2, 16, device=-1)
+    assert e.value.status == P.EINVAL
+    with pytest.raises(P.PmgError) as e:
+        P.Solver(3, 2, 16, geometry=P.GEOM_QUARTER_ANNULUS, device=-1)
+    assert e.value.status == P.EINVAL
+    # 26 -> 13 stops at the odd mesh: 12^2 = 144 unknowns is fine in 2-D ...
+    s = P.Solver(2, 2, 26, device=-1)
+    assert s.info.nlev == 2 and s.info.n_coarsest == 144
+    with pytest.raises(P.PmgError) as e:
+        P.Solver(3, 2, 26, device=-1)           # ... but 12^3 = 1728 exceeds the limit in 3-D
+    assert e.value.status == P.EINVAL
+    s = P.Solver(2, 2, 16, device=-1)
+    st = P.lib().pmg_solve(s._h, None, None, 1e-8, None, None, None)
+    assert st == P.EDEVICE
+    assert P.lib().pmg_get_info(None, None) == P.EINVAL
+    assert P.lib().pmg_status_str(P.EZEROPIVOT) == b"zero pivot in ILUT"
