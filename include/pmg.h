@@ -54,6 +54,7 @@ enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1 };
 enum { PMG_FP64 = 0, PMG_FP32_IN_FP64 = 1 };
 enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1 };
 enum { PMG_GS_MULTICOLOR = 0 };
+enum { PMG_ORDER_NATURAL = 0, PMG_ORDER_NESTED_DISSECTION = 1 };
 
 /* The problem (Section 2): -Lap u = f on Omega = F((0,1)^dim), u = 0 on the
  * boundary, discretised with tensor B-splines of degree `degree` on the open
@@ -90,6 +91,8 @@ typedef struct {
   double diverge_ratio;     /* PMG_EDIVERGED above this relative residual */
   int32_t device;           /* HIP device ordinal; -1 = host-only setup (export) */
   int32_t setup_threads;    /* host threads for setup; 0 = hardware concurrency */
+  int32_t ordering;         /* ILUT permutation: PMG_ORDER_* (default nested dissection) */
+  int32_t nd_leaf;          /* nested dissection: lines per undivided block (default 8) */
 } pmg_options;
 
 typedef struct {
@@ -115,6 +118,15 @@ typedef struct {
   int64_t device_bytes;       /* device memory held by the handle */
   double t_assembly, t_ilut, t_upload; /* setup phase times, seconds */
 } pmg_info;
+
+/* ILUT ordering (Section 3, "Smoother": the factorisation follows a
+ * fill-reducing permutation the paper does not name).  Unknowns are grouped
+ * in grid lines along x; PMG_ORDER_NESTED_DISSECTION cuts the grid of lines
+ * recursively across its longest side with separators p lines wide (the two
+ * halves are then uncoupled), orders each half first and the separator
+ * last, and keeps blocks of at most nd_leaf lines in natural order.  The
+ * factors are those of P A P^T and one smoothing step is
+ * x <- x + P^T U^{-1} L^{-1} P r. */
 
 /* Fills *o with the defaults listed above. */
 pmg_status pmg_default_options(pmg_options *o);
@@ -143,6 +155,14 @@ pmg_status pmg_residual(pmg_handle h, const double *b, const double *x, double *
 /* Steps a2 + a3: one ILUT smoothing step (Section 3, "Smoother"):
  * x <- x + U^{-1} L^{-1} r, r given (normally b - A x).  r is not modified. */
 pmg_status pmg_smooth(pmg_handle h, const double *r, double *x, void *stream);
+
+/* Step a2 alone: y = L^{-1} r (forward substitution with the unit lower ILUT
+ * factor, Section 3, "Smoother").  r, y device, length n, distinct. */
+pmg_status pmg_lower_solve(pmg_handle h, const double *r, double *y, void *stream);
+
+/* Step a3 alone: e = U^{-1} y (backward substitution with the upper ILUT
+ * factor), written over y, and x <- x + e.  y, x device, length n. */
+pmg_status pmg_upper_solve(pmg_handle h, double *y, double *x, void *stream);
 
 /* Step a4: r1 = (M_1^L)^{-1} P_p^1 r (lumped L2 restriction, Section 3). */
 pmg_status pmg_restrict(pmg_handle h, const double *r, double *r1, void *stream);
@@ -176,7 +196,7 @@ pmg_status pmg_solve(pmg_handle h, const double *b, double *x, double tol, pmg_r
 pmg_status pmg_get_info(pmg_handle h, pmg_info *info);
 
 /* Host copies of setup operators (test hook).  which: 0 A_p, 1 L (strict
- * lower), 2 U (diagonal first), 3 P_p^1 (n1 x n), 4 P_1^p (n x n1),
+ * lower, permuted numbering), 2 U (diagonal first, permuted numbering), 3 P_p^1 (n1 x n), 4 P_1^p (n x n1),
  * 5 A_{2^k h,1} (level k), 6 canonical prolongation level k -> k+1.
  * dims[0..2] = rows, cols, nnz are always written; rp (rows+1), ci, v are
  * filled when non-NULL.  EINVAL for an unknown operator or level. */
@@ -186,6 +206,28 @@ pmg_status pmg_export(pmg_handle h, int32_t which, int32_t level, int64_t *dims,
 /* Host copies of setup vectors: 0 f_p (n), 1 M_p^L (n), 2 M_1^L (n1),
  * 3 inverse of the coarsest A_1 (n_coarsest^2, row-major). */
 pmg_status pmg_export_vec(pmg_handle h, int32_t which, double *out);
+
+/* The ILUT ordering: out[i] = unknown placed at position i (length n). */
+pmg_status pmg_export_perm(pmg_handle h, int32_t *out);
+
+/* Per-step timing with HIP events recorded on the launch stream around each
+ * step of the solve phase (classes below; the coarse class spans the whole
+ * h-multigrid solve).  pmg_profile_enable(h, 1) synchronises the device,
+ * clears the records and starts recording; 0 stops.  pmg_profile_read
+ * waits for the recorded events and writes, per class, the total time in
+ * milliseconds (ms[PMG_PROF_NCLASS]) and the number of timed launches
+ * (count[PMG_PROF_NCLASS]). */
+enum {
+  PMG_PROF_RESIDUAL = 0,
+  PMG_PROF_LOWER = 1,
+  PMG_PROF_UPPER = 2,
+  PMG_PROF_RESTRICT = 3,
+  PMG_PROF_COARSE = 4,
+  PMG_PROF_PROLONG = 5,
+  PMG_PROF_NCLASS = 6
+};
+pmg_status pmg_profile_enable(pmg_handle h, int32_t on);
+pmg_status pmg_profile_read(pmg_handle h, double *ms, int64_t *count);
 
 const char *pmg_status_str(pmg_status s);
 /* Detail of the last error on the calling thread ("" if none). */

@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
 class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("fill", C.c_double), ("limit_mode", C.c_int),
                 ("coarse_cycles", C.c_int), ("gs_variant", C.c_int), ("coarse_min", C.c_int),
-                ("nu1", C.c_int), ("nu2", C.c_int)]
+                ("nu1", C.c_int), ("nu2", C.c_int), ("ordering", C.c_int), ("nd_leaf", C.c_int)]
 
 
 _lib = None
@@ -68,6 +68,7 @@ def lib():
         L.orc_info.argtypes = [vp, i64p]
         L.orc_get_csr.argtypes = [vp, C.c_int, C.c_int, i64p, i64p, ip, dp]
         L.orc_get_vec.argtypes = [vp, C.c_int, dp]
+        L.orc_get_perm.argtypes = [vp, ip]
         L.orc_solve.argtypes = [vp, dp, dp, C.c_double, C.c_int, dp, ip]
         L.orc_vcycle.argtypes = [vp, dp, dp, dp]
         L.orc_cg.argtypes = [vp, dp, dp, C.c_double, C.c_int, C.c_int, ip]
@@ -112,10 +113,12 @@ class Options:
     coarse_min: int = 8
     nu1: int = 1
     nu2: int = 1
+    ordering: int = 1        # 0: natural, 1: nested dissection over grid lines
+    nd_leaf: int = 8
 
     def c(self):
         return _Opts(self.tau, self.fill, self.limit_mode, self.coarse_cycles, self.gs_variant,
-                     self.coarse_min, self.nu1, self.nu2)
+                     self.coarse_min, self.nu1, self.nu2, self.ordering, self.nd_leaf)
 
 
 # ---------------------------------------------------------------- primitives
@@ -270,6 +273,11 @@ class Oracle:
 
     def f(self):
         return self._vec(V_F, self.n)
+
+    def perm(self):
+        out = np.zeros(self.n, dtype=np.int32)
+        lib().orc_get_perm(self._h, _ip(out))
+        return out
 
     def mlp(self):
         return self._vec(V_MLP, self.n)

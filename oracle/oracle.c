@@ -800,6 +800,7 @@ int orc_ilut_raw(int n, const int64_t *rp, const int *ci, const double *v, doubl
 typedef struct {
   double tau, fill;
   int limit_mode, coarse_cycles, gs_variant, coarse_min, nu1, nu2;
+  int ordering, nd_leaf;
 } orc_opts;
 
 typedef struct {
@@ -808,6 +809,7 @@ typedef struct {
   orc_opts o;
   int n, n1;
   ocsr A, L, U;
+  int *perm;  /* ILUT ordering: row i of the factors is unknown perm[i] */
   ocsr R;   /* P_p^1 : n1 x n (restriction matrix) */
   ocsr Pr;  /* P_1^p : n x n1 (prolongation matrix) */
   double *f, *mlp, *ml1;
@@ -833,6 +835,8 @@ void orc_default_opts(orc_opts *o) {
   o->coarse_min = 8;
   o->nu1 = 1;
   o->nu2 = 1;
+  o->ordering = 1;  /* nested dissection over grid lines */
+  o->nd_leaf = 8;
 }
 
 static int dense_cholesky(const ocsr *A, double **out) {
@@ -877,9 +881,97 @@ void orc_free(orc *s) {
     csr_free(&s->A1[l]); csr_free(&s->Ph[l]); csr_free(&s->Rh[l]);
     free(s->hv_b[l]); free(s->hv_e[l]); free(s->hv_r[l]);
   }
-  free(s->f); free(s->mlp); free(s->ml1); free(s->chol);
+  free(s->f); free(s->mlp); free(s->ml1); free(s->chol); free(s->perm);
   free(s->r); free(s->y); free(s->r1); free(s->e1);
   free(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fill-reducing permutation for ILUT (Section 3, "Smoother": the factors    */
+/* are computed after a fill-reducing permutation, which the paper does not  */
+/* name).  Unknowns are grouped in grid lines along x (all unknowns sharing  */
+/* y, or (y, z)); lines form a grid of dimension dim-1 and two lines are     */
+/* coupled when their indices differ by at most p in every direction.        */
+/*   ordering 0: natural order.                                              */
+/*   ordering 1: nested dissection of the line grid: a box of lines with     */
+/*     more than nd_leaf lines is cut across its longest side by a separator */
+/*     p lines wide (which leaves the two halves uncoupled); the first half, */
+/*     then the second, are ordered recursively, the separator comes last.   */
+/*     Boxes of at most nd_leaf lines (or too thin to cut) keep the natural  */
+/*     line order.  Within a line the natural order is kept.                 */
+/* ------------------------------------------------------------------------ */
+static void nd_box(int a0, int b0, int a1, int b1, int nl0, int p, int leaf, int *out, int *pos) {
+  int e0 = b0 - a0, e1 = b1 - a1;
+  if (e0 <= 0 || e1 <= 0) return;
+  int longest = e0 >= e1 ? e0 : e1;
+  if (e0 * e1 <= leaf || longest < 2 * p + 3) {
+    for (int k = a1; k < b1; ++k)
+      for (int j = a0; j < b0; ++j) out[(*pos)++] = j + nl0 * k;
+    return;
+  }
+  if (e0 >= e1) {
+    int m = a0 + (e0 - p) / 2;
+    nd_box(a0, m, a1, b1, nl0, p, leaf, out, pos);
+    nd_box(m + p, b0, a1, b1, nl0, p, leaf, out, pos);
+    nd_box(m, m + p, a1, b1, nl0, p, e0 * e1, out, pos);
+  } else {
+    int m = a1 + (e1 - p) / 2;
+    nd_box(a0, b0, a1, m, nl0, p, leaf, out, pos);
+    nd_box(a0, b0, m + p, b1, nl0, p, leaf, out, pos);
+    nd_box(a0, b0, m, m + p, nl0, p, e0 * e1, out, pos);
+  }
+}
+
+/* perm[i] = original unknown placed at position i */
+static int *make_ordering(int dim, int nint, int p, int ordering, int leaf) {
+  int n = ipow(nint, dim);
+  int *perm = malloc(sizeof(int) * (size_t)n);
+  if (ordering == 0) {
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    return perm;
+  }
+  int nlines = ipow(nint, dim - 1);
+  int *ord = malloc(sizeof(int) * (size_t)nlines);
+  int pos = 0;
+  if (dim == 2) nd_box(0, nint, 0, 1, nint, p, leaf, ord, &pos);
+  else nd_box(0, nint, 0, nint, nint, p, leaf, ord, &pos);
+  int i = 0;
+  for (int q = 0; q < nlines; ++q)
+    for (int k = 0; k < nint; ++k) perm[i++] = ord[q] * nint + k;
+  free(ord);
+  return perm;
+}
+
+/* B = P A P^T with P the permutation (row i of B = row perm[i] of A),
+ * columns sorted. */
+static int permute_sym(const ocsr *A, const int *perm, ocsr *B) {
+  int n = A->nrows;
+  int *inv = malloc(sizeof(int) * (size_t)n);
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  B->nrows = B->ncols = n;
+  B->nnz = A->nnz;
+  B->rp = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  B->ci = malloc(sizeof(int) * (size_t)(A->nnz > 0 ? A->nnz : 1));
+  B->v = malloc(sizeof(double) * (size_t)(A->nnz > 0 ? A->nnz : 1));
+  B->rp[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    int r = perm[i];
+    int64_t len = A->rp[r + 1] - A->rp[r];
+    B->rp[i + 1] = B->rp[i] + len;
+    ent *tmp = malloc(sizeof(ent) * (size_t)(len > 0 ? len : 1));
+    for (int64_t k = 0; k < len; ++k) {
+      tmp[k].j = inv[A->ci[A->rp[r] + k]];
+      tmp[k].v = A->v[A->rp[r] + k];
+    }
+    qsort(tmp, (size_t)len, sizeof(ent), ent_cmp_col);
+    for (int64_t k = 0; k < len; ++k) {
+      B->ci[B->rp[i] + k] = tmp[k].j;
+      B->v[B->rp[i] + k] = tmp[k].v;
+    }
+    free(tmp);
+  }
+  free(inv);
+  return ORC_OK;
 }
 
 /* Builds every operator of the method for one problem:
@@ -929,10 +1021,14 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, const int *freq, con
   }
   s->nlev = l + 1;
   if (!rc && s->n1 > 0) rc = dense_cholesky(&s->A1[s->nlev - 1], &s->chol);
+  s->perm = make_ordering(dim, nel + p - 2, p, s->o.ordering, s->o.nd_leaf);
   if (!rc && !(stage_mask & 1)) {
     s->bad_row = -1;
-    rc = orc_ilut_raw(s->n, s->A.rp, s->A.ci, s->A.v, s->o.tau, s->o.fill, s->o.limit_mode, &s->L,
-                      &s->U, &s->bad_row);
+    ocsr Ap = {0};
+    permute_sym(&s->A, s->perm, &Ap);
+    rc = orc_ilut_raw(s->n, Ap.rp, Ap.ci, Ap.v, s->o.tau, s->o.fill, s->o.limit_mode, &s->L, &s->U,
+                      &s->bad_row);
+    csr_free(&Ap);
   }
   s->r = calloc(s->n, sizeof(double));
   s->y = calloc(s->n, sizeof(double));
@@ -970,11 +1066,12 @@ static double norm2(const double *v, int n) {
 }
 
 /* One ILUT smoothing step (Section 3, "Smoother"): given r = f - A u,
- * e = U^{-1} L^{-1} r by forward then backward substitution, u <- u + e. */
+ * e = P^T U^{-1} L^{-1} P r by forward then backward substitution with the
+ * factors of the permuted matrix P A P^T, u <- u + e. */
 static void ilut_smooth(const orc *s, const double *r, double *x, double *y) {
   int n = s->n;
   for (int i = 0; i < n; ++i) {
-    double t = r[i];
+    double t = r[s->perm[i]];
     for (int64_t k = s->L.rp[i]; k < s->L.rp[i + 1]; ++k) t -= s->L.v[k] * y[s->L.ci[k]];
     y[i] = t;
   }
@@ -984,7 +1081,7 @@ static void ilut_smooth(const orc *s, const double *r, double *x, double *y) {
     for (int64_t k = k0 + 1; k < s->U.rp[i + 1]; ++k) t -= s->U.v[k] * y[s->U.ci[k]];
     y[i] = t / s->U.v[k0];
   }
-  for (int i = 0; i < n; ++i) x[i] += y[i];
+  for (int i = 0; i < n; ++i) x[s->perm[i]] += y[i];
 }
 
 /* Gauss-Seidel sweep on A_l e = b (Section 3: the smoother of the h-multigrid
@@ -1215,6 +1312,11 @@ int orc_get_csr(const orc *s, int which, int lev, int64_t *dims, int64_t *rp, in
   if (rp) memcpy(rp, m->rp, sizeof(int64_t) * ((size_t)m->nrows + 1));
   if (ci) memcpy(ci, m->ci, sizeof(int) * (size_t)m->nnz);
   if (v) memcpy(v, m->v, sizeof(double) * (size_t)m->nnz);
+  return ORC_OK;
+}
+
+int orc_get_perm(const orc *s, int *out) {
+  memcpy(out, s->perm, sizeof(int) * (size_t)s->n);
   return ORC_OK;
 }
 

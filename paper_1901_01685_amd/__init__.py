@@ -21,8 +21,10 @@ OK, EINVAL, ENOMEM, EDEVICE, EZEROPIVOT, EDIVERGED, EMAXIT, ENAN, EBUDGET = rang
 GEOM_BOX, GEOM_QUARTER_ANNULUS = 0, 1
 RHS_SINE, RHS_ANNULUS = 0, 1
 FP64, FP32_IN_FP64 = 0, 1
+ORDER_NATURAL, ORDER_NESTED_DISSECTION = 0, 1
 OP_A, OP_L, OP_U, OP_R, OP_P, OP_A1, OP_PH = range(7)
 VEC_F, VEC_MLP, VEC_ML1, VEC_COARSE_INV = range(4)
+PROF_CLASSES = ("residual", "lower", "upper", "restrict", "coarse", "prolong")
 
 
 class PmgError(RuntimeError):
@@ -41,7 +43,7 @@ class Options(C.Structure):
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("coarse_cycles", C.c_int32),
                 ("coarse_min_elems", C.c_int32), ("gs_variant", C.c_int32), ("precision", C.c_int32),
                 ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
-                ("setup_threads", C.c_int32)]
+                ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -72,6 +74,10 @@ SIGNATURES = {
     "pmg_rhs": (C.c_int, [_VP, _VP, _VP]),
     "pmg_residual": (C.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
     "pmg_smooth": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_lower_solve": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_upper_solve": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_profile_enable": (C.c_int, [_VP, C.c_int32]),
+    "pmg_profile_read": (C.c_int, [_VP, _DP, _I64P]),
     "pmg_restrict": (C.c_int, [_VP, _VP, _VP, _VP]),
     "pmg_coarse": (C.c_int, [_VP, _VP, _VP, _VP]),
     "pmg_prolong": (C.c_int, [_VP, _VP, _VP, _VP]),
@@ -80,6 +86,7 @@ SIGNATURES = {
     "pmg_get_info": (C.c_int, [_VP, C.POINTER(Info)]),
     "pmg_export": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _I64P, _I32P, _DP]),
     "pmg_export_vec": (C.c_int, [_VP, C.c_int32, _DP]),
+    "pmg_export_perm": (C.c_int, [_VP, _I32P]),
     "pmg_status_str": (C.c_char_p, [C.c_int]),
     "pmg_last_error": (C.c_char_p, []),
 }
@@ -188,6 +195,22 @@ class Solver:
     def smooth(self, r, x, stream=None):
         _check(lib().pmg_smooth(self._h, _ptr(r), _ptr(x), _stream(stream)))
 
+    def lower_solve(self, r, y, stream=None):
+        _check(lib().pmg_lower_solve(self._h, _ptr(r), _ptr(y), _stream(stream)))
+
+    def upper_solve(self, y, x, stream=None):
+        _check(lib().pmg_upper_solve(self._h, _ptr(y), _ptr(x), _stream(stream)))
+
+    def profile_enable(self, on=True):
+        _check(lib().pmg_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{class: (total_ms, launches)} for the classes of PROF_CLASSES."""
+        ms = np.zeros(len(PROF_CLASSES))
+        cnt = np.zeros(len(PROF_CLASSES), dtype=np.int64)
+        _check(lib().pmg_profile_read(self._h, ms.ctypes.data_as(_DP), cnt.ctypes.data_as(_I64P)))
+        return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
+
     def restrict(self, r, r1, stream=None):
         _check(lib().pmg_restrict(self._h, _ptr(r), _ptr(r1), _stream(stream)))
 
@@ -225,6 +248,11 @@ class Solver:
         _check(lib().pmg_export(self._h, which, level, dims.ctypes.data_as(_I64P), rp.ctypes.data_as(_I64P),
                                 ci.ctypes.data_as(_I32P), v.ctypes.data_as(_DP)))
         return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(nr, nc))
+
+    def export_perm(self):
+        out = np.zeros(self.n, dtype=np.int32)
+        _check(lib().pmg_export_perm(self._h, out.ctypes.data_as(_I32P)))
+        return out
 
     def export_vec(self, which):
         n = {VEC_F: self.n, VEC_MLP: self.n, VEC_ML1: self.n1,

@@ -205,14 +205,61 @@ __device__ __forceinline__ void publish(int* prog, int seg, int val, int lane) {
   if (lane == 0) __hip_atomic_store(prog + seg, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// y = L^{-1} r, L unit lower (strict part stored, sorted columns).
+// Called by every wave once its segment is final.  The last wave to finish
+// clears the progress counters and the ticket for the next launch (all other
+// waves are past their last read of them), so a solve needs no separate
+// reset launch.  state[0] = ticket, state[1] = finished waves.
+__device__ __forceinline__ void finish_segment(int nseg, int* prog, unsigned* state, int lane) {
+  unsigned prev = 0;
+  if (lane == 0) prev = atomicAdd(state + 1, 1u);
+  prev = __builtin_amdgcn_readfirstlane(__shfl((int)prev, 0, 64));
+  if (prev == (unsigned)(nseg - 1)) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int i = lane; i < nseg; i += kWave) st_dev(prog + i, 0);
+    if (lane == 0) {
+      st_dev(state, 0u);
+      st_dev(state + 1, 0u);
+    }
+  }
+}
+
+// Off-chunk part of a row: t -= sum_{k in [k0, k1)} v[k] y[ci[k]], in k order,
+// with the loads issued in batches of 8 so that they are in flight together.
+template <typename T>
+__device__ __forceinline__ T gather_sub(T t, int k0, int k1, const int* __restrict__ ci,
+                                        const T* __restrict__ v, const T* y) {
+  int k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    int c[8];
+    T a[8], yy[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = ci[k + u];
+      a[u] = v[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) yy[u] = ld_dev(y + c[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t -= a[u] * yy[u];
+  }
+  for (; k < k1; ++k) t -= v[k] * ld_dev(y + ci[k]);
+  return t;
+}
+
+// y = L^{-1} P r, L unit lower (strict part stored, sorted columns), P the
+// ILUT ordering ((P r)_i = r[perm[i]]).  ks[row]
+// is the first entry of the row whose column lies in the row's own chunk.
+// The in-chunk entries are staged in a dense 64 x 64 LDS tile (source row j,
+// target lane) before the wait, so the ordered part touches no global memory.
 template <typename T>
 __global__ __launch_bounds__(64) void trisolve_lower(int nseg, int seg_len, const int* __restrict__ rp,
                                                      const int* __restrict__ ci, const T* __restrict__ v,
-                                                     const T* __restrict__ r, T* y,
-                                                     const int* __restrict__ wptr,
+                                                     const int* __restrict__ ks,
+                                                     const int* __restrict__ perm, const T* __restrict__ r,
+                                                     T* y, const int* __restrict__ wptr,
                                                      const int2* __restrict__ waits, int* prog,
                                                      unsigned* ticket) {
+  __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
   const int s = wave_ticket(ticket);
   if (s >= nseg) return;
@@ -223,40 +270,42 @@ __global__ __launch_bounds__(64) void trisolve_lower(int nseg, int seg_len, cons
     const int nrow = min(kWave, seg_len - c * kWave);
     const int row = r0 + lane;
     const bool act = lane < nrow;
-    wait_chunk(wptr, waits, s * nch + c, lane, prog);
+#pragma unroll 8
+    for (int j = 0; j < kWave; ++j) tile[j * kWave + lane] = 0;
+    int k0 = 0, k1 = 0, kin = 0;
     T t = 0;
-    int k = 0, k1 = 0;
     if (act) {
-      t = r[row];
-      k = rp[row];
+      k0 = rp[row];
       k1 = rp[row + 1];
-      for (; k < k1; ++k) {
-        const int col = ci[k];
-        if (col >= r0) break;
-        t -= v[k] * ld_dev(y + col);
-      }
+      kin = ks[row];
+      t = r[perm[row]];
+      for (int k = kin; k < k1; ++k) tile[(ci[k] - r0) * kWave + lane] = v[k];
     }
+    wait_chunk(wptr, waits, s * nch + c, lane, prog);
+    if (act) t = gather_sub(t, k0, kin, ci, v, y);
     // rows inside the chunk, in order
     for (int j = 0; j < nrow - 1; ++j) {
       const T yj = lane_bcast(t, j);
-      if (act && k < k1 && ci[k] == r0 + j) {
-        t -= v[k] * yj;
-        ++k;
-      }
+      t -= tile[j * kWave + lane] * yj;
     }
     if (act) st_dev(y + row, t);
     publish(prog, s, c * kWave + nrow, lane);
   }
+  finish_segment(nseg, prog, ticket, lane);
 }
 
 // e = U^{-1} y (diagonal first in each row, then the strict upper part
-// sorted), written over y, and x += e.
+// sorted), written over y, and x += P^T e.  ks[row] is the first entry whose
+// column lies beyond the row's own chunk.
 template <typename T>
 __global__ __launch_bounds__(64) void trisolve_upper(int nseg, int seg_len, const int* __restrict__ rp,
                                                      const int* __restrict__ ci, const T* __restrict__ v,
-                                                     T* y, T* __restrict__ x, const int* __restrict__ wptr,
+                                                     const int* __restrict__ ks,
+                                                     const int* __restrict__ perm, T* y, T* __restrict__ x,
+                                                     const int* __restrict__ wptr,
                                                      const int2* __restrict__ waits, int* prog,
                                                      unsigned* ticket) {
+  __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
   const int sr = wave_ticket(ticket);
   if (sr >= nseg) return;
@@ -267,39 +316,37 @@ __global__ __launch_bounds__(64) void trisolve_upper(int nseg, int seg_len, cons
   for (int c = nch - 1; c >= 0; --c) {
     const int r0 = seg0 + c * kWave;
     const int nrow = min(kWave, seg_len - c * kWave);
-    const int rend = r0 + nrow;
     const int row = r0 + lane;
     const bool act = lane < nrow;
-    wait_chunk(wptr, waits, sr * nch + (nch - 1 - c), lane, prog);
+#pragma unroll 8
+    for (int j = 0; j < kWave; ++j) tile[j * kWave + lane] = 0;
     T t = 0, dg = 1;
-    int kin0 = 0, kin1 = 0;  // in-chunk entries [kin0, kin1)
+    int kout = 0, k1 = 0;
     if (act) {
-      const int k0 = rp[row], k1 = rp[row + 1];
+      const int k0 = rp[row];
+      k1 = rp[row + 1];
+      kout = ks[row];
       t = y[row];
       dg = v[k0];
-      int k = k0 + 1;
-      kin0 = k;
-      while (k < k1 && ci[k] < rend) ++k;
-      kin1 = k;
-      for (; k < k1; ++k) t -= v[k] * ld_dev(y + ci[k]);
+      for (int k = k0 + 1; k < kout; ++k) tile[(ci[k] - r0) * kWave + lane] = v[k];
     }
+    wait_chunk(wptr, waits, sr * nch + (nch - 1 - c), lane, prog);
+    if (act) t = gather_sub(t, kout, k1, ci, v, y);
     // rows inside the chunk, last to first
     T e = 0;
     for (int j = nrow - 1; j >= 0; --j) {
       if (lane == j) e = t / dg;
       const T ej = lane_bcast(e, j);
-      if (act && lane < j && kin1 > kin0 && ci[kin1 - 1] == r0 + j) {
-        t -= v[kin1 - 1] * ej;
-        --kin1;
-      }
+      t -= tile[j * kWave + lane] * ej;
     }
     if (act) {
       st_dev(y + row, e);
-      x[row] += e;
+      x[perm[row]] += e;
     }
     done += nrow;
     publish(prog, s, done, lane);
   }
+  finish_segment(nseg, prog, ticket, lane);
 }
 
 }  // namespace pmg

@@ -53,8 +53,10 @@ struct TriSched {
   int nseg = 0, seg_len = 0, nch = 0, nwaits = 0, dag_levels = 0;
   std::vector<int> wptr;
   std::vector<int2> waits;
+  std::vector<int> ks;  // per row: split between in-chunk and off-chunk entries
   int* d_wptr = nullptr;
   int2* d_waits = nullptr;
+  int* d_ks = nullptr;
 };
 
 int pick_group(double avg) {
@@ -105,6 +107,20 @@ void build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
     }
   }
   S.nwaits = (int)S.waits.size();
+  // split index per row: lower -> first entry with column >= chunk start;
+  // upper -> first entry (after the diagonal) with column >= chunk end
+  S.ks.assign(n, 0);
+  for (int row = 0; row < n; ++row) {
+    const int s = row / seg_len, c = (row - s * seg_len) / 64;
+    const int cs = s * seg_len + c * 64, ce = std::min(s * seg_len + seg_len, cs + 64);
+    int64_t k = T.rp[row] + (upper ? 1 : 0);
+    if (!upper) {
+      while (k < T.rp[row + 1] && T.ci[k] < cs) ++k;
+    } else {
+      while (k < T.rp[row + 1] && T.ci[k] < ce) ++k;
+    }
+    S.ks[row] = (int)k;
+  }
   // depth of the dependency DAG (for the record)
   std::vector<int> lev(n, 0);
   int mx = 0;
@@ -143,7 +159,8 @@ struct pmg_handle_s {
   float *mlp_inv32 = nullptr, *ml1_inv32 = nullptr;
   TriSched tl, tu;
   int *prog_l = nullptr, *prog_u = nullptr;
-  unsigned* tickets = nullptr;  // [0] lower, [1] upper
+  int* d_perm = nullptr;
+  unsigned* tickets = nullptr;  // lower: [0] ticket, [1] finished; upper: [2], [3]
   // work
   double *y = nullptr, *r = nullptr, *r1 = nullptr, *e1 = nullptr, *partial = nullptr,
          *scalar = nullptr;
@@ -155,6 +172,22 @@ struct pmg_handle_s {
   size_t dev_bytes = 0;
   std::vector<void*> allocs;
   pmg_info info{};
+  // per-step event timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev[PMG_PROF_NCLASS];  // start/stop pairs
+  size_t ev_used[PMG_PROF_NCLASS] = {};
+  void prof_mark(int cls, hipStream_t st, bool start) {
+    auto& v = ev[cls];
+    size_t& u = ev_used[cls];
+    if (u >= v.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      v.push_back(e);
+    }
+    hipEventRecord(v[u], st);
+    ++u;
+    (void)start;
+  }
 
   template <typename T>
   pmg_status dalloc(T** p, size_t count) {
@@ -201,6 +234,8 @@ struct pmg_handle_s {
       hipSetDevice(device);
       hipDeviceSynchronize();
       for (void* p : allocs) hipFree(p);
+      for (auto& v : ev)
+        for (hipEvent_t e : v) hipEventDestroy(e);
       if (host_scalar) hipHostFree(host_scalar);
     }
   }
@@ -209,6 +244,19 @@ struct pmg_handle_s {
 namespace {
 
 unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// Per-step timing with HIP events on the launch stream (pmg_profile_*).
+struct ProfScope {
+  pmg_handle h;
+  int cls;
+  hipStream_t st;
+  ProfScope(pmg_handle h_, int c, hipStream_t s) : h(h_), cls(c), st(s) {
+    if (h->profiling) h->prof_mark(cls, st, true);
+  }
+  ~ProfScope() {
+    if (h->profiling) h->prof_mark(cls, st, false);
+  }
+};
 
 // ------------------------------------------------------------ launch helpers
 template <typename T, int G>
@@ -257,6 +305,7 @@ void fill(T* p, int64_t n, T val, hipStream_t st) {
 
 // r = b - A x; if norm_out != nullptr, ||r||_2 lands in h->scalar (device).
 void residual64(pmg_handle h, const double* b, const double* x, double* r, bool norm, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_RESIDUAL, st);
   csr_launch<double>(pmg::kResid, h->A.nrows, nullptr, h->A, h->A.v, x, b, nullptr, r, h->partial, st);
   if (norm) {
     const int nb = (int)nblocks(h->A.nrows, 256 / h->A.G);
@@ -271,16 +320,27 @@ double read_norm(pmg_handle h, hipStream_t st) {
 }
 
 template <typename T>
-void smooth_impl(pmg_handle h, const T* r, T* x, T* y, bool fp32, hipStream_t st) {
-  const int m = std::max(h->tl.nseg, h->tu.nseg);
-  pmg::reset_ints<<<nblocks(m + 2, 256), 256, 0, st>>>(h->tl.nseg, h->prog_l, h->tu.nseg, h->prog_u);
-  pmg::reset_ints<<<1, 64, 0, st>>>(2, (int*)h->tickets, 0, nullptr);
+void lower_impl(pmg_handle h, const T* r, T* y, bool fp32, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_LOWER, st);
   const T* lv = fp32 ? (const T*)h->L.v32 : (const T*)h->L.v;
+  pmg::trisolve_lower<T><<<h->tl.nseg, 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, h->L.rp, h->L.ci, lv,
+                                                     h->tl.d_ks, h->d_perm, r, y, h->tl.d_wptr, h->tl.d_waits,
+                                                     h->prog_l, h->tickets);
+}
+
+template <typename T>
+void upper_impl(pmg_handle h, T* y, T* x, bool fp32, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_UPPER, st);
   const T* uv = fp32 ? (const T*)h->U.v32 : (const T*)h->U.v;
-  pmg::trisolve_lower<T><<<h->tl.nseg, 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, h->L.rp, h->L.ci, lv, r, y,
-                                                     h->tl.d_wptr, h->tl.d_waits, h->prog_l, h->tickets);
-  pmg::trisolve_upper<T><<<h->tu.nseg, 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, h->U.rp, h->U.ci, uv, y, x,
-                                                     h->tu.d_wptr, h->tu.d_waits, h->prog_u, h->tickets + 1);
+  pmg::trisolve_upper<T><<<h->tu.nseg, 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, h->U.rp, h->U.ci, uv,
+                                                     h->tu.d_ks, h->d_perm, y, x, h->tu.d_wptr, h->tu.d_waits,
+                                                     h->prog_u, h->tickets + 2);
+}
+
+template <typename T>
+void smooth_impl(pmg_handle h, const T* r, T* x, T* y, bool fp32, hipStream_t st) {
+  lower_impl<T>(h, r, y, fp32, st);
+  upper_impl<T>(h, y, x, fp32, st);
 }
 
 void gs_sweeps(pmg_handle h, int l, const double* b, double* e, int nsweep, hipStream_t st) {
@@ -311,15 +371,18 @@ void hcycle(pmg_handle h, int l, const double* b, double* e, hipStream_t st) {
 }
 
 void coarse_impl(pmg_handle h, const double* r1, double* e1, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_COARSE, st);
   fill<double>(e1, h->H.n1, 0.0, st);
   for (int c = 0; c < h->opt.coarse_cycles; ++c) hcycle(h, 0, r1, e1, st);
 }
 
 void restrict64(pmg_handle h, const double* r, double* r1, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_RESTRICT, st);
   csr_launch<double>(pmg::kScale, h->R.nrows, nullptr, h->R, h->R.v, r, nullptr, h->ml1_inv, r1, nullptr, st);
 }
 
 void prolong64(pmg_handle h, const double* e1, double* x, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_PROLONG, st);
   csr_launch<double>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v, e1, nullptr, h->mlp_inv, x, nullptr, st);
 }
 
@@ -435,6 +498,8 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->diverge_ratio = 1e10;
   o->device = 0;
   o->setup_threads = 0;
+  o->ordering = PMG_ORDER_NESTED_DISSECTION;
+  o->nd_leaf = 8;
   return PMG_OK;
 }
 
@@ -449,7 +514,8 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   if (o.nu1 < 0 || o.nu2 < 0 || o.coarse_cycles < 1 || o.coarse_min_elems < 1 || o.max_iter < 0 ||
       !(o.ilut_tau >= 0) || o.gs_variant != PMG_GS_MULTICOLOR ||
       (o.precision != PMG_FP64 && o.precision != PMG_FP32_IN_FP64) ||
-      (o.ilut_limit_mode != PMG_LIMIT_PER_PART && o.ilut_limit_mode != PMG_LIMIT_PER_ROW) || o.device < -1)
+      (o.ilut_limit_mode != PMG_LIMIT_PER_PART && o.ilut_limit_mode != PMG_LIMIT_PER_ROW) || o.device < -1 ||
+      (o.ordering != PMG_ORDER_NATURAL && o.ordering != PMG_ORDER_NESTED_DISSECTION) || o.nd_leaf < 1)
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
@@ -465,6 +531,8 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   sp.fill = o.ilut_fill;
   sp.limit_mode = o.ilut_limit_mode;
   sp.coarse_min = o.coarse_min_elems;
+  sp.ordering = o.ordering;
+  sp.nd_leaf = o.nd_leaf;
   int hw = (int)std::thread::hardware_concurrency();
   sp.threads = o.setup_threads > 0 ? o.setup_threads : std::max(1, std::min(hw, 16));
   int rc = pmg::assemble_all(sp, h->H, msg);
@@ -476,7 +544,9 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   {
     auto t0 = std::chrono::steady_clock::now();
     int bad = -1;
-    rc = pmg::ilut_factor(H.A, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, sp.threads, H.L, H.U, bad);
+    H.perm = pmg::line_ordering(prob->dim, prob->n_elem + prob->degree - 2, prob->degree, o.ordering, o.nd_leaf);
+    pmg::Csr Ap = pmg::permute(H.A, H.perm, sp.threads);
+    rc = pmg::ilut_factor(Ap, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, sp.threads, H.L, H.U, bad);
     H.t_ilut = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return fail(PMG_EZEROPIVOT, "ILUT: zero or non-finite pivot in row " + std::to_string(bad));
   }
@@ -587,9 +657,12 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     if ((s = h->upload(&h->tl.d_waits, h->tl.waits.data(), h->tl.waits.size()))) return s;
     if ((s = h->upload(&h->tu.d_wptr, h->tu.wptr.data(), h->tu.wptr.size()))) return s;
     if ((s = h->upload(&h->tu.d_waits, h->tu.waits.data(), h->tu.waits.size()))) return s;
+    if ((s = h->upload(&h->tl.d_ks, h->tl.ks.data(), h->tl.ks.size()))) return s;
+    if ((s = h->upload(&h->d_perm, H.perm.data(), H.perm.size()))) return s;
+    if ((s = h->upload(&h->tu.d_ks, h->tu.ks.data(), h->tu.ks.size()))) return s;
     if ((s = h->dalloc(&h->prog_l, h->tl.nseg + 1))) return s;
     if ((s = h->dalloc(&h->prog_u, h->tu.nseg + 1))) return s;
-    if ((s = h->dalloc(&h->tickets, 2))) return s;
+    if ((s = h->dalloc(&h->tickets, 4))) return s;
     if ((s = h->dalloc(&h->y, n))) return s;
     if ((s = h->dalloc(&h->r, n))) return s;
     if ((s = h->dalloc(&h->r1, n1))) return s;
@@ -618,7 +691,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     HIP_OK(hipHostMalloc((void**)&h->host_scalar, 4 * sizeof(double), hipHostMallocDefault));
     HIP_OK(hipMemset(h->prog_l, 0, sizeof(int) * (h->tl.nseg + 1)));
     HIP_OK(hipMemset(h->prog_u, 0, sizeof(int) * (h->tu.nseg + 1)));
-    HIP_OK(hipMemset(h->tickets, 0, sizeof(unsigned) * 2));
+    HIP_OK(hipMemset(h->tickets, 0, sizeof(unsigned) * 4));
     HIP_OK(hipDeviceSynchronize());
     I.t_upload = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     I.device_bytes = (int64_t)h->dev_bytes;
@@ -681,6 +754,12 @@ pmg_status pmg_export_vec(pmg_handle h, int32_t which, double* out) {
   return PMG_OK;
 }
 
+pmg_status pmg_export_perm(pmg_handle h, int32_t* out) {
+  if (!h || !out) return fail(PMG_EINVAL, "NULL argument");
+  std::memcpy(out, h->H.perm.data(), sizeof(int32_t) * h->H.perm.size());
+  return PMG_OK;
+}
+
 #define NEED_DEVICE(h)                                                              \
   do {                                                                              \
     if (!(h)) return fail(PMG_EINVAL, "handle is NULL");                            \
@@ -710,6 +789,48 @@ pmg_status pmg_smooth(pmg_handle h, const double* r, double* x, void* stream) {
   if (!r || !x) return fail(PMG_EINVAL, "NULL vector");
   smooth_impl<double>(h, r, x, h->y, false, (hipStream_t)stream);
   HIP_OK(hipGetLastError());
+  return PMG_OK;
+}
+
+pmg_status pmg_lower_solve(pmg_handle h, const double* r, double* y, void* stream) {
+  NEED_DEVICE(h);
+  if (!r || !y) return fail(PMG_EINVAL, "NULL vector");
+  lower_impl<double>(h, r, y, false, (hipStream_t)stream);
+  HIP_OK(hipGetLastError());
+  return PMG_OK;
+}
+
+pmg_status pmg_upper_solve(pmg_handle h, double* y, double* x, void* stream) {
+  NEED_DEVICE(h);
+  if (!y || !x) return fail(PMG_EINVAL, "NULL vector");
+  upper_impl<double>(h, y, x, false, (hipStream_t)stream);
+  HIP_OK(hipGetLastError());
+  return PMG_OK;
+}
+
+pmg_status pmg_profile_enable(pmg_handle h, int32_t on) {
+  NEED_DEVICE(h);
+  HIP_OK(hipDeviceSynchronize());
+  for (auto& u : h->ev_used) u = 0;
+  h->profiling = on != 0;
+  return PMG_OK;
+}
+
+pmg_status pmg_profile_read(pmg_handle h, double* ms, int64_t* count) {
+  NEED_DEVICE(h);
+  if (!ms || !count) return fail(PMG_EINVAL, "NULL argument");
+  for (int c = 0; c < PMG_PROF_NCLASS; ++c) {
+    double tot = 0.0;
+    const size_t pairs = h->ev_used[c] / 2;
+    for (size_t i = 0; i < pairs; ++i) {
+      HIP_OK(hipEventSynchronize(h->ev[c][2 * i + 1]));
+      float t = 0.0f;
+      HIP_OK(hipEventElapsedTime(&t, h->ev[c][2 * i], h->ev[c][2 * i + 1]));
+      tot += t;
+    }
+    ms[c] = tot;
+    count[c] = (int64_t)pairs;
+  }
   return PMG_OK;
 }
 

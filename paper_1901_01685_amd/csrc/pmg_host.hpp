@@ -24,12 +24,14 @@ struct SetupParams {
   int limit_mode = 0;
   int coarse_min = 8;
   int threads = 1;
+  int ordering = 1, nd_leaf = 8;
 };
 
 struct HostOps {
   int dim = 2, p = 2, nel = 16;
   int n = 0, n1 = 0;           // interior unknowns at degree p and 1
-  Csr A, L, U;                 // U: diagonal first in each row
+  Csr A, L, U;                 // L, U: factors of P A P^T; U diagonal first
+  std::vector<int32_t> perm;   // position i of the factors holds unknown perm[i]
   Csr R;                       // P_p^1 (n1 x n)
   Csr P;                       // P_1^p (n x n1)
   std::vector<double> f, mlp, ml1;
@@ -48,11 +50,17 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // Builds everything but ILUT.  Returns 0 or a pmg_status code; msg on error.
 int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg);
 
-// ILUT(tau, m) of A in the natural order; returns 0, or PMG_EZEROPIVOT with
+// ILUT(tau, m) of A in its given row order; returns 0, or PMG_EZEROPIVOT with
 // the failing row in bad_row.
 int ilut_factor(const Csr& A, double tau, double fill, int mode, int threads, Csr& L, Csr& U,
                 int& bad_row);
 
 Csr transpose(const Csr& A);
+
+// ILUT ordering over grid lines (natural or nested dissection).
+std::vector<int32_t> line_ordering(int dim, int nint, int p, int ordering, int leaf);
+
+// B = P A P^T, B_ij = A_{perm[i], perm[j]}, columns sorted.
+Csr permute(const Csr& A, const std::vector<int32_t>& perm, int threads);
 
 }  // namespace pmg

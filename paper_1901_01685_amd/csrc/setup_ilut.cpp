@@ -249,4 +249,90 @@ int ilut_factor(const Csr& A, double tau, double fill, int mode, int threads, Cs
   return 0;
 }
 
+// ----------------------------------------------------------------- ordering
+// Lines along x are indexed by their (y[, z]) position.  Boxes of lines are
+// split across the longest side by a separator p lines wide; the emitted
+// order is first part, second part, separator.  An explicit stack replays
+// that order: a box to split pushes (separator, second, first) so that the
+// first part is processed next.
+std::vector<int32_t> line_ordering(int dim, int nint, int p, int ordering, int leaf) {
+  const int64_t nlines = dim == 2 ? nint : (int64_t)nint * nint;
+  std::vector<int32_t> lines;
+  lines.reserve(nlines);
+  if (ordering == 0) {
+    for (int64_t l = 0; l < nlines; ++l) lines.push_back((int32_t)l);
+  } else {
+    struct Box {
+      int y0, y1, z0, z1;
+      bool whole;  // emit without cutting (a separator)
+    };
+    std::vector<Box> stack;
+    stack.push_back({0, nint, 0, dim == 2 ? 1 : nint, false});
+    while (!stack.empty()) {
+      Box b = stack.back();
+      stack.pop_back();
+      const int ey = b.y1 - b.y0, ez = b.z1 - b.z0;
+      if (ey <= 0 || ez <= 0) continue;
+      const int longest = std::max(ey, ez);
+      if (b.whole || ey * ez <= leaf || longest < 2 * p + 3) {
+        for (int z = b.z0; z < b.z1; ++z)
+          for (int y = b.y0; y < b.y1; ++y) lines.push_back(y + nint * z);
+        continue;
+      }
+      if (ey >= ez) {
+        const int m = b.y0 + (ey - p) / 2;
+        stack.push_back({m, m + p, b.z0, b.z1, true});
+        stack.push_back({m + p, b.y1, b.z0, b.z1, false});
+        stack.push_back({b.y0, m, b.z0, b.z1, false});
+      } else {
+        const int m = b.z0 + (ez - p) / 2;
+        stack.push_back({b.y0, b.y1, m, m + p, true});
+        stack.push_back({b.y0, b.y1, m + p, b.z1, false});
+        stack.push_back({b.y0, b.y1, b.z0, m, false});
+      }
+    }
+  }
+  std::vector<int32_t> perm((size_t)nlines * nint);
+  size_t i = 0;
+  for (int32_t l : lines)
+    for (int x = 0; x < nint; ++x) perm[i++] = l * nint + x;
+  return perm;
+}
+
+Csr permute(const Csr& A, const std::vector<int32_t>& perm, int threads) {
+  const int n = A.nrows;
+  std::vector<int32_t> inv(n);
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  Csr B;
+  B.nrows = B.ncols = n;
+  B.rp.assign((size_t)n + 1, 0);
+  for (int i = 0; i < n; ++i) B.rp[i + 1] = B.rp[i] + (A.rp[perm[i] + 1] - A.rp[perm[i]]);
+  B.ci.resize(B.rp[n]);
+  B.v.resize(B.rp[n]);
+  auto work = [&](int lo, int hi) {
+    std::vector<Entry> tmp;
+    for (int i = lo; i < hi; ++i) {
+      const int r = perm[i];
+      tmp.clear();
+      for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) tmp.push_back({inv[A.ci[k]], A.v[k]});
+      std::sort(tmp.begin(), tmp.end(), col_before);
+      int64_t o = B.rp[i];
+      for (const Entry& e : tmp) {
+        B.ci[o] = e.j;
+        B.v[o] = e.v;
+        ++o;
+      }
+    }
+  };
+  threads = std::max(1, threads);
+  std::vector<std::thread> pool;
+  const int chunk = (n + threads - 1) / threads;
+  for (int t = 0; t < threads; ++t) {
+    const int lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo < hi) pool.emplace_back(work, lo, hi);
+  }
+  for (auto& th : pool) th.join();
+  return B;
+}
+
 }  // namespace pmg

@@ -65,7 +65,8 @@ def test_host_setup_matches_oracle(case):
     inv = np.linalg.inv(C @ C.T)
     nc = C.shape[0]
     assert _rel(s.export_vec(P.VEC_COARSE_INV).reshape(nc, nc), inv) < 1e-12
-    # ILUT: identical patterns, values to rounding
+    # ILUT ordering and factors: identical permutation and patterns, values to rounding
+    assert np.array_equal(s.export_perm(), o.perm())
     for a, b in ((s.export(P.OP_L), o.L()), (s.export(P.OP_U), o.U())):
         assert _same_pattern(a, b)
         assert _rel(a, b) < 1e-12
@@ -80,8 +81,16 @@ def test_ilut_independent_of_thread_count():
         assert np.array_equal(x.data, y.data)
 
 
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_orderings_match_oracle(ordering):
+    for (dim, p, nel) in [(2, 3, 40), (3, 2, 14), (2, 5, 100)]:
+        s = P.Solver(dim, p, nel, device=-1, ordering=ordering)
+        o = O.Oracle(dim, p, nel, opts=O.Options(ordering=ordering), ilut=False)
+        assert np.array_equal(s.export_perm(), o.perm())
+
+
 def test_info_sizes_and_bytes():
-    s = P.Solver(2, 5, 64, device=-1)
+    s = P.Solver(2, 5, 64, device=-1, ordering=0)
     i = s.info
     assert i.n == (64 + 5 - 2) ** 2 and i.n1 == 63 ** 2
     assert i.seg_len == 67 and i.segments == 67

@@ -84,8 +84,10 @@ def test_invariants_paper_constants(mode, geom, dim, p, nel):
     # bit-reproducible on rerun
     o2 = O.Oracle(dim, p, nel, geom=geom, rhs=geom, opts=O.Options(limit_mode=mode))
     assert np.array_equal(o2.L().data, L.data) and np.array_equal(o2.U().indices, U.indices)
-    # L U approximates A: the factorisation error is far below ||A||
-    E = (sp.eye(n) + L) @ U - A
+    # L U approximates the permuted A: the factorisation error is far below ||A||
+    perm = o.perm()
+    Ap = A[perm][:, perm]
+    E = (sp.eye(n) + L) @ U - Ap
     assert abs(E).max() < 0.05 * abs(A).max()
 
 

@@ -50,7 +50,7 @@ def test_two_grid_error_propagator(geom, p):
     exact two-grid method.  Its error propagator, built column by column from
     unit initial guesses with f = 0 (Section 4), must equal
     S (I - diag(M_p^L)^-1 P_1^p A_1^-1 diag(M_1^L)^-1 P_p^1 A) S,
-    S = I - (L U)^-1 A, from the oracle's own operators."""
+    S = I - Pi^T (L U)^-1 Pi A, from the oracle's own operators."""
     o = O.Oracle(2, p, 8, geom=geom, rhs=geom)
     assert o.nlev == 1
     n = o.n
@@ -59,7 +59,8 @@ def test_two_grid_error_propagator(geom, p):
     U = o.U().toarray()
     P = o.P().toarray()
     A1 = o.A1(0).toarray()
-    S = np.eye(n) - np.linalg.solve(U, np.linalg.solve(L, A))
+    Pi = np.eye(n)[o.perm()]            # (Pi v)_i = v[perm[i]]
+    S = np.eye(n) - Pi.T @ np.linalg.solve(U, np.linalg.solve(L, Pi @ A))
     C = np.eye(n) - (P / o.mlp()[:, None]) @ np.linalg.solve(A1, (P.T / o.ml1()[:, None]) @ A)
     E_ref = S @ C @ S
     E = np.zeros((n, n))
@@ -88,6 +89,21 @@ def test_spectral_radius_small_like_table_2a():
         rho = _spectral_radius(o)
         assert rho < 0.1, (p, rho)
         assert rho < 10 * max(r[gold["p"].index(p)] for r in gold["rho"])
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_smoothing_step_is_permuted_ilu_solve(ordering):
+    """One smoothing step equals x + Pi^T (L U)^-1 Pi r (scipy triangular solves)."""
+    o = O.Oracle(2, 3, 24, geom=1, rhs=1, opts=O.Options(ordering=ordering))
+    n = o.n
+    rng = np.random.default_rng(3)
+    r, x = rng.standard_normal(n), rng.standard_normal(n)
+    perm = o.perm()
+    y = spla.spsolve_triangular((o.L() + sp.eye(n)).tocsr(), r[perm], lower=True)
+    e = spla.spsolve_triangular(o.U().tocsr(), y, lower=False)
+    ref = x.copy()
+    ref[perm] += e
+    assert np.abs(o.smooth(r, x) - ref).max() < 1e-12 * np.abs(ref).max()
 
 
 def test_gs_lexicographic_is_triangular_solve():
