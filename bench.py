@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--dim", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 512 MiB (3 times), the reference for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve phase here runs on a single MI355X; "
@@ -115,6 +118,15 @@ def main():
     import paper_1901_01685_amd as pmg
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "launches": 3}))
+        return
     t0 = time.perf_counter()
     s = pmg.Solver(dim=args.dim, degree=args.degree, n_elem=args.nel, device=0)
     t_setup = time.perf_counter() - t0
