@@ -95,6 +95,125 @@ def cpu_baseline(p, nel_full, n_full, budget_s=20.0):
     }
 
 
+def serve_bench(args):
+    """Continuous-batching server on the serving workload: a seeded stream of
+    2-D/3-D unit-square/cube Poisson solves, p uniform in {2..5}, h uniform in
+    {1/32, 1/64, 1/128, 1/256}, manufactured right-hand sides with integer
+    frequencies 1..4 per axis, Poisson arrivals (mean 200 requests/s), FP32
+    V-cycles inside FP64 defect correction to a 1e-10 relative residual.
+    Classes are set up before the stream (setup time reported, not in the
+    latencies); classes above the per-class device budget are rejected and
+    counted.  Compared with plain FP64 single solves (one at a time, FP64
+    V-cycles) and mixed-precision single solves on the same requests."""
+    import numpy as np
+    import paper_1901_01685_amd as pmg
+
+    rng = np.random.default_rng(args.seed)
+    n_warm, n_timed = args.serve_warmup, args.serve_requests
+    total = n_warm + n_timed
+    dims = rng.choice([2, 3], size=total)
+    degs = rng.integers(2, 6, size=total)
+    nels = rng.choice([32, 64, 128, 256], size=total)
+    freqs = rng.integers(1, 5, size=(total, 3))
+    gaps = rng.exponential(1.0 / args.rate, size=total)
+    arrivals = np.cumsum(gaps)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    srv = pmg.Server(max_slots=args.slots, budget_bytes=budget, max_class_bytes=budget // 8,
+                     precision=pmg.FP32_IN_FP64, tol=1e-10)
+    classes = sorted(set(zip(dims.tolist(), degs.tolist(), nels.tolist())))
+    t0 = time.perf_counter()
+    admitted = set()
+    for c in classes:
+        st = srv.prepare(*c)
+        if st == pmg.OK:
+            admitted.add(c)
+        print(f"# class {c}: {'ready' if st == pmg.OK else 'rejected (%d)' % st}", file=sys.stderr, flush=True)
+    t_setup = time.perf_counter() - t0
+
+    # open loop at the arrival rate
+    clock0 = srv.clock()
+    tickets = []
+    rejected = 0
+    for i in range(total):
+        target = clock0 + arrivals[i]
+        while srv.clock() < target:
+            time.sleep(max(0.0, min(0.001, target - srv.clock())))
+        st, t = srv.submit(int(dims[i]), int(degs[i]), int(nels[i]), freq=tuple(int(v) for v in freqs[i]))
+        if st != pmg.OK:
+            rejected += i >= n_warm
+            continue
+        tickets.append((i, t))
+    lat, outer, fails, fin, sub = [], [], 0, [], []
+    for i, t in tickets:
+        st, info, _ = srv.wait(t, want_x=False)
+        if i < n_warm:
+            continue
+        if st != pmg.OK:
+            fails += 1
+            continue
+        lat.append(info["t_finish"] - info["t_submit"])
+        outer.append(info["iterations"])
+        fin.append(info["t_finish"])
+        sub.append(info["t_submit"])
+    lat = np.array(lat)
+    open_loop = {
+        "rate_req_s": args.rate, "requests": n_timed, "completed": len(lat), "rejected_budget": rejected,
+        "failed": fails, "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3), "solves_per_s": len(lat) / (max(fin) - min(sub)),
+        "mean_outer_steps": float(np.mean(outer)),
+    }
+
+    # the same admitted requests, all submitted at once (saturating load)
+    idx = [i for i in range(n_warm, total) if (int(dims[i]), int(degs[i]), int(nels[i])) in admitted]
+    idx = idx[: args.closed_requests]
+
+    def run_batch(slots, precision, sequential):
+        srv.configure(slots, precision)
+        t0 = time.perf_counter()
+        if sequential:
+            for i in idx:
+                st, t = srv.submit(int(dims[i]), int(degs[i]), int(nels[i]), freq=tuple(int(v) for v in freqs[i]))
+                st, info, _ = srv.wait(t, want_x=False)
+                assert st == pmg.OK and info["relres"] <= 1e-10
+        else:
+            ts = []
+            for i in idx:
+                st, t = srv.submit(int(dims[i]), int(degs[i]), int(nels[i]), freq=tuple(int(v) for v in freqs[i]))
+                ts.append(t)
+            for t in ts:
+                st, info, _ = srv.wait(t, want_x=False)
+                assert st == pmg.OK and info["relres"] <= 1e-10
+        return len(idx) / (time.perf_counter() - t0)
+
+    served = run_batch(args.slots, pmg.FP32_IN_FP64, False)
+    plain64 = run_batch(1, pmg.FP64, True)
+    mixed1 = run_batch(1, pmg.FP32_IN_FP64, True)
+    stats = srv.stats()
+    srv.close()
+    out = {
+        "metric": METRIC,
+        "value": served,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32-in-f64",
+        "data": "synthetic",
+        "config": {"workload": "serving: 2-D/3-D unit square/cube, p in 2..5, h in 1/32..1/256, freq 1..4, "
+                               "Poisson arrivals", "seed": args.seed, "slots": args.slots,
+                   "budget_GB": args.serve_budget_gb, "class_limit_GB": args.serve_budget_gb / 8,
+                   "classes_admitted": len(admitted), "classes_rejected": len(classes) - len(admitted),
+                   "setup_s": round(t_setup, 1), "tol": 1e-10},
+        "open_loop": open_loop,
+        "closed_loop_requests": len(idx),
+        "served_solves_per_s": served,
+        "plain_fp64_single_solves_per_s": plain64,
+        "mixed_single_solves_per_s": mixed1,
+        "server_stats": stats,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +224,14 @@ def main():
     ap.add_argument("--dim", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--serve", action="store_true", help="continuous-batching serving benchmark")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--closed-requests", type=int, default=600)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 512 MiB (3 times), the reference for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -118,6 +245,9 @@ def main():
     import paper_1901_01685_amd as pmg
 
     dev = torch.device("cuda:0")
+    if args.serve:
+        serve_bench(args)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 26, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

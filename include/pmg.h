@@ -233,6 +233,70 @@ const char *pmg_status_str(pmg_status s);
 /* Detail of the last error on the calling thread ("" if none). */
 const char *pmg_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Request server: many Poisson solves of different classes (dim, degree,
+ * n_elem, geometry) on one device, with continuous batching.  Each class's
+ * operators and ILUT factors are set up once and stay resident while the
+ * device-memory budget allows (least recently used idle classes are evicted).
+ * A scheduler thread admits queued requests into slots as slots and memory
+ * free up and advances every active request by one outer step per tick (one
+ * FP32 V-cycle plus the FP64 residual in mixed precision, one FP64 V-cycle
+ * otherwise), each slot on its own stream, so the work of concurrent
+ * requests overlaps on the device.  Results do not depend on what else runs:
+ * every reduction has a fixed order, and each slot has its own workspace.
+ * The server object is thread-safe. */
+typedef struct pmg_server_s *pmg_server;
+
+typedef struct {
+  int64_t budget_bytes;    /* device memory for operators and slot workspaces */
+  int64_t max_class_bytes; /* classes estimated above this are rejected; 0: budget/4 */
+  int32_t max_slots;       /* requests in flight on the device */
+  int32_t precision;       /* PMG_FP32_IN_FP64 (default) or PMG_FP64 */
+  double tol;              /* relative FP64 residual target, default 1e-10 */
+  int32_t max_iter;        /* outer steps per request, default 100 */
+  int32_t device;          /* HIP device ordinal */
+  int32_t setup_threads;   /* host threads per class setup; 0 = default */
+} pmg_server_options;
+
+typedef struct {
+  int32_t status;     /* pmg_status of the solve */
+  int32_t iterations; /* outer steps (V-cycles) */
+  double relres;      /* final ||b - A x|| / ||b - A x0||, FP64, x0 = 0 */
+  double t_submit, t_admit, t_finish; /* seconds on the server clock */
+  int64_t n;          /* unknowns */
+} pmg_request_info;
+
+typedef struct {
+  int64_t submitted, completed, rejected, failed, evictions;
+  int32_t classes_resident, slots_active, queued;
+  int64_t bytes_in_use;
+  double setup_seconds; /* total host setup time of all classes so far */
+} pmg_server_stats;
+
+pmg_status pmg_server_default_options(pmg_server_options *o);
+/* Starts the scheduler and setup threads.  Errors: EINVAL, EDEVICE. */
+pmg_status pmg_server_create(const pmg_server_options *o, pmg_server *out);
+/* Sets up the class of prob now (blocking) so that later requests find it
+ * resident.  EBUDGET if the class can never fit (estimate above
+ * max_class_bytes or the budget) or does not fit now. */
+pmg_status pmg_server_prepare(pmg_server s, const pmg_problem *prob);
+/* Queues one solve of prob with zero initial guess.  b_host (host, length n,
+ * copied) is the right-hand side, or NULL for the load vector of prob's
+ * rhs_kind and freq.  *ticket identifies the request.  EBUDGET at once if
+ * the class can never fit; EINVAL for an invalid problem. */
+pmg_status pmg_server_submit(pmg_server s, const pmg_problem *prob, const double *b_host, int64_t *ticket);
+/* Blocks until the request is done; copies the solution into x_host (length
+ * n) if non-NULL and its record into *info if non-NULL, then forgets the
+ * ticket.  Returns the solve status; EINVAL for an unknown ticket. */
+pmg_status pmg_server_wait(pmg_server s, int64_t ticket, double *x_host, pmg_request_info *info);
+/* Changes slots and precision; waits until no request is queued or active. */
+pmg_status pmg_server_configure(pmg_server s, int32_t max_slots, int32_t precision);
+pmg_status pmg_server_get_stats(pmg_server s, pmg_server_stats *st);
+/* Seconds since the server was created (the clock of pmg_request_info). */
+double pmg_server_clock(pmg_server s);
+/* Stops the threads (waiting for active requests) and frees everything. */
+pmg_status pmg_server_destroy(pmg_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,30 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("max_class_bytes", C.c_int64), ("max_slots", C.c_int32),
+                ("precision", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("device", C.c_int32),
+                ("setup_threads", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("relres", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_finish", C.c_double), ("n", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("failed", C.c_int64), ("evictions", C.c_int64), ("classes_resident", C.c_int32),
+                ("slots_active", C.c_int32), ("queued", C.c_int32), ("bytes_in_use", C.c_int64),
+                ("setup_seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # exported symbols and their signatures (the tests check them against include/pmg.h)
 _VP, _DP, _I64P, _I32P = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)
 SIGNATURES = {
@@ -87,6 +111,15 @@ SIGNATURES = {
     "pmg_export": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _I64P, _I32P, _DP]),
     "pmg_export_vec": (C.c_int, [_VP, C.c_int32, _DP]),
     "pmg_export_perm": (C.c_int, [_VP, _I32P]),
+    "pmg_server_default_options": (C.c_int, [C.POINTER(ServerOptions)]),
+    "pmg_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(_VP)]),
+    "pmg_server_prepare": (C.c_int, [_VP, C.POINTER(Problem)]),
+    "pmg_server_submit": (C.c_int, [_VP, C.POINTER(Problem), _DP, _I64P]),
+    "pmg_server_wait": (C.c_int, [_VP, C.c_int64, _DP, C.POINTER(RequestInfo)]),
+    "pmg_server_configure": (C.c_int, [_VP, C.c_int32, C.c_int32]),
+    "pmg_server_get_stats": (C.c_int, [_VP, C.POINTER(ServerStats)]),
+    "pmg_server_clock": (C.c_double, [_VP]),
+    "pmg_server_destroy": (C.c_int, [_VP]),
     "pmg_status_str": (C.c_char_p, [C.c_int]),
     "pmg_last_error": (C.c_char_p, []),
 }
@@ -260,3 +293,72 @@ class Solver:
         out = np.zeros(max(n, 1))
         _check(lib().pmg_export_vec(self._h, which, out.ctypes.data_as(_DP)))
         return out[:n]
+
+
+class Server:
+    """Continuous-batching request server (pmg_server_*): requests of any class
+    are queued, admitted into device slots as slots and memory free up, and
+    advanced one outer step per scheduler tick until they converge."""
+
+    def __init__(self, **opts):
+        o = ServerOptions()
+        _check(lib().pmg_server_default_options(C.byref(o)))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise AttributeError(k)
+            setattr(o, k, v)
+        self.options = o
+        h = C.c_void_p()
+        _check(lib().pmg_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pmg_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, dim, degree, n_elem, geometry=GEOM_BOX):
+        """Sets up a class ahead of requests; returns the status (EBUDGET if rejected)."""
+        pr = make_problem(dim, degree, n_elem, geometry, RHS_SINE, (1, 1, 1))
+        return lib().pmg_server_prepare(self._h, C.byref(pr))
+
+    def submit(self, dim, degree, n_elem, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1), b=None):
+        """Queues a solve; returns (status, ticket)."""
+        pr = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq)
+        t = C.c_int64(-1)
+        bp = None
+        if b is not None:
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            bp = b.ctypes.data_as(_DP)
+        st = lib().pmg_server_submit(self._h, C.byref(pr), bp, C.byref(t))
+        if st == OK:
+            self._n[t.value] = (n_elem + degree - 2) ** dim
+        return st, t.value
+
+    def wait(self, ticket, want_x=True):
+        """Blocks until the request is done; returns (status, info dict, x or None)."""
+        n = self._n.pop(ticket, None)
+        if n is None:
+            raise KeyError(ticket)
+        x = np.zeros(n) if want_x else None
+        info = RequestInfo()
+        st = lib().pmg_server_wait(self._h, ticket, x.ctypes.data_as(_DP) if want_x else None, C.byref(info))
+        return st, info.as_dict(), x
+
+    def configure(self, max_slots, precision):
+        _check(lib().pmg_server_configure(self._h, max_slots, precision))
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().pmg_server_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def clock(self):
+        return lib().pmg_server_clock(self._h)

@@ -24,10 +24,11 @@ __device__ __forceinline__ T group_sum(T v, int G) {
   return v;
 }
 
-// CSR kernel with G lanes per row (G divides 64), 256 threads per block.
-// Consecutive lanes of a group read consecutive non-zeros (coalesced); x is
-// gathered through the caches.  Per-row sums are reduced in a fixed tree, so
-// results are bit-reproducible from run to run.
+// CSR kernel with G lanes per row (G divides 64), 256 threads per block,
+// grid-stride over row groups (the grid is capped, so a residual produces at
+// most one partial sum per block).  Consecutive lanes of a group read
+// consecutive non-zeros (coalesced); x is gathered through the caches.  Row
+// sums are reduced in a fixed tree, so results are bit-reproducible.
 template <typename T, int G, int MODE>
 __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restrict__ rows,
                                                   const int* __restrict__ rp, const int* __restrict__ ci,
@@ -37,12 +38,11 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
   const int tid = threadIdx.x;
   const int g = tid / G, l = tid % G;
   const int rpb = 256 / G;
-  const int idx = blockIdx.x * rpb + g;
-  T acc = 0, diag = 0;
-  int row = -1;
-  if (idx < nrows) {
-    row = rows ? rows[idx] : idx;
+  double sq = 0.0;
+  for (int idx = blockIdx.x * rpb + g; idx < nrows; idx += gridDim.x * rpb) {
+    const int row = rows ? rows[idx] : idx;
     const int k0 = rp[row], k1 = rp[row + 1];
+    T acc = 0, diag = 0;
     for (int k = k0 + l; k < k1; k += G) {
       const int c = ci[k];
       const T a = v[k];
@@ -56,29 +56,29 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
         acc += a * x[c];
       }
     }
-  }
-  acc = group_sum(acc, G);
-  if (MODE == kGS) diag = group_sum(diag, G);
-  T res = 0;
-  if (idx < nrows && l == 0) {
-    if (MODE == kResid) {
-      res = b[row] - acc;
-      out[row] = res;
-    } else if (MODE == kPlain) {
-      out[row] = acc;
-    } else if (MODE == kScale) {
-      out[row] = d[row] * acc;
-    } else if (MODE == kScaleAdd) {
-      out[row] = out[row] + d[row] * acc;
-    } else if (MODE == kAdd) {
-      out[row] = out[row] + acc;
-    } else if (MODE == kGS) {
-      out[row] = (b[row] - acc) / diag;
+    acc = group_sum(acc, G);
+    if (MODE == kGS) diag = group_sum(diag, G);
+    if (l == 0) {
+      if (MODE == kResid) {
+        const T res = b[row] - acc;
+        out[row] = res;
+        sq += (double)res * (double)res;
+      } else if (MODE == kPlain) {
+        out[row] = acc;
+      } else if (MODE == kScale) {
+        out[row] = d[row] * acc;
+      } else if (MODE == kScaleAdd) {
+        out[row] = out[row] + d[row] * acc;
+      } else if (MODE == kAdd) {
+        out[row] = out[row] + acc;
+      } else if (MODE == kGS) {
+        out[row] = (b[row] - acc) / diag;
+      }
     }
   }
   if (MODE == kResid) {
     __shared__ double red[256];
-    red[tid] = (l == 0 && idx < nrows) ? (double)res * (double)res : 0.0;
+    red[tid] = sq;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
       if (tid < s) red[tid] += red[tid + s];
@@ -107,12 +107,6 @@ template <typename T>
 __global__ void fill_kernel(int64_t n, T* __restrict__ y, T val) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) y[i] = val;
-}
-
-__global__ void reset_ints(int n, int* __restrict__ a, int m, int* __restrict__ b) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = 0;
-  if (i < m) b[i] = 0;
 }
 
 template <typename TI, typename TO>

@@ -17,47 +17,47 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/pmg.h"
 #include "kernels.hpp"
-#include "pmg_host.hpp"
+#include "pmg_internal.hpp"
 
-namespace {
+using pmgdev::DevMat;
+using pmgdev::TriSched;
+using pmgdev::Workspace;
+using pmgdev::fail;
 
-thread_local std::string g_last_error;
+namespace pmgdev {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
 
 pmg_status fail(pmg_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
 
-#define HIP_OK(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess) {                                                              \
-      g_last_error = std::string(#call) + ": " + hipGetErrorString(e_);                  \
-      return e_ == hipErrorOutOfMemory ? PMG_ENOMEM : PMG_EDEVICE;                       \
-    }                                                                                    \
-  } while (0)
+pmg_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? PMG_ENOMEM : PMG_EDEVICE;
+}
 
-struct DevMat {
-  int nrows = 0, ncols = 0;
-  int64_t nnz = 0;
-  int* rp = nullptr;
-  int* ci = nullptr;
-  double* v = nullptr;
-  float* v32 = nullptr;
-  int G = 8;
-};
+const char* last_error_cstr() { return g_last_error.c_str(); }
 
-struct TriSched {
-  int nseg = 0, seg_len = 0, nch = 0, nwaits = 0, dag_levels = 0;
-  std::vector<int> wptr;
-  std::vector<int2> waits;
-  std::vector<int> ks;  // per row: split between in-chunk and off-chunk entries
-  int* d_wptr = nullptr;
-  int2* d_waits = nullptr;
-  int* d_ks = nullptr;
-};
+}  // namespace pmgdev
+
+pmg_handle_s::~pmg_handle_s() {
+  if (on_device) {
+    hipSetDevice(device);
+    hipDeviceSynchronize();
+    ops.release();
+    for (auto& v : ev)
+      for (hipEvent_t e : v) hipEventDestroy(e);
+  }
+}
+
+namespace {
+
+constexpr int kMaxCsrBlocks = 4096;
 
 int pick_group(double avg) {
   if (avg >= 128) return 64;
@@ -66,6 +66,10 @@ int pick_group(double avg) {
   if (avg >= 8) return 8;
   return 4;
 }
+
+unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+unsigned csr_grid(int nrows, int G) { return std::min<unsigned>(nblocks(nrows, 256 / G), kMaxCsrBlocks); }
 
 // Wait lists of the segment-ordered triangular solves.  Forward: chunk
 // (s, c) reads rows of segments < s; for each such segment the number of its
@@ -142,108 +146,23 @@ void build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
   S.dag_levels = mx;
 }
 
-}  // namespace
-
-struct pmg_handle_s {
-  pmg_problem prob{};
-  pmg_options opt{};
-  pmg::HostOps H;
-  int device = -1;
-  bool on_device = false;
-  int colors = 4;
-  DevMat A, L, U, R, P;
-  std::vector<DevMat> A1, Ph, Rh;
-  std::vector<std::vector<int*>> color_rows;
-  std::vector<std::vector<int>> color_cnt;
-  double *f = nullptr, *mlp_inv = nullptr, *ml1_inv = nullptr, *coarse_inv = nullptr;
-  float *mlp_inv32 = nullptr, *ml1_inv32 = nullptr;
-  TriSched tl, tu;
-  int *prog_l = nullptr, *prog_u = nullptr;
-  int* d_perm = nullptr;
-  unsigned* tickets = nullptr;  // lower: [0] ticket, [1] finished; upper: [2], [3]
-  // work
-  double *y = nullptr, *r = nullptr, *r1 = nullptr, *e1 = nullptr, *partial = nullptr,
-         *scalar = nullptr;
-  double* host_scalar = nullptr;  // pinned
-  std::vector<double*> hb, he, hr;
-  int partial_cap = 0;
-  // mixed precision work
-  float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *t32 = nullptr, *q32 = nullptr;
-  size_t dev_bytes = 0;
-  std::vector<void*> allocs;
-  pmg_info info{};
-  // per-step event timing
-  bool profiling = false;
-  std::vector<hipEvent_t> ev[PMG_PROF_NCLASS];  // start/stop pairs
-  size_t ev_used[PMG_PROF_NCLASS] = {};
-  void prof_mark(int cls, hipStream_t st, bool start) {
-    auto& v = ev[cls];
-    size_t& u = ev_used[cls];
-    if (u >= v.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return;
-      v.push_back(e);
-    }
-    hipEventRecord(v[u], st);
-    ++u;
-    (void)start;
+pmg_status upload_mat(pmgdev::DevArena& mem, const pmg::Csr& M, DevMat& D, bool with32) {
+  D.nrows = M.nrows;
+  D.ncols = M.ncols;
+  D.nnz = M.nnz();
+  if (D.nnz >= (int64_t)INT32_MAX) return fail(PMG_EINVAL, "operator has more than 2^31 non-zeros");
+  std::vector<int> rp32(M.rp.begin(), M.rp.end());
+  pmg_status s;
+  if ((s = mem.upload(&D.rp, rp32.data(), rp32.size()))) return s;
+  if ((s = mem.upload(&D.ci, M.ci.data(), M.ci.size()))) return s;
+  if ((s = mem.upload(&D.v, M.v.data(), M.v.size()))) return s;
+  if (with32) {
+    std::vector<float> v32(M.v.begin(), M.v.end());
+    if ((s = mem.upload(&D.v32, v32.data(), v32.size()))) return s;
   }
-
-  template <typename T>
-  pmg_status dalloc(T** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-    if (e != hipSuccess) {
-      g_last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
-      return PMG_ENOMEM;
-    }
-    allocs.push_back(*p);
-    dev_bytes += count * sizeof(T);
-    return PMG_OK;
-  }
-
-  template <typename T>
-  pmg_status upload(T** p, const T* src, size_t count) {
-    pmg_status s = dalloc(p, count);
-    if (s) return s;
-    if (count) HIP_OK(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
-    return PMG_OK;
-  }
-
-  pmg_status upload_mat(const pmg::Csr& M, DevMat& D, bool with32) {
-    D.nrows = M.nrows;
-    D.ncols = M.ncols;
-    D.nnz = M.nnz();
-    if (D.nnz >= (int64_t)INT32_MAX) return fail(PMG_EINVAL, "operator has more than 2^31 non-zeros");
-    std::vector<int> rp32(M.rp.begin(), M.rp.end());
-    pmg_status s;
-    if ((s = upload(&D.rp, rp32.data(), rp32.size()))) return s;
-    if ((s = upload(&D.ci, M.ci.data(), M.ci.size()))) return s;
-    if ((s = upload(&D.v, M.v.data(), M.v.size()))) return s;
-    if (with32) {
-      std::vector<float> v32(M.v.begin(), M.v.end());
-      if ((s = upload(&D.v32, v32.data(), v32.size()))) return s;
-    }
-    D.G = pick_group(D.nrows ? (double)D.nnz / D.nrows : 1.0);
-    return PMG_OK;
-  }
-
-  ~pmg_handle_s() {
-    if (on_device) {
-      hipSetDevice(device);
-      hipDeviceSynchronize();
-      for (void* p : allocs) hipFree(p);
-      for (auto& v : ev)
-        for (hipEvent_t e : v) hipEventDestroy(e);
-      if (host_scalar) hipHostFree(host_scalar);
-    }
-  }
-};
-
-namespace {
-
-unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+  D.G = pick_group(D.nrows ? (double)D.nnz / D.nrows : 1.0);
+  return PMG_OK;
+}
 
 // Per-step timing with HIP events on the launch stream (pmg_profile_*).
 struct ProfScope {
@@ -251,10 +170,10 @@ struct ProfScope {
   int cls;
   hipStream_t st;
   ProfScope(pmg_handle h_, int c, hipStream_t s) : h(h_), cls(c), st(s) {
-    if (h->profiling) h->prof_mark(cls, st, true);
+    if (h->profiling) h->prof_mark(cls, st);
   }
   ~ProfScope() {
-    if (h->profiling) h->prof_mark(cls, st, false);
+    if (h->profiling) h->prof_mark(cls, st);
   }
 };
 
@@ -262,8 +181,8 @@ struct ProfScope {
 template <typename T, int G>
 void csr_launch_g(int mode, int nrows, const int* rows, const DevMat& M, const T* v, const T* x,
                   const T* b, const T* d, T* out, double* partial, hipStream_t st) {
-  const unsigned grid = nblocks(nrows, 256 / G);
-  if (grid == 0) return;
+  if (nrows <= 0) return;
+  const unsigned grid = csr_grid(nrows, G);
   switch (mode) {
     case pmg::kResid:
       pmg::csr_kernel<T, G, pmg::kResid><<<grid, 256, 0, st>>>(nrows, rows, M.rp, M.ci, v, x, b, d, out, partial);
@@ -303,44 +222,34 @@ void fill(T* p, int64_t n, T val, hipStream_t st) {
   if (n > 0) pmg::fill_kernel<T><<<nblocks(n, 256), 256, 0, st>>>(n, p, val);
 }
 
-// r = b - A x; if norm_out != nullptr, ||r||_2 lands in h->scalar (device).
-void residual64(pmg_handle h, const double* b, const double* x, double* r, bool norm, hipStream_t st) {
-  ProfScope ps(h, PMG_PROF_RESIDUAL, st);
-  csr_launch<double>(pmg::kResid, h->A.nrows, nullptr, h->A, h->A.v, x, b, nullptr, r, h->partial, st);
-  if (norm) {
-    const int nb = (int)nblocks(h->A.nrows, 256 / h->A.G);
-    pmg::reduce_partials<<<1, 256, 0, st>>>(nb, h->partial, h->scalar);
-  }
-}
-
-double read_norm(pmg_handle h, hipStream_t st) {
-  hipMemcpyAsync(h->host_scalar, h->scalar, sizeof(double), hipMemcpyDeviceToHost, st);
+double read_norm(Workspace& ws, hipStream_t st) {
+  pmgdev::enqueue_norm_readback(ws, st);
   hipStreamSynchronize(st);
-  return std::sqrt(h->host_scalar[0]);
+  return std::sqrt(ws.host_scalar[0]);
 }
 
 template <typename T>
-void lower_impl(pmg_handle h, const T* r, T* y, bool fp32, hipStream_t st) {
+void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, bool fp32, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_LOWER, st);
   const T* lv = fp32 ? (const T*)h->L.v32 : (const T*)h->L.v;
-  pmg::trisolve_lower<T><<<h->tl.nseg, 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, h->L.rp, h->L.ci, lv,
-                                                     h->tl.d_ks, h->d_perm, r, y, h->tl.d_wptr, h->tl.d_waits,
-                                                     h->prog_l, h->tickets);
+  pmg::trisolve_lower<T><<<h->tl.nseg, 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, h->L.rp, h->L.ci, lv, h->tl.d_ks,
+                                                     h->d_perm, r, y, h->tl.d_wptr, h->tl.d_waits, ws.prog_l,
+                                                     ws.tickets);
 }
 
 template <typename T>
-void upper_impl(pmg_handle h, T* y, T* x, bool fp32, hipStream_t st) {
+void upper_impl(pmg_handle h, Workspace& ws, T* y, T* x, bool fp32, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_UPPER, st);
   const T* uv = fp32 ? (const T*)h->U.v32 : (const T*)h->U.v;
-  pmg::trisolve_upper<T><<<h->tu.nseg, 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, h->U.rp, h->U.ci, uv,
-                                                     h->tu.d_ks, h->d_perm, y, x, h->tu.d_wptr, h->tu.d_waits,
-                                                     h->prog_u, h->tickets + 2);
+  pmg::trisolve_upper<T><<<h->tu.nseg, 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, h->U.rp, h->U.ci, uv, h->tu.d_ks,
+                                                     h->d_perm, y, x, h->tu.d_wptr, h->tu.d_waits, ws.prog_u,
+                                                     ws.tickets + 2);
 }
 
 template <typename T>
-void smooth_impl(pmg_handle h, const T* r, T* x, T* y, bool fp32, hipStream_t st) {
-  lower_impl<T>(h, r, y, fp32, st);
-  upper_impl<T>(h, y, x, fp32, st);
+void smooth_impl(pmg_handle h, Workspace& ws, const T* r, T* x, T* y, bool fp32, hipStream_t st) {
+  lower_impl<T>(h, ws, r, y, fp32, st);
+  upper_impl<T>(h, ws, y, x, fp32, st);
 }
 
 void gs_sweeps(pmg_handle h, int l, const double* b, double* e, int nsweep, hipStream_t st) {
@@ -350,30 +259,30 @@ void gs_sweeps(pmg_handle h, int l, const double* b, double* e, int nsweep, hipS
                          nullptr, e, nullptr, st);
 }
 
-void hcycle(pmg_handle h, int l, const double* b, double* e, hipStream_t st) {
+void hcycle(pmg_handle h, Workspace& ws, int l, const double* b, double* e, hipStream_t st) {
   const pmg::HostOps& H = h->H;
   if (l == H.nlev - 1) {
     pmg::dense_matvec<<<1, 256, 0, st>>>(H.n_coarse, h->coarse_inv, b, e);
     return;
   }
   gs_sweeps(h, l, b, e, h->opt.nu1, st);
-  double* r = h->hr[l];
-  csr_launch<double>(pmg::kResid, h->A1[l].nrows, nullptr, h->A1[l], h->A1[l].v, e, b, nullptr, r, h->partial, st);
-  double* bc = h->hb[l + 1];
-  double* ec = h->he[l + 1];
+  double* r = ws.hr[l];
+  csr_launch<double>(pmg::kResid, h->A1[l].nrows, nullptr, h->A1[l], h->A1[l].v, e, b, nullptr, r, ws.partial, st);
+  double* bc = ws.hb[l + 1];
+  double* ec = ws.he[l + 1];
   csr_launch<double>(pmg::kPlain, h->Rh[l].nrows, nullptr, h->Rh[l], h->Rh[l].v, r, nullptr, nullptr, bc, nullptr,
                      st);
   fill<double>(ec, H.ln[l + 1], 0.0, st);
-  hcycle(h, l + 1, bc, ec, st);
+  hcycle(h, ws, l + 1, bc, ec, st);
   csr_launch<double>(pmg::kAdd, h->Ph[l].nrows, nullptr, h->Ph[l], h->Ph[l].v, ec, nullptr, nullptr, e, nullptr,
                      st);
   gs_sweeps(h, l, b, e, h->opt.nu2, st);
 }
 
-void coarse_impl(pmg_handle h, const double* r1, double* e1, hipStream_t st) {
+void coarse_impl(pmg_handle h, Workspace& ws, const double* r1, double* e1, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_COARSE, st);
   fill<double>(e1, h->H.n1, 0.0, st);
-  for (int c = 0; c < h->opt.coarse_cycles; ++c) hcycle(h, 0, r1, e1, st);
+  for (int c = 0; c < h->opt.coarse_cycles; ++c) hcycle(h, ws, 0, r1, e1, st);
 }
 
 void restrict64(pmg_handle h, const double* r, double* r1, hipStream_t st) {
@@ -386,56 +295,36 @@ void prolong64(pmg_handle h, const double* e1, double* x, hipStream_t st) {
   csr_launch<double>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v, e1, nullptr, h->mlp_inv, x, nullptr, st);
 }
 
-// One FP64 V-cycle; r holds b - A x on entry and exit.
-void vcycle64(pmg_handle h, const double* b, double* x, double* r, bool norm, hipStream_t st) {
-  const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
-  for (int k = 0; k < nu1; ++k) {
-    smooth_impl<double>(h, r, x, h->y, false, st);
-    residual64(h, b, x, r, false, st);
-  }
-  if (h->H.n1 > 0) {
-    restrict64(h, r, h->r1, st);
-    coarse_impl(h, h->r1, h->e1, st);
-    prolong64(h, h->e1, x, st);
-    residual64(h, b, x, r, nu2 == 0 && norm, st);
-  }
-  for (int k = 0; k < nu2; ++k) {
-    smooth_impl<double>(h, r, x, h->y, false, st);
-    residual64(h, b, x, r, k == nu2 - 1 && norm, st);
-  }
-  if (nu2 == 0 && h->H.n1 == 0) residual64(h, b, x, r, norm, st);
-}
-
 // One FP32 V-cycle on A c = r32 from c = 0 (inner step of defect
 // correction): pre-smoothing, residual, restriction, FP64 h-multigrid at
-// p = 1, prolongation, residual, post-smoothing.  Result in h->c32.
-void vcycle32(pmg_handle h, hipStream_t st) {
+// p = 1, prolongation, residual, post-smoothing.  Result in ws.c32.
+void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
   const int n = h->H.n, n1 = h->H.n1;
-  float* c = h->c32;
-  float* t = h->t32;  // inner residual r32 - A c
+  float* c = ws.c32;
+  float* t = ws.t32;  // inner residual r32 - A c
   fill<float>(c, n, 0.0f, st);
   const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
-  const float* cur = h->r32;  // residual of the correction equation at c = 0
+  const float* cur = ws.r32;  // residual of the correction equation at c = 0
   for (int k = 0; k < nu1; ++k) {
-    smooth_impl<float>(h, cur, c, h->y32, true, st);
-    csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, h->r32, nullptr, t, h->partial, st);
+    smooth_impl<float>(h, ws, cur, c, ws.y32, true, st);
+    csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
     cur = t;
   }
   if (n1 > 0) {
-    csr_launch<float>(pmg::kScale, h->R.nrows, nullptr, h->R, h->R.v32, cur, nullptr, h->ml1_inv32, h->q32,
+    csr_launch<float>(pmg::kScale, h->R.nrows, nullptr, h->R, h->R.v32, cur, nullptr, h->ml1_inv32, ws.q32,
                       nullptr, st);
-    pmg::cast_kernel<float, double><<<nblocks(n1, 256), 256, 0, st>>>(n1, h->q32, h->r1);
-    coarse_impl(h, h->r1, h->e1, st);
-    pmg::cast_kernel<double, float><<<nblocks(n1, 256), 256, 0, st>>>(n1, h->e1, h->q32);
-    csr_launch<float>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v32, h->q32, nullptr, h->mlp_inv32, c,
+    pmg::cast_kernel<float, double><<<nblocks(n1, 256), 256, 0, st>>>(n1, ws.q32, ws.r1);
+    coarse_impl(h, ws, ws.r1, ws.e1, st);
+    pmg::cast_kernel<double, float><<<nblocks(n1, 256), 256, 0, st>>>(n1, ws.e1, ws.q32);
+    csr_launch<float>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v32, ws.q32, nullptr, h->mlp_inv32, c,
                       nullptr, st);
-    csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, h->r32, nullptr, t, h->partial, st);
+    csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
     cur = t;
   }
   for (int k = 0; k < nu2; ++k) {
-    smooth_impl<float>(h, cur, c, h->y32, true, st);
+    smooth_impl<float>(h, ws, cur, c, ws.y32, true, st);
     if (k + 1 < nu2) {
-      csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, h->r32, nullptr, t, h->partial, st);
+      csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
       cur = t;
     }
   }
@@ -460,6 +349,108 @@ bool valid_problem(const pmg_problem* p, std::string& msg) {
 
 }  // namespace
 
+// ----------------------------------------------------------- shared internals
+namespace pmgdev {
+
+size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors) {
+  const pmg::HostOps& H = h->H;
+  size_t b = 8 * (2 * (size_t)H.n + 2 * (size_t)std::max(H.n1, 1)) + 8 * (size_t)h->partial_cap + 32;
+  for (int l = 0; l < H.nlev; ++l) b += 8 * (size_t)H.ln[l] * (l == 0 ? 1 : 3);
+  b += 4 * (size_t)(h->tl.nseg + h->tu.nseg + 2) + 16;
+  if (mixed) b += 4 * (4 * (size_t)H.n + (size_t)std::max(H.n1, 1));
+  if (request_vectors) b += 16 * (size_t)H.n;
+  return b;
+}
+
+void zero(double* p, int64_t n, hipStream_t st) { fill<double>(p, n, 0.0, st); }
+
+pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request_vectors, hipStream_t st) {
+  const pmg::HostOps& H = h->H;
+  const int64_t n = H.n, n1 = std::max(H.n1, 1);
+  ws.n = H.n;
+  ws.n1 = H.n1;
+  ws.mixed = mixed;
+  pmg_status s;
+  DevArena& m = ws.mem;
+  if ((s = m.alloc(&ws.y, n))) return s;
+  if ((s = m.alloc(&ws.r, n))) return s;
+  if ((s = m.alloc(&ws.r1, n1))) return s;
+  if ((s = m.alloc(&ws.e1, n1))) return s;
+  if ((s = m.alloc(&ws.partial, h->partial_cap))) return s;
+  if ((s = m.alloc(&ws.scalar, 4))) return s;
+  ws.hb.assign(H.nlev, nullptr);
+  ws.he.assign(H.nlev, nullptr);
+  ws.hr.assign(H.nlev, nullptr);
+  for (int l = 1; l < H.nlev; ++l) {
+    if ((s = m.alloc(&ws.hb[l], H.ln[l]))) return s;
+    if ((s = m.alloc(&ws.he[l], H.ln[l]))) return s;
+  }
+  for (int l = 0; l < H.nlev; ++l)
+    if ((s = m.alloc(&ws.hr[l], H.ln[l]))) return s;
+  if ((s = m.alloc(&ws.prog_l, h->tl.nseg + 1))) return s;
+  if ((s = m.alloc(&ws.prog_u, h->tu.nseg + 1))) return s;
+  if ((s = m.alloc(&ws.tickets, 4))) return s;
+  fill<int>(ws.prog_l, h->tl.nseg + 1, 0, st);
+  fill<int>(ws.prog_u, h->tu.nseg + 1, 0, st);
+  fill<unsigned>(ws.tickets, 4, 0u, st);
+  PMG_HIP_OK(hipGetLastError());
+  if (mixed) {
+    if ((s = m.alloc(&ws.r32, n))) return s;
+    if ((s = m.alloc(&ws.c32, n))) return s;
+    if ((s = m.alloc(&ws.y32, n))) return s;
+    if ((s = m.alloc(&ws.t32, n))) return s;
+    if ((s = m.alloc(&ws.q32, n1))) return s;
+  }
+  if (request_vectors) {
+    if ((s = m.alloc(&ws.b, n))) return s;
+    if ((s = m.alloc(&ws.x, n))) return s;
+  }
+  PMG_HIP_OK(hipHostMalloc((void**)&ws.host_scalar, 4 * sizeof(double), hipHostMallocDefault));
+  if (!st) PMG_HIP_OK(hipDeviceSynchronize());
+  return PMG_OK;
+}
+
+void residual64(pmg_handle h, Workspace& ws, const double* b, const double* x, double* r, bool norm,
+                hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_RESIDUAL, st);
+  csr_launch<double>(pmg::kResid, h->A.nrows, nullptr, h->A, h->A.v, x, b, nullptr, r, ws.partial, st);
+  if (norm) pmg::reduce_partials<<<1, 256, 0, st>>>((int)csr_grid(h->A.nrows, h->A.G), ws.partial, ws.scalar);
+}
+
+void enqueue_norm_readback(Workspace& ws, hipStream_t st) {
+  hipMemcpyAsync(ws.host_scalar, ws.scalar, sizeof(double), hipMemcpyDeviceToHost, st);
+}
+
+// One FP64 V-cycle; r holds b - A x on entry and exit.
+void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st) {
+  const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+  for (int k = 0; k < nu1; ++k) {
+    smooth_impl<double>(h, ws, r, x, ws.y, false, st);
+    residual64(h, ws, b, x, r, false, st);
+  }
+  if (h->H.n1 > 0) {
+    restrict64(h, r, ws.r1, st);
+    coarse_impl(h, ws, ws.r1, ws.e1, st);
+    prolong64(h, ws.e1, x, st);
+    residual64(h, ws, b, x, r, nu2 == 0 && norm, st);
+  }
+  for (int k = 0; k < nu2; ++k) {
+    smooth_impl<double>(h, ws, r, x, ws.y, false, st);
+    residual64(h, ws, b, x, r, k == nu2 - 1 && norm, st);
+  }
+  if (nu2 == 0 && h->H.n1 == 0) residual64(h, ws, b, x, r, norm, st);
+}
+
+void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st) {
+  const int n = h->H.n;
+  pmg::cast_kernel<double, float><<<nblocks(n, 256), 256, 0, st>>>(n, ws.r, ws.r32);
+  vcycle32(h, ws, st);
+  pmg::add_cast_kernel<float><<<nblocks(n, 256), 256, 0, st>>>(n, ws.c32, x);
+  residual64(h, ws, b, x, ws.r, true, st);
+}
+
+}  // namespace pmgdev
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -480,7 +471,7 @@ const char* pmg_status_str(pmg_status s) {
   return "unknown status";
 }
 
-const char* pmg_last_error(void) { return g_last_error.c_str(); }
+const char* pmg_last_error(void) { return pmgdev::last_error_cstr(); }
 
 pmg_status pmg_default_options(pmg_options* o) {
   if (!o) return fail(PMG_EINVAL, "options pointer is NULL");
@@ -504,7 +495,7 @@ pmg_status pmg_default_options(pmg_options* o) {
 }
 
 pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle* out) {
-  g_last_error.clear();
+  pmgdev::set_error("");
   if (!out) return fail(PMG_EINVAL, "out pointer is NULL");
   *out = nullptr;
   std::string msg;
@@ -538,9 +529,6 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   int rc = pmg::assemble_all(sp, h->H, msg);
   if (rc) return fail((pmg_status)rc, msg);
   pmg::HostOps& H = h->H;
-  if (H.n_coarse > 1024)
-    return fail(PMG_EINVAL, "coarsest degree-1 level has " + std::to_string(H.n_coarse) +
-                                " unknowns (limit 1024): use an even n_elem or a smaller coarse_min_elems");
   {
     auto t0 = std::chrono::steady_clock::now();
     int bad = -1;
@@ -554,6 +542,11 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   build_schedule(H.L, seg_len, false, h->tl);
   build_schedule(H.U, seg_len, true, h->tu);
   h->colors = 1 << prob->dim;
+  h->partial_cap = (int)csr_grid(H.n, pick_group((double)H.A.nnz() / std::max(H.n, 1))) + 16;
+  for (int l = 0; l < H.nlev; ++l) {
+    const int G1 = pick_group((double)H.A1[l].nnz() / std::max(H.ln[l], 1));
+    h->partial_cap = std::max(h->partial_cap, (int)csr_grid(H.ln[l], G1) + 16);
+  }
 
   // info
   pmg_info& I = h->info;
@@ -601,26 +594,27 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= o.device)
       return fail(PMG_EDEVICE, "no HIP device " + std::to_string(o.device));
-    HIP_OK(hipSetDevice(o.device));
+    PMG_HIP_OK(hipSetDevice(o.device));
     h->device = o.device;
     h->on_device = true;
     const bool mixed = o.precision == PMG_FP32_IN_FP64;
+    pmgdev::DevArena& m = h->ops;
     pmg_status s;
-    if ((s = h->upload_mat(H.A, h->A, mixed))) return s;
-    if ((s = h->upload_mat(H.L, h->L, mixed))) return s;
-    if ((s = h->upload_mat(H.U, h->U, mixed))) return s;
+    if ((s = upload_mat(m, H.A, h->A, mixed))) return s;
+    if ((s = upload_mat(m, H.L, h->L, mixed))) return s;
+    if ((s = upload_mat(m, H.U, h->U, mixed))) return s;
     if (n1 > 0) {
-      if ((s = h->upload_mat(H.R, h->R, mixed))) return s;
-      if ((s = h->upload_mat(H.P, h->P, mixed))) return s;
+      if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
+      if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
     }
     h->A1.resize(H.nlev);
     h->Ph.resize(H.Ph.size());
     h->Rh.resize(H.Rh.size());
     for (int l = 0; l < H.nlev; ++l)
-      if ((s = h->upload_mat(H.A1[l], h->A1[l], false))) return s;
+      if ((s = upload_mat(m, H.A1[l], h->A1[l], false))) return s;
     for (size_t l = 0; l < H.Ph.size(); ++l) {
-      if ((s = h->upload_mat(H.Ph[l], h->Ph[l], false))) return s;
-      if ((s = h->upload_mat(H.Rh[l], h->Rh[l], false))) return s;
+      if ((s = upload_mat(m, H.Ph[l], h->Ph[l], false))) return s;
+      if ((s = upload_mat(m, H.Rh[l], h->Rh[l], false))) return s;
     }
     // multicolour row lists per level
     h->color_rows.assign(H.nlev, std::vector<int*>(h->colors, nullptr));
@@ -638,63 +632,32 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
       }
       for (int c = 0; c < h->colors; ++c) {
         h->color_cnt[l][c] = (int)lists[c].size();
-        if ((s = h->upload(&h->color_rows[l][c], lists[c].data(), lists[c].size()))) return s;
+        if ((s = m.upload(&h->color_rows[l][c], lists[c].data(), lists[c].size()))) return s;
       }
     }
     std::vector<double> inv(H.n), inv1(std::max<int64_t>(n1, 1));
     for (int64_t i = 0; i < n; ++i) inv[i] = 1.0 / H.mlp[i];
     for (int64_t i = 0; i < n1; ++i) inv1[i] = 1.0 / H.ml1[i];
-    if ((s = h->upload(&h->f, H.f.data(), H.f.size()))) return s;
-    if ((s = h->upload(&h->mlp_inv, inv.data(), inv.size()))) return s;
-    if ((s = h->upload(&h->ml1_inv, inv1.data(), inv1.size()))) return s;
-    if ((s = h->upload(&h->coarse_inv, H.coarse_inv.data(), H.coarse_inv.size()))) return s;
+    if ((s = m.upload(&h->f, H.f.data(), H.f.size()))) return s;
+    if ((s = m.upload(&h->mlp_inv, inv.data(), inv.size()))) return s;
+    if ((s = m.upload(&h->ml1_inv, inv1.data(), inv1.size()))) return s;
+    if ((s = m.upload(&h->coarse_inv, H.coarse_inv.data(), H.coarse_inv.size()))) return s;
     if (mixed) {
       std::vector<float> a(inv.begin(), inv.end()), b(inv1.begin(), inv1.end());
-      if ((s = h->upload(&h->mlp_inv32, a.data(), a.size()))) return s;
-      if ((s = h->upload(&h->ml1_inv32, b.data(), b.size()))) return s;
+      if ((s = m.upload(&h->mlp_inv32, a.data(), a.size()))) return s;
+      if ((s = m.upload(&h->ml1_inv32, b.data(), b.size()))) return s;
     }
-    if ((s = h->upload(&h->tl.d_wptr, h->tl.wptr.data(), h->tl.wptr.size()))) return s;
-    if ((s = h->upload(&h->tl.d_waits, h->tl.waits.data(), h->tl.waits.size()))) return s;
-    if ((s = h->upload(&h->tu.d_wptr, h->tu.wptr.data(), h->tu.wptr.size()))) return s;
-    if ((s = h->upload(&h->tu.d_waits, h->tu.waits.data(), h->tu.waits.size()))) return s;
-    if ((s = h->upload(&h->tl.d_ks, h->tl.ks.data(), h->tl.ks.size()))) return s;
-    if ((s = h->upload(&h->d_perm, H.perm.data(), H.perm.size()))) return s;
-    if ((s = h->upload(&h->tu.d_ks, h->tu.ks.data(), h->tu.ks.size()))) return s;
-    if ((s = h->dalloc(&h->prog_l, h->tl.nseg + 1))) return s;
-    if ((s = h->dalloc(&h->prog_u, h->tu.nseg + 1))) return s;
-    if ((s = h->dalloc(&h->tickets, 4))) return s;
-    if ((s = h->dalloc(&h->y, n))) return s;
-    if ((s = h->dalloc(&h->r, n))) return s;
-    if ((s = h->dalloc(&h->r1, n1))) return s;
-    if ((s = h->dalloc(&h->e1, n1))) return s;
-    int pc = (int)nblocks(n, 256 / h->A.G) + 16;
-    for (int l = 0; l < H.nlev; ++l) pc = std::max(pc, (int)nblocks(H.ln[l], 256 / h->A1[l].G) + 16);
-    h->partial_cap = pc;
-    if ((s = h->dalloc(&h->partial, pc))) return s;
-    if ((s = h->dalloc(&h->scalar, 4))) return s;
-    h->hb.assign(H.nlev, nullptr);
-    h->he.assign(H.nlev, nullptr);
-    h->hr.assign(H.nlev, nullptr);
-    for (int l = 1; l < H.nlev; ++l) {
-      if ((s = h->dalloc(&h->hb[l], H.ln[l]))) return s;
-      if ((s = h->dalloc(&h->he[l], H.ln[l]))) return s;
-    }
-    for (int l = 0; l < H.nlev; ++l)
-      if ((s = h->dalloc(&h->hr[l], H.ln[l]))) return s;
-    if (mixed) {
-      if ((s = h->dalloc(&h->r32, n))) return s;
-      if ((s = h->dalloc(&h->c32, n))) return s;
-      if ((s = h->dalloc(&h->y32, n))) return s;
-      if ((s = h->dalloc(&h->t32, n))) return s;
-      if ((s = h->dalloc(&h->q32, std::max<int64_t>(n1, 1)))) return s;
-    }
-    HIP_OK(hipHostMalloc((void**)&h->host_scalar, 4 * sizeof(double), hipHostMallocDefault));
-    HIP_OK(hipMemset(h->prog_l, 0, sizeof(int) * (h->tl.nseg + 1)));
-    HIP_OK(hipMemset(h->prog_u, 0, sizeof(int) * (h->tu.nseg + 1)));
-    HIP_OK(hipMemset(h->tickets, 0, sizeof(unsigned) * 4));
-    HIP_OK(hipDeviceSynchronize());
+    if ((s = m.upload(&h->tl.d_wptr, h->tl.wptr.data(), h->tl.wptr.size()))) return s;
+    if ((s = m.upload(&h->tl.d_waits, h->tl.waits.data(), h->tl.waits.size()))) return s;
+    if ((s = m.upload(&h->tu.d_wptr, h->tu.wptr.data(), h->tu.wptr.size()))) return s;
+    if ((s = m.upload(&h->tu.d_waits, h->tu.waits.data(), h->tu.waits.size()))) return s;
+    if ((s = m.upload(&h->tl.d_ks, h->tl.ks.data(), h->tl.ks.size()))) return s;
+    if ((s = m.upload(&h->tu.d_ks, h->tu.ks.data(), h->tu.ks.size()))) return s;
+    if ((s = m.upload(&h->d_perm, H.perm.data(), H.perm.size()))) return s;
+    if ((s = pmgdev::alloc_workspace(h.get(), h->ws, mixed, false))) return s;
+    PMG_HIP_OK(hipDeviceSynchronize());
     I.t_upload = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    I.device_bytes = (int64_t)h->dev_bytes;
+    I.device_bytes = (int64_t)(h->ops.bytes + h->ws.mem.bytes);
   }
   *out = h.release();
   return PMG_OK;
@@ -764,13 +727,13 @@ pmg_status pmg_export_perm(pmg_handle h, int32_t* out) {
   do {                                                                              \
     if (!(h)) return fail(PMG_EINVAL, "handle is NULL");                            \
     if (!(h)->on_device) return fail(PMG_EDEVICE, "handle was set up host-only");   \
-    HIP_OK(hipSetDevice((h)->device));                                              \
+    PMG_HIP_OK(hipSetDevice((h)->device));                                          \
   } while (0)
 
 pmg_status pmg_rhs(pmg_handle h, double* b, void* stream) {
   NEED_DEVICE(h);
   if (!b) return fail(PMG_EINVAL, "b is NULL");
-  HIP_OK(hipMemcpyAsync(b, h->f, sizeof(double) * h->H.n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  PMG_HIP_OK(hipMemcpyAsync(b, h->f, sizeof(double) * h->H.n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return PMG_OK;
 }
 
@@ -778,39 +741,39 @@ pmg_status pmg_residual(pmg_handle h, const double* b, const double* x, double* 
   NEED_DEVICE(h);
   if (!b || !x || !r) return fail(PMG_EINVAL, "NULL vector");
   hipStream_t st = (hipStream_t)stream;
-  residual64(h, b, x, r, rnorm != nullptr, st);
-  HIP_OK(hipGetLastError());
-  if (rnorm) *rnorm = read_norm(h, st);
+  pmgdev::residual64(h, h->ws, b, x, r, rnorm != nullptr, st);
+  PMG_HIP_OK(hipGetLastError());
+  if (rnorm) *rnorm = read_norm(h->ws, st);
   return PMG_OK;
 }
 
 pmg_status pmg_smooth(pmg_handle h, const double* r, double* x, void* stream) {
   NEED_DEVICE(h);
   if (!r || !x) return fail(PMG_EINVAL, "NULL vector");
-  smooth_impl<double>(h, r, x, h->y, false, (hipStream_t)stream);
-  HIP_OK(hipGetLastError());
+  smooth_impl<double>(h, h->ws, r, x, h->ws.y, false, (hipStream_t)stream);
+  PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
 
 pmg_status pmg_lower_solve(pmg_handle h, const double* r, double* y, void* stream) {
   NEED_DEVICE(h);
   if (!r || !y) return fail(PMG_EINVAL, "NULL vector");
-  lower_impl<double>(h, r, y, false, (hipStream_t)stream);
-  HIP_OK(hipGetLastError());
+  lower_impl<double>(h, h->ws, r, y, false, (hipStream_t)stream);
+  PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
 
 pmg_status pmg_upper_solve(pmg_handle h, double* y, double* x, void* stream) {
   NEED_DEVICE(h);
   if (!y || !x) return fail(PMG_EINVAL, "NULL vector");
-  upper_impl<double>(h, y, x, false, (hipStream_t)stream);
-  HIP_OK(hipGetLastError());
+  upper_impl<double>(h, h->ws, y, x, false, (hipStream_t)stream);
+  PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
 
 pmg_status pmg_profile_enable(pmg_handle h, int32_t on) {
   NEED_DEVICE(h);
-  HIP_OK(hipDeviceSynchronize());
+  PMG_HIP_OK(hipDeviceSynchronize());
   for (auto& u : h->ev_used) u = 0;
   h->profiling = on != 0;
   return PMG_OK;
@@ -823,9 +786,9 @@ pmg_status pmg_profile_read(pmg_handle h, double* ms, int64_t* count) {
     double tot = 0.0;
     const size_t pairs = h->ev_used[c] / 2;
     for (size_t i = 0; i < pairs; ++i) {
-      HIP_OK(hipEventSynchronize(h->ev[c][2 * i + 1]));
+      PMG_HIP_OK(hipEventSynchronize(h->ev[c][2 * i + 1]));
       float t = 0.0f;
-      HIP_OK(hipEventElapsedTime(&t, h->ev[c][2 * i], h->ev[c][2 * i + 1]));
+      PMG_HIP_OK(hipEventElapsedTime(&t, h->ev[c][2 * i], h->ev[c][2 * i + 1]));
       tot += t;
     }
     ms[c] = tot;
@@ -839,7 +802,7 @@ pmg_status pmg_restrict(pmg_handle h, const double* r, double* r1, void* stream)
   if (!r || !r1) return fail(PMG_EINVAL, "NULL vector");
   if (h->H.n1 == 0) return PMG_OK;
   restrict64(h, r, r1, (hipStream_t)stream);
-  HIP_OK(hipGetLastError());
+  PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
 
@@ -847,8 +810,8 @@ pmg_status pmg_coarse(pmg_handle h, const double* r1, double* e1, void* stream) 
   NEED_DEVICE(h);
   if (!r1 || !e1) return fail(PMG_EINVAL, "NULL vector");
   if (h->H.n1 == 0) return PMG_OK;
-  coarse_impl(h, r1, e1, (hipStream_t)stream);
-  HIP_OK(hipGetLastError());
+  coarse_impl(h, h->ws, r1, e1, (hipStream_t)stream);
+  PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
 
@@ -857,7 +820,7 @@ pmg_status pmg_prolong(pmg_handle h, const double* e1, double* x, void* stream) 
   if (!e1 || !x) return fail(PMG_EINVAL, "NULL vector");
   if (h->H.n1 == 0) return PMG_OK;
   prolong64(h, e1, x, (hipStream_t)stream);
-  HIP_OK(hipGetLastError());
+  PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
 
@@ -865,9 +828,9 @@ pmg_status pmg_vcycle(pmg_handle h, const double* b, double* x, double* r, doubl
   NEED_DEVICE(h);
   if (!b || !x || !r) return fail(PMG_EINVAL, "NULL vector");
   hipStream_t st = (hipStream_t)stream;
-  vcycle64(h, b, x, r, rnorm != nullptr, st);
-  HIP_OK(hipGetLastError());
-  if (rnorm) *rnorm = read_norm(h, st);
+  pmgdev::vcycle64(h, h->ws, b, x, r, rnorm != nullptr, st);
+  PMG_HIP_OK(hipGetLastError());
+  if (rnorm) *rnorm = read_norm(h->ws, st);
   return PMG_OK;
 }
 
@@ -876,12 +839,12 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
   NEED_DEVICE(h);
   if (!b || !x || !(tol >= 0)) return fail(PMG_EINVAL, "invalid argument");
   hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = h->ws;
   auto t0 = std::chrono::steady_clock::now();
   pmg_result R{};
-  const int n = h->H.n;
-  residual64(h, b, x, h->r, true, st);
-  HIP_OK(hipGetLastError());
-  const double r0 = read_norm(h, st);
+  pmgdev::residual64(h, ws, b, x, ws.r, true, st);
+  PMG_HIP_OK(hipGetLastError());
+  const double r0 = read_norm(ws, st);
   R.r0 = r0;
   R.relres = 1.0;
   if (hist) hist[0] = 1.0;
@@ -894,16 +857,12 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
   } else {
     const bool mixed = h->opt.precision == PMG_FP32_IN_FP64;
     for (int it = 1; it <= h->opt.max_iter; ++it) {
-      if (!mixed) {
-        vcycle64(h, b, x, h->r, true, st);
-      } else {
-        pmg::cast_kernel<double, float><<<nblocks(n, 256), 256, 0, st>>>(n, h->r, h->r32);
-        vcycle32(h, st);
-        pmg::add_cast_kernel<float><<<nblocks(n, 256), 256, 0, st>>>(n, h->c32, x);
-        residual64(h, b, x, h->r, true, st);
-      }
-      HIP_OK(hipGetLastError());
-      const double rel = read_norm(h, st) / r0;
+      if (!mixed)
+        pmgdev::vcycle64(h, ws, b, x, ws.r, true, st);
+      else
+        pmgdev::mixed_step(h, ws, b, x, st);
+      PMG_HIP_OK(hipGetLastError());
+      const double rel = read_norm(ws, st) / r0;
       R.iterations = it;
       R.relres = rel;
       if (hist) hist[it] = rel;
@@ -920,7 +879,7 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
   R.status = status;
   R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (res) *res = R;
-  if (status != PMG_OK) g_last_error = pmg_status_str(status);
+  if (status != PMG_OK) pmgdev::set_error(pmg_status_str(status));
   return status;
 }
 

@@ -50,6 +50,10 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // Builds everything but ILUT.  Returns 0 or a pmg_status code; msg on error.
 int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg);
 
+// Load vector f_i = int f Phi_i of the problem's right-hand side (interior
+// functions of degree sp.p), as assemble_all computes it.
+int load_vector(const SetupParams& sp, std::vector<double>& f, std::string& msg);
+
 // ILUT(tau, m) of A in its given row order; returns 0, or PMG_EZEROPIVOT with
 // the failing row in bad_row.
 int ilut_factor(const Csr& A, double tau, double fill, int mode, int threads, Csr& L, Csr& U,

@@ -1,0 +1,156 @@
+// Internal device-side structures shared by the C ABI (pmg_device.hip) and
+// the request server (pmg_serve.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pmg.h"
+#include "pmg_host.hpp"
+
+namespace pmgdev {
+
+// thread-local error detail behind pmg_last_error()
+void set_error(const std::string& msg);
+pmg_status fail(pmg_status s, const std::string& msg);
+pmg_status hip_fail(hipError_t e, const char* what);
+const char* last_error_cstr();
+
+#define PMG_HIP_OK(call)                                        \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return pmgdev::hip_fail(e_, #call);   \
+  } while (0)
+
+// Device allocations owned together and released together.
+struct DevArena {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  pmg_status alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    ptrs.push_back(*p);
+    bytes += count * sizeof(T);
+    return PMG_OK;
+  }
+  template <typename T>
+  pmg_status upload(T** p, const T* src, size_t count) {
+    pmg_status s = alloc(p, count);
+    if (s) return s;
+    if (count) PMG_HIP_OK(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return PMG_OK;
+  }
+  void release() {
+    for (void* q : ptrs) hipFree(q);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+struct DevMat {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  double* v = nullptr;
+  float* v32 = nullptr;
+  int G = 8;
+};
+
+struct TriSched {
+  int nseg = 0, seg_len = 0, nch = 0, nwaits = 0, dag_levels = 0;
+  std::vector<int> wptr;
+  std::vector<int2> waits;
+  std::vector<int> ks;  // per row: split between in-chunk and off-chunk entries
+  int* d_wptr = nullptr;
+  int2* d_waits = nullptr;
+  int* d_ks = nullptr;
+};
+
+// Everything one solve in flight writes: vectors, norm partials, the
+// triangular-solve counters.  Several workspaces may use one operator set
+// concurrently on different streams.
+struct Workspace {
+  DevArena mem;
+  int n = 0, n1 = 0;
+  double *y = nullptr, *r = nullptr, *r1 = nullptr, *e1 = nullptr, *partial = nullptr, *scalar = nullptr;
+  double *b = nullptr, *x = nullptr;  // request vectors (server slots only)
+  double* host_scalar = nullptr;      // pinned
+  std::vector<double*> hb, he, hr;
+  int* prog_l = nullptr;
+  int* prog_u = nullptr;
+  unsigned* tickets = nullptr;  // lower: [0] ticket, [1] finished; upper: [2], [3]
+  float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *t32 = nullptr, *q32 = nullptr;
+  bool mixed = false;
+  ~Workspace() {
+    mem.release();
+    if (host_scalar) hipHostFree(host_scalar);
+  }
+};
+
+}  // namespace pmgdev
+
+struct pmg_handle_s {
+  pmg_problem prob{};
+  pmg_options opt{};
+  pmg::HostOps H;
+  int device = -1;
+  bool on_device = false;
+  int colors = 4;
+  pmgdev::DevArena ops;  // operators (read-only during solves)
+  pmgdev::DevMat A, L, U, R, P;
+  std::vector<pmgdev::DevMat> A1, Ph, Rh;
+  std::vector<std::vector<int*>> color_rows;
+  std::vector<std::vector<int>> color_cnt;
+  double *f = nullptr, *mlp_inv = nullptr, *ml1_inv = nullptr, *coarse_inv = nullptr;
+  float *mlp_inv32 = nullptr, *ml1_inv32 = nullptr;
+  int* d_perm = nullptr;
+  pmgdev::TriSched tl, tu;
+  int partial_cap = 0;
+  pmgdev::Workspace ws;  // the workspace of the single-handle entry points
+  pmg_info info{};
+  // per-step event timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev[PMG_PROF_NCLASS];
+  size_t ev_used[PMG_PROF_NCLASS] = {};
+  void prof_mark(int cls, hipStream_t st) {
+    auto& v = ev[cls];
+    size_t& u = ev_used[cls];
+    if (u >= v.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      v.push_back(e);
+    }
+    hipEventRecord(v[u], st);
+    ++u;
+  }
+  ~pmg_handle_s();
+};
+
+namespace pmgdev {
+
+// Workspace for one solve on handle h (mixed: FP32 vectors as well).  Its
+// counters are cleared by a kernel on `st`; work later enqueued on `st` is
+// ordered after that (with st == nullptr the device is synchronised).
+pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request_vectors,
+                           hipStream_t st = nullptr);
+// p[0..n) = 0 on stream st
+void zero(double* p, int64_t n, hipStream_t st);
+// Bytes a workspace of h would take.
+size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors);
+
+// Solve-phase steps on stream st with workspace ws.
+void residual64(pmg_handle h, Workspace& ws, const double* b, const double* x, double* r, bool norm,
+                hipStream_t st);
+void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st);
+// One defect-correction step: r (FP64 residual, in ws.r) -> FP32 V-cycle ->
+// x += c -> r = b - A x and its norm (device scalar).
+void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st);
+// Enqueues the copy of the last norm^2 into ws.host_scalar.
+void enqueue_norm_readback(Workspace& ws, hipStream_t st);
+
+}  // namespace pmgdev

@@ -588,6 +588,37 @@ static bool dense_spd_inverse(const Csr& A, std::vector<double>& inv) {
   return true;
 }
 
+int load_vector(const SetupParams& sp, std::vector<double>& f, std::string& msg) {
+  const int dim = sp.dim, p = sp.p, nel = sp.nel;
+  const int64_t n = ipow(nel + p - 2, dim);
+  if (sp.geom == 0 && sp.rhs == 0) {
+    std::vector<std::vector<double>> sf(dim);
+    double ks = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      sf[a] = integrals_1d(p, nel, p + 1, sp.freq[a]);
+      ks += (double)sp.freq[a] * sp.freq[a];
+    }
+    const int np1 = nel + p - 2;
+    f.resize(n);
+    for (int64_t r = 0; r < n; ++r) {
+      int64_t t = r;
+      double s = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        s *= sf[a][(int)(t % np1) + 1];
+        t /= np1;
+      }
+      f[r] = M_PI * M_PI * ks * s;
+    }
+    return 0;
+  }
+  if (dim != 2) {
+    msg = "this right-hand side is two-dimensional";
+    return 1;
+  }
+  element_vectors_2d(sp.geom, sp.rhs, sp.freq, p, nel, p + 1, &f, nullptr);
+  return 0;
+}
+
 int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
   auto t0 = std::chrono::steady_clock::now();
   const int dim = sp.dim, p = sp.p, nel = sp.nel;

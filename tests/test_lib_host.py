@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return set(re.findall(r"^\s*(?:pmg_status|const char\s*\*)\s*(pmg_\w+)\s*\(", src, flags=re.M))
+    return set(re.findall(r"^\s*(?:pmg_status|double|const char\s*\*)\s*(pmg_\w+)\s*\(", src, flags=re.M))
 
 
 def test_library_exports_every_declared_symbol():
