@@ -161,7 +161,8 @@ pmg_status pmg_smooth(pmg_handle h, const double *r, double *x, void *stream);
 pmg_status pmg_lower_solve(pmg_handle h, const double *r, double *y, void *stream);
 
 /* Step a3 alone: e = U^{-1} y (backward substitution with the upper ILUT
- * factor), written over y, and x <- x + e.  y, x device, length n. */
+ * factor), written over y, and x <- x + P^T e (P the ILUT ordering).  y, x
+ * device, length n. */
 pmg_status pmg_upper_solve(pmg_handle h, double *y, double *x, void *stream);
 
 /* Step a4: r1 = (M_1^L)^{-1} P_p^1 r (lumped L2 restriction, Section 3). */
@@ -209,6 +210,17 @@ pmg_status pmg_export_vec(pmg_handle h, int32_t which, double *out);
 
 /* The ILUT ordering: out[i] = unknown placed at position i (length n). */
 pmg_status pmg_export_perm(pmg_handle h, int32_t *out);
+
+/* Host copies of the schedule and chunk-sliced layout of a triangular solve
+ * (test hook; layout of each field as the kernels read it).  factor: 0 lower,
+ * 1 upper.  field: 0 chunk order (ticket -> chunk), 1 wptr and 2 waits (per
+ * chunk, pairs of segment and rows of it read), 3 off_ptr, 4 off_w,
+ * 5 off_col, 6 in_ptr, 7 in_w, 8 in_j (int32 elements), 9 off_val,
+ * 10 in_val, 11 diag (double elements; diag for the upper factor only).  *count receives the
+ * number of elements; out, when non-NULL, must hold that many.  Chunks are
+ * numbered segment * ceil(seg_len / 64) + chunk (segments and seg_len in
+ * pmg_info).  EINVAL for an unknown factor or field. */
+pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int64_t *count, void *out);
 
 /* Per-step timing with HIP events recorded on the launch stream around each
  * step of the solve phase (classes below; the coarse class spans the whole

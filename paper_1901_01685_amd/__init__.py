@@ -111,6 +111,7 @@ SIGNATURES = {
     "pmg_export": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _I64P, _I32P, _DP]),
     "pmg_export_vec": (C.c_int, [_VP, C.c_int32, _DP]),
     "pmg_export_perm": (C.c_int, [_VP, _I32P]),
+    "pmg_export_schedule": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _VP]),
     "pmg_server_default_options": (C.c_int, [C.POINTER(ServerOptions)]),
     "pmg_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(_VP)]),
     "pmg_server_prepare": (C.c_int, [_VP, C.POINTER(Problem)]),
@@ -285,6 +286,23 @@ class Solver:
     def export_perm(self):
         out = np.zeros(self.n, dtype=np.int32)
         _check(lib().pmg_export_perm(self._h, out.ctypes.data_as(_I32P)))
+        return out
+
+    SCHEDULE_FIELDS = ("order", "wptr", "waits", "off_ptr", "off_w", "off_col",
+                       "in_ptr", "in_w", "in_j", "off_val", "in_val", "diag")
+
+    def export_schedule(self, factor):
+        """Schedule and chunk-sliced layout of the lower (0) or upper (1)
+        triangular solve, as a dict of numpy arrays (waits as (k, 2))."""
+        out = {}
+        for f, name in enumerate(self.SCHEDULE_FIELDS):
+            cnt = np.zeros(1, dtype=np.int64)
+            _check(lib().pmg_export_schedule(self._h, factor, f, cnt.ctypes.data_as(_I64P), None))
+            dt = np.float64 if f >= 9 else np.int32
+            a = np.zeros(max(int(cnt[0]), 1), dtype=dt)
+            _check(lib().pmg_export_schedule(self._h, factor, f, cnt.ctypes.data_as(_I64P), a.ctypes.data_as(C.c_void_p)))
+            a = a[: int(cnt[0])]
+            out[name] = a.reshape(-1, 2) if name == "waits" else a
         return out
 
     def export_vec(self, which):

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tri_layout.hpp"
+
 namespace pmg {
 
 constexpr int kWave = 64;
@@ -141,16 +143,20 @@ __global__ __launch_bounds__(256) void dense_matvec(int n, const double* __restr
 // Sparse triangular solves with the ILUT factors (Section 3, "Smoother").
 //
 // Rows are grouped in segments (grid lines of the tensor numbering, seg_len
-// consecutive rows).  One wave owns one segment and walks it in chunks of 64
-// rows, lane = row.  Waves take segments in increasing dependency order
-// through an atomic ticket, so a wave only ever waits for segments already
-// owned by running waves (no deadlock, whatever the launch order).  Each
-// segment publishes how many of its rows are final in prog[segment].  Before
-// a chunk, the wave waits until every segment it reads from has progressed
-// far enough (precomputed (segment, rows needed) pairs per chunk), then each
-// lane accumulates its row's products with rows outside the chunk in
-// parallel, and the rows inside the chunk are finished in order, the newest
-// value broadcast from its lane.
+// consecutive rows) and segments in chunks of 64 rows, lane = row.  A grid of
+// persistent waves takes chunks through an atomic ticket in a topological
+// order of the chunk dependency graph, so a wave only ever waits for chunks
+// already owned by running waves (no deadlock, whatever the launch order or
+// the number of resident waves).
+//
+// Readiness travels with the data: the output vector starts filled with the
+// kPending marker, and a wave that reads an entry of another chunk reloads it
+// until the marker is gone.  Per chunk: the in-chunk entries are staged in
+// LDS, the off-chunk slots are gathered batch by batch (entries that are
+// final early first), then the rows inside the chunk are finished in order,
+// the newest value broadcast from its lane, and stored.  Every load of a batch
+// is issued before the first is consumed, so a chunk costs a few memory round
+// trips, and the chain from one level to the next is one store and one load.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double lane_bcast(double v, int lane) {
@@ -163,10 +169,9 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Values of y published by other waves are read and written with device-scope
-// (agent) atomic accesses: a wave may read part of a cache line of another
-// segment while the rest of that line is not final yet, and a plain load
-// could later hit that stale copy in this XCD's L2.
+// Entries written by other waves during the solve are read and written with
+// device-scope (agent) atomic accesses, which are coherent across the XCDs'
+// L2 caches: every reload sees the newest stored value.
 template <typename T>
 __device__ __forceinline__ T ld_dev(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -177,170 +182,246 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int wave_ticket(unsigned* ticket) {
-  int t = 0;
-  if ((threadIdx.x & 63) == 0) t = (int)atomicAdd(ticket, 1u);
-  return __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+__device__ __forceinline__ bool pending(double v) {
+  return (unsigned long long)__double_as_longlong(v) == kPending64;
 }
+__device__ __forceinline__ bool pending(float v) { return (unsigned)__float_as_int(v) == kPending32; }
 
-__device__ __forceinline__ void wait_chunk(const int* __restrict__ wptr, const int2* __restrict__ waits,
-                                           int chunk, int lane, int* prog) {
-  const int w0 = wptr[chunk], w1 = wptr[chunk + 1];
-  for (int w = w0 + lane; w < w1; w += kWave) {
-    const int2 pr = waits[w];
-    while (__hip_atomic_load(prog + pr.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < pr.y)
-      __builtin_amdgcn_s_sleep(1);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-__device__ __forceinline__ void publish(int* prog, int seg, int val, int lane) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (lane == 0) __hip_atomic_store(prog + seg, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Called by every wave once its segment is final.  The last wave to finish
-// clears the progress counters and the ticket for the next launch (all other
-// waves are past their last read of them), so a solve needs no separate
-// reset launch.  state[0] = ticket, state[1] = finished waves.
-__device__ __forceinline__ void finish_segment(int nseg, int* prog, unsigned* state, int lane) {
-  unsigned prev = 0;
-  if (lane == 0) prev = atomicAdd(state + 1, 1u);
-  prev = __builtin_amdgcn_readfirstlane(__shfl((int)prev, 0, 64));
-  if (prev == (unsigned)(nseg - 1)) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int i = lane; i < nseg; i += kWave) st_dev(prog + i, 0);
-    if (lane == 0) {
-      st_dev(state, 0u);
-      st_dev(state + 1, 0u);
-    }
-  }
-}
-
-// Off-chunk part of a row: t -= sum_{k in [k0, k1)} v[k] y[ci[k]], in k order,
-// with the loads issued in batches of 8 so that they are in flight together.
+// A computed value never has the marker's bits (it is a signalling NaN);
+// should one arrive anyway it is stored as the canonical quiet NaN.
 template <typename T>
-__device__ __forceinline__ T gather_sub(T t, int k0, int k1, const int* __restrict__ ci,
-                                        const T* __restrict__ v, const T* y) {
-  int k = k0;
-  for (; k + 8 <= k1; k += 8) {
-    int c[8];
-    T a[8], yy[8];
+__device__ __forceinline__ T publishable(T v) {
+  return pending(v) ? (T)__builtin_nan("") : v;
+}
+
+// Draws the next ticket for the whole wave: every lane takes part in the
+// atomic (lane 0 adds 1, the others 0) and lane 0's old value is the ticket.
+// No branch depends on the lane here: inside a loop, a lane-dependent branch
+// around the atomic followed by a cross-lane read lets the compiler send lane
+// 0 and the other lanes round different loops.
+__device__ __forceinline__ int wave_ticket(unsigned* ticket) {
+  const unsigned v = atomicAdd(ticket, (threadIdx.x & 63) == 0 ? 1u : 0u);
+  return __builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Called by every wave of the grid once it has drawn a ticket past the last
+// chunk.  The last wave to get here clears the ticket for the next launch
+// (all other waves have exited), so a solve needs no separate reset launch.
+// state[0] = ticket, state[1] = exited waves.
+__device__ __forceinline__ void finish_grid(unsigned* state, int lane) {
+  const unsigned prev = atomicAdd(state + 1, lane == 0 ? 1u : 0u);
+  if ((unsigned)__builtin_amdgcn_readfirstlane((int)prev) == gridDim.x - 1 && lane == 0) {
+    st_dev(state, 0u);
+    st_dev(state + 1, 0u);
+  }
+}
+
+// Read-only data with a wave-uniform address through the scalar cache (the
+// constant address space): such loads are counted apart from the vector
+// loads in flight, so waiting for them does not drain the gathers.
+__device__ __forceinline__ TriMeta ld_meta(const TriMeta* p) {
+  const auto* w = (const __attribute__((address_space(4))) int*)p;
+  TriMeta m;
+  m.q = w[0];
+  m.off_ptr = w[1];
+  m.off_w = w[2];
+  m.in_ptr = w[3];
+  m.in_w = w[4];
+  return m;
+}
+
+constexpr int kStage = 16;  // in-chunk slots loaded per round trip
+
+template <typename T>
+__device__ __forceinline__ void load_in(int (&jj)[kStage], T (&vv)[kStage], int u0, int w, int base, int lane,
+                                        const TriDev<T>& F) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      c[u] = ci[k + u];
-      a[u] = v[k + u];
+  for (int u = 0; u < kStage; ++u) {
+    const int i = u0 + u < w ? base + (u0 + u) * kWave + lane : F.in_pad + lane;
+    jj[u] = F.in_j[i];
+    vv[u] = F.in_val[i];
+  }
+}
+
+// Stage the in-chunk entries of this lane's row in column `lane` of the tile
+// (each lane only ever touches its own column); the first kStage slots were
+// loaded into jj/vv by the caller.  Padding slots write 0 on the diagonal,
+// which holds no entry of a strictly triangular part.
+template <typename T>
+__device__ __forceinline__ void stage_tile(T* tile, int (&jj)[kStage], T (&vv)[kStage], int base, int w,
+                                           int lane, const TriDev<T>& F) {
+#pragma unroll
+  for (int j = 0; j < kWave; ++j) tile[j * kWave + lane] = 0;
+  for (int u0 = 0;;) {
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) tile[(jj[u] >= 0 ? jj[u] : lane) * kWave + lane] = jj[u] >= 0 ? vv[u] : (T)0;
+    u0 += kStage;
+    if (u0 >= w) break;
+    load_in(jj, vv, u0, w, base, lane, F);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_batch(int (&c)[kTriBatch], T (&a)[kTriBatch], int u0, int w, int base,
+                                           int lane, const TriDev<T>& F) {
+#pragma unroll
+  for (int u = 0; u < kTriBatch; ++u) {
+    const int i = u0 + u < w ? base + (u0 + u) * kWave + lane : F.off_pad + lane;
+    c[u] = F.off_col[i];
+    a[u] = F.off_val[i];
+  }
+}
+
+// t -= sum over the off-chunk slots of this lane of val * y[col], slot by
+// slot.  Entries still holding the marker are reloaded until they are final
+// (only those lanes issue loads).  The first batch was loaded into cc/aa by
+// the caller.
+template <typename T>
+__device__ __forceinline__ T gather_off(T t, int (&cc)[kTriBatch], T (&aa)[kTriBatch], const TriMeta& m, int lane,
+                                        const TriDev<T>& F, const T* y) {
+  const T* zero = F.off_val + F.off_pad;  // padding reads a 0 here
+  for (int b = 0; b * kTriBatch < m.off_w; ++b) {
+    T yy[kTriBatch];
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u) yy[u] = ld_dev(cc[u] >= 0 ? y + cc[u] : zero);
+    int cn[kTriBatch];
+    T an[kTriBatch];
+    load_batch(cn, an, (b + 1) * kTriBatch, m.off_w, m.off_ptr, lane, F);
+    for (;;) {
+      bool nan = false;  // cheap first test: the marker is a NaN
+#pragma unroll
+      for (int u = 0; u < kTriBatch; ++u) nan |= yy[u] != yy[u];
+      if (__ballot(nan) == 0) break;
+      bool pend = false;
+#pragma unroll
+      for (int u = 0; u < kTriBatch; ++u) pend |= pending(yy[u]);
+      if (__ballot(pend) == 0) break;
+      __builtin_amdgcn_s_sleep(2);
+#pragma unroll
+      for (int u = 0; u < kTriBatch; ++u)
+        if (pending(yy[u])) yy[u] = ld_dev(y + cc[u]);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) yy[u] = ld_dev(y + c[u]);
+    for (int u = 0; u < kTriBatch; ++u) t -= aa[u] * yy[u];  // padding: 0 * 0
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t -= a[u] * yy[u];
+    for (int u = 0; u < kTriBatch; ++u) {
+      cc[u] = cn[u];
+      aa[u] = an[u];
+    }
   }
-  for (; k < k1; ++k) t -= v[k] * ld_dev(y + ci[k]);
   return t;
 }
 
-// y = L^{-1} P r, L unit lower (strict part stored, sorted columns), P the
-// ILUT ordering ((P r)_i = r[perm[i]]).  ks[row]
-// is the first entry of the row whose column lies in the row's own chunk.
-// The in-chunk entries are staged in a dense 64 x 64 LDS tile (source row j,
-// target lane) before the wait, so the ordered part touches no global memory.
+// Rows inside the chunk, first to last: after step j the value of row j
+// (lane j) is final and is subtracted, times column j of the tile, from the
+// later rows.  Lanes past the chunk's end hold zeros and change nothing.
 template <typename T>
-__global__ __launch_bounds__(64) void trisolve_lower(int nseg, int seg_len, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci, const T* __restrict__ v,
-                                                     const int* __restrict__ ks,
-                                                     const int* __restrict__ perm, const T* __restrict__ r,
-                                                     T* y, const int* __restrict__ wptr,
-                                                     const int2* __restrict__ waits, int* prog,
-                                                     unsigned* ticket) {
-  __shared__ T tile[kWave * kWave];
-  const int lane = threadIdx.x & 63;
-  const int s = wave_ticket(ticket);
-  if (s >= nseg) return;
-  const int seg0 = s * seg_len;
-  const int nch = (seg_len + kWave - 1) / kWave;
-  for (int c = 0; c < nch; ++c) {
-    const int r0 = seg0 + c * kWave;
-    const int nrow = min(kWave, seg_len - c * kWave);
-    const int row = r0 + lane;
-    const bool act = lane < nrow;
-#pragma unroll 8
-    for (int j = 0; j < kWave; ++j) tile[j * kWave + lane] = 0;
-    int k0 = 0, k1 = 0, kin = 0;
-    T t = 0;
-    if (act) {
-      k0 = rp[row];
-      k1 = rp[row + 1];
-      kin = ks[row];
-      t = r[perm[row]];
-      for (int k = kin; k < k1; ++k) tile[(ci[k] - r0) * kWave + lane] = v[k];
-    }
-    wait_chunk(wptr, waits, s * nch + c, lane, prog);
-    if (act) t = gather_sub(t, k0, kin, ci, v, y);
-    // rows inside the chunk, in order
-    for (int j = 0; j < nrow - 1; ++j) {
-      const T yj = lane_bcast(t, j);
-      t -= tile[j * kWave + lane] * yj;
-    }
-    if (act) st_dev(y + row, t);
-    publish(prog, s, c * kWave + nrow, lane);
+__device__ __forceinline__ T serial_forward(T t, const T* tile, int lane) {
+#pragma unroll
+  for (int j0 = 0; j0 < kWave; j0 += 16) {
+    T cf[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) cf[u] = tile[(j0 + u) * kWave + lane];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (j0 + u < kWave - 1) t -= cf[u] * lane_bcast(t, j0 + u);
   }
-  finish_segment(nseg, prog, ticket, lane);
+  return t;
 }
 
-// e = U^{-1} y (diagonal first in each row, then the strict upper part
-// sorted), written over y, and x += P^T e.  ks[row] is the first entry whose
-// column lies beyond the row's own chunk.
+// Rows inside the chunk, last to first, on undivided partial sums (the tile
+// holds U_ij / U_jj).
 template <typename T>
-__global__ __launch_bounds__(64) void trisolve_upper(int nseg, int seg_len, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci, const T* __restrict__ v,
-                                                     const int* __restrict__ ks,
-                                                     const int* __restrict__ perm, T* y, T* __restrict__ x,
-                                                     const int* __restrict__ wptr,
-                                                     const int2* __restrict__ waits, int* prog,
-                                                     unsigned* ticket) {
+__device__ __forceinline__ T serial_backward(T t, const T* tile, int lane) {
+#pragma unroll
+  for (int j0 = kWave - 16; j0 >= 0; j0 -= 16) {
+    T cf[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) cf[u] = tile[(j0 + u) * kWave + lane];
+#pragma unroll
+    for (int u = 15; u >= 0; --u)
+      if (j0 + u > 0) t -= cf[u] * lane_bcast(t, j0 + u);
+  }
+  return t;
+}
+
+// y = L^{-1} P r, L unit lower, P the ILUT ordering ((P r)_i = r[perm[i]]).
+// y must hold kPending in every entry at launch.
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_lower(
+    int nseg, int seg_len, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y,
+    unsigned* state) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
-  const int sr = wave_ticket(ticket);
-  if (sr >= nseg) return;
-  const int s = nseg - 1 - sr;
-  const int seg0 = s * seg_len;
   const int nch = (seg_len + kWave - 1) / kWave;
-  int done = 0;
-  for (int c = nch - 1; c >= 0; --c) {
-    const int r0 = seg0 + c * kWave;
+  const int nq = nseg * nch;
+  for (;;) {
+    const int tk = wave_ticket(state);
+    if (tk >= nq) break;
+    const TriMeta m = ld_meta(F.meta + tk);
+    const int s = m.q / nch, c = m.q - s * nch;
+    const int row = s * seg_len + c * kWave + lane;
     const int nrow = min(kWave, seg_len - c * kWave);
-    const int row = r0 + lane;
     const bool act = lane < nrow;
-#pragma unroll 8
-    for (int j = 0; j < kWave; ++j) tile[j * kWave + lane] = 0;
-    T t = 0, dg = 1;
-    int kout = 0, k1 = 0;
-    if (act) {
-      const int k0 = rp[row];
-      k1 = rp[row + 1];
-      kout = ks[row];
-      t = y[row];
-      dg = v[k0];
-      for (int k = k0 + 1; k < kout; ++k) tile[(ci[k] - r0) * kWave + lane] = v[k];
-    }
-    wait_chunk(wptr, waits, sr * nch + (nch - 1 - c), lane, prog);
-    if (act) t = gather_sub(t, kout, k1, ci, v, y);
-    // rows inside the chunk, last to first
-    T e = 0;
-    for (int j = nrow - 1; j >= 0; --j) {
-      if (lane == j) e = t / dg;
-      const T ej = lane_bcast(e, j);
-      t -= tile[j * kWave + lane] * ej;
-    }
-    if (act) {
-      st_dev(y + row, e);
-      x[perm[row]] += e;
-    }
-    done += nrow;
-    publish(prog, s, done, lane);
+    // every independent load of the chunk first
+    const int pr = perm[act ? row : row - lane];  // lanes past the end read the chunk's first row
+    int cc[kTriBatch];
+    T aa[kTriBatch];
+    load_batch(cc, aa, 0, m.off_w, m.off_ptr, lane, F);
+    int jj[kStage];
+    T vv[kStage];
+    load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F);
+    T t = r[pr];
+    t = act ? t : (T)0;
+    stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F);
+    t = gather_off(t, cc, aa, m, lane, F, y);
+    t = serial_forward(t, tile, lane);
+    if (act) st_dev(y + row, publishable(t));
   }
-  finish_segment(nseg, prog, ticket, lane);
+  finish_grid(state, lane);
+}
+
+// e = U^{-1} y (diagonal in F.diag) and x += P^T e.  e must hold kPending in
+// every entry at launch; y is only read.
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_upper(
+    int nseg, int seg_len, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ y, T* e,
+    T* __restrict__ x, unsigned* state) {
+  __shared__ T tile[kWave * kWave];
+  const int lane = threadIdx.x & 63;
+  const int nch = (seg_len + kWave - 1) / kWave;
+  const int nq = nseg * nch;
+  for (;;) {
+    const int tk = wave_ticket(state);
+    if (tk >= nq) break;
+    const TriMeta m = ld_meta(F.meta + tk);
+    const int s = m.q / nch, c = m.q - s * nch;
+    const int row = s * seg_len + c * kWave + lane;
+    const int nrow = min(kWave, seg_len - c * kWave);
+    const bool act = lane < nrow;
+    const int ra = act ? row : row - lane;  // lanes past the end read the chunk's first row
+    const T t0 = y[ra];
+    const T d0 = F.diag[ra];
+    const int pr = perm[ra];
+    int cc[kTriBatch];
+    T aa[kTriBatch];
+    load_batch(cc, aa, 0, m.off_w, m.off_ptr, lane, F);
+    int jj[kStage];
+    T vv[kStage];
+    load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F);
+    const T xv = x[pr];  // each entry of x is updated by one row only
+    stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F);
+    T t = act ? t0 : (T)0;
+    const T dg = act ? d0 : (T)1;
+    t = gather_off(t, cc, aa, m, lane, F, (const T*)e);
+    t = serial_backward(t, tile, lane);
+    const T ev = t / dg;
+    if (act) {
+      st_dev(e + row, publishable(ev));
+      x[pr] = xv + ev;
+    }
+  }
+  finish_grid(state, lane);
 }
 
 }  // namespace pmg

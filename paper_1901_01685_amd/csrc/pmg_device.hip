@@ -71,61 +71,141 @@ unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 unsigned csr_grid(int nrows, int G) { return std::min<unsigned>(nblocks(nrows, 256 / G), kMaxCsrBlocks); }
 
-// Wait lists of the segment-ordered triangular solves.  Forward: chunk
-// (s, c) reads rows of segments < s; for each such segment the number of its
-// leading rows that must be final.  Backward (upper == true): segments are
-// taken from the last, chunks from the end of the segment, and a segment's
-// progress counts rows final from its end.
-void build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
+// Schedule and chunk-sliced layout of one segment-ordered triangular solve
+// (the layout is described with pmg::TriDev).  Forward: row i reads rows
+// j < i; a segment's progress counts its leading rows that are final.
+// Backward (upper == true): row i reads rows j > i, chunks are finished from
+// the end of the segment, and progress counts rows final from its end.
+pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
   const int n = T.nrows;
   S.seg_len = seg_len;
   S.nseg = n / seg_len;
   S.nch = (seg_len + 63) / 64;
-  S.wptr.assign((size_t)S.nseg * S.nch + 1, 0);
-  S.waits.clear();
-  std::vector<int> need(S.nseg, 0), touched;
-  for (int q = 0; q < S.nseg; ++q) {
-    const int s = upper ? S.nseg - 1 - q : q;
-    for (int cc = 0; cc < S.nch; ++cc) {
-      const int c = upper ? S.nch - 1 - cc : cc;
-      const int r0 = s * seg_len + c * 64;
-      const int r1 = std::min(s * seg_len + seg_len, r0 + 64);
-      touched.clear();
-      for (int row = r0; row < r1; ++row) {
-        const int64_t kb = T.rp[row] + (upper ? 1 : 0);
-        for (int64_t k = kb; k < T.rp[row + 1]; ++k) {
-          const int col = T.ci[k];
-          const int sc = col / seg_len;
-          if (sc == s) continue;
-          const int req = upper ? (sc * seg_len + seg_len - col) : (col - sc * seg_len + 1);
-          if (need[sc] == 0) touched.push_back(sc);
-          need[sc] = std::max(need[sc], req);
+  const int nch = S.nch;
+  const int nq = S.nseg * nch;
+  S.wptr.assign((size_t)nq + 1, 0);
+  S.off_ptr.assign(nq, 0);
+  S.off_w.assign(nq, 0);
+  S.in_ptr.assign(nq, 0);
+  S.in_w.assign(nq, 0);
+  S.diag.assign(upper ? n : 0, 0.0);
+  if (upper)
+    for (int row = 0; row < n; ++row) S.diag[row] = T.v[T.rp[row]];
+  // slot counts first, so the sliced arrays are written in place below
+  for (int q = 0; q < nq; ++q) {
+    const int r0 = (q / nch) * seg_len + (q % nch) * 64;
+    const int r1 = std::min((q / nch) * seg_len + seg_len, r0 + 64);
+    int wo = 0, wi = 0;
+    for (int row = r0; row < r1; ++row) {
+      int ni = 0, no = 0;
+      for (int64_t k = T.rp[row] + (upper ? 1 : 0); k < T.rp[row + 1]; ++k)
+        (T.ci[k] >= r0 && T.ci[k] < r1) ? ++ni : ++no;
+      wo = std::max(wo, no);
+      wi = std::max(wi, ni);
+    }
+    S.off_w[q] = wo;
+    S.in_w[q] = wi;
+  }
+  int64_t no_tot = 0, ni_tot = 0;
+  for (int q = 0; q < nq; ++q) {
+    S.off_ptr[q] = (int)no_tot;
+    S.in_ptr[q] = (int)ni_tot;
+    no_tot += (int64_t)S.off_w[q] * 64;
+    ni_tot += (int64_t)S.in_w[q] * 64;
+  }
+  if (no_tot + 64 >= INT32_MAX || ni_tot + 64 >= INT32_MAX)
+    return fail(PMG_EINVAL, "triangular factor has more than 2^31 stored slots");
+  // 64 trailing padding entries each (see pmg::TriDev)
+  S.off_pad = (int)no_tot;
+  S.in_pad = (int)ni_tot;
+  S.off_col.assign(no_tot + 64, -1);
+  S.off_val.assign(no_tot + 64, 0.0);
+  S.in_j.assign(ni_tot + 64, -1);
+  S.in_val.assign(ni_tot + 64, 0.0);
+  // per chunk, in a topological order (forward: ascending q, backward:
+  // descending q): its dependencies, their levels and the sliced entries
+  std::vector<int> level(nq, 0), need(nq, 0), touched;
+  std::vector<std::vector<int2>> waits_q(nq);
+  std::vector<std::vector<int>> oc(64), ic(64);
+  auto chunk_of = [&](int col) { return (col / seg_len) * nch + (col % seg_len) / 64; };
+  for (int qq = 0; qq < nq; ++qq) {
+    const int q = upper ? nq - 1 - qq : qq;
+    const int s = q / nch, c = q % nch;
+    const int r0 = s * seg_len + c * 64;
+    const int r1 = std::min(s * seg_len + seg_len, r0 + 64);
+    touched.clear();
+    auto add_need = [&](int qd, int req) {
+      if (need[qd] == 0) touched.push_back(qd);
+      need[qd] = std::max(need[qd], req);
+    };
+    // the previous chunk of the own segment, always
+    if (!upper && c > 0) add_need(q - 1, c * 64);
+    if (upper && c < nch - 1) add_need(q + 1, seg_len - (c + 1) * 64);
+    for (int row = r0; row < r1; ++row) {
+      const int l = row - r0;
+      oc[l].clear();
+      ic[l].clear();
+      const int64_t k0 = T.rp[row] + (upper ? 1 : 0), k1 = T.rp[row + 1];
+      for (int64_t k = k0; k < k1; ++k) {
+        const int col = T.ci[k];
+        if (col >= r0 && col < r1) {
+          ic[l].push_back((int)k);
+          continue;
         }
+        oc[l].push_back((int)k);
+        const int sc = col / seg_len;
+        add_need(chunk_of(col), upper ? (sc * seg_len + seg_len - col) : (col - sc * seg_len + 1));
       }
-      std::sort(touched.begin(), touched.end());
-      for (int sc : touched) {
-        S.waits.push_back(make_int2(sc, need[sc]));
-        need[sc] = 0;
+    }
+    int lv = 0;
+    for (int qd : touched) lv = std::max(lv, level[qd]);
+    level[q] = lv + 1;
+    // dependencies sorted by level (ties: processing order)
+    auto earlier = [&](int a, int b) {
+      if (level[a] != level[b]) return level[a] < level[b];
+      return upper ? a > b : a < b;
+    };
+    std::sort(touched.begin(), touched.end(), earlier);
+    for (size_t i = 0; i < touched.size(); ++i) {
+      waits_q[q].push_back(make_int2(touched[i] / nch, need[touched[i]]));
+      need[touched[i]] = 0;
+    }
+    // slots of each row by the level of their chunk, then by column
+    for (int l = 0; l < r1 - r0; ++l)
+      std::sort(oc[l].begin(), oc[l].end(), [&](int ka, int kb) {
+        const int qa = chunk_of(T.ci[ka]), qb = chunk_of(T.ci[kb]);
+        if (qa != qb) return earlier(qa, qb);
+        return upper ? T.ci[ka] > T.ci[kb] : T.ci[ka] < T.ci[kb];
+      });
+    for (int l = 0; l < r1 - r0; ++l) {
+      for (size_t u = 0; u < oc[l].size(); ++u) {
+        const size_t o = S.off_ptr[q] + u * 64 + l;
+        S.off_col[o] = T.ci[oc[l][u]];
+        S.off_val[o] = T.v[oc[l][u]];
       }
-      S.wptr[(size_t)q * S.nch + cc + 1] = (int)S.waits.size();
+      for (size_t u = 0; u < ic[l].size(); ++u) {
+        const size_t o = S.in_ptr[q] + u * 64 + l;
+        const int col = T.ci[ic[l][u]];
+        S.in_j[o] = col - r0;
+        S.in_val[o] = upper ? T.v[ic[l][u]] / S.diag[col] : T.v[ic[l][u]];
+      }
     }
   }
+  // dependency lists by natural chunk index (they define the order; the
+  // kernels find readiness in the data)
+  S.waits.clear();
+  for (int q = 0; q < nq; ++q) {
+    S.waits.insert(S.waits.end(), waits_q[q].begin(), waits_q[q].end());
+    S.wptr[q + 1] = (int)S.waits.size();
+  }
+  // ticket order: by level, ties in processing order
+  S.order.resize(nq);
+  for (int i = 0; i < nq; ++i) S.order[i] = upper ? nq - 1 - i : i;
+  std::stable_sort(S.order.begin(), S.order.end(), [&](int a, int b) { return level[a] < level[b]; });
+  S.chunk_levels = nq ? *std::max_element(level.begin(), level.end()) : 0;
   S.nwaits = (int)S.waits.size();
-  // split index per row: lower -> first entry with column >= chunk start;
-  // upper -> first entry (after the diagonal) with column >= chunk end
-  S.ks.assign(n, 0);
-  for (int row = 0; row < n; ++row) {
-    const int s = row / seg_len, c = (row - s * seg_len) / 64;
-    const int cs = s * seg_len + c * 64, ce = std::min(s * seg_len + seg_len, cs + 64);
-    int64_t k = T.rp[row] + (upper ? 1 : 0);
-    if (!upper) {
-      while (k < T.rp[row + 1] && T.ci[k] < cs) ++k;
-    } else {
-      while (k < T.rp[row + 1] && T.ci[k] < ce) ++k;
-    }
-    S.ks[row] = (int)k;
-  }
-  // depth of the dependency DAG (for the record)
+  S.slots = (int64_t)S.off_pad;
+  // depth of the row dependency DAG (for the record)
   std::vector<int> lev(n, 0);
   int mx = 0;
   if (!upper) {
@@ -144,6 +224,7 @@ void build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
     }
   }
   S.dag_levels = mx;
+  return PMG_OK;
 }
 
 pmg_status upload_mat(pmgdev::DevArena& mem, const pmg::Csr& M, DevMat& D, bool with32) {
@@ -161,6 +242,67 @@ pmg_status upload_mat(pmgdev::DevArena& mem, const pmg::Csr& M, DevMat& D, bool 
     if ((s = mem.upload(&D.v32, v32.data(), v32.size()))) return s;
   }
   D.G = pick_group(D.nrows ? (double)D.nnz / D.nrows : 1.0);
+  return PMG_OK;
+}
+
+pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with32) {
+  pmg_status s;
+  const int nq = (int)S.order.size();
+  std::vector<pmg::TriMeta> meta(nq);
+  for (int tk = 0; tk < nq; ++tk) {
+    const int q = S.order[tk];
+    meta[tk] = pmg::TriMeta{q, S.off_ptr[q], S.off_w[q], S.in_ptr[q], S.in_w[q], {0, 0, 0}};
+  }
+  pmg::TriMeta* md;
+  int *oc, *ij;
+  double *ov, *iv, *dg = nullptr;
+  if ((s = mem.upload(&md, meta.data(), meta.size()))) return s;
+  if ((s = mem.upload(&oc, S.off_col.data(), S.off_col.size()))) return s;
+  if ((s = mem.upload(&ov, S.off_val.data(), S.off_val.size()))) return s;
+  if ((s = mem.upload(&ij, S.in_j.data(), S.in_j.size()))) return s;
+  if ((s = mem.upload(&iv, S.in_val.data(), S.in_val.size()))) return s;
+  if (upper && (s = mem.upload(&dg, S.diag.data(), S.diag.size()))) return s;
+  S.dev64 = pmg::TriDev<double>{S.off_pad, S.in_pad, md, oc, ov, ij, iv, dg};
+  if (with32) {
+    std::vector<float> a(S.off_val.begin(), S.off_val.end()), b(S.in_val.begin(), S.in_val.end()),
+        c(S.diag.begin(), S.diag.end());
+    float *ov32, *iv32, *dg32 = nullptr;
+    if ((s = mem.upload(&ov32, a.data(), a.size()))) return s;
+    if ((s = mem.upload(&iv32, b.data(), b.size()))) return s;
+    if (upper && (s = mem.upload(&dg32, c.data(), c.size()))) return s;
+    S.dev32 = pmg::TriDev<float>{S.off_pad, S.in_pad, md, oc, ov32, ij, iv32, dg32};
+  }
+  return PMG_OK;
+}
+
+template <typename T>
+const pmg::TriDev<T>& tri_dev(const TriSched& S);
+template <>
+const pmg::TriDev<double>& tri_dev<double>(const TriSched& S) { return S.dev64; }
+template <>
+const pmg::TriDev<float>& tri_dev<float>(const TriSched& S) { return S.dev32; }
+
+template <typename T>
+int tri_grid(const TriSched& S) {
+  return sizeof(T) == 8 ? S.grid64 : S.grid32;
+}
+
+// Persistent grid of the triangular solves: as many waves as fit on the
+// device at once (more would only start after others exit), at most one per
+// chunk.
+template <typename T>
+pmg_status size_tri_grid(int device, TriSched& L, TriSched& U) {
+  hipDeviceProp_t prop;
+  PMG_HIP_OK(hipGetDeviceProperties(&prop, device));
+  int per_cu_l = 0, per_cu_u = 0;
+  PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_l, pmg::trisolve_lower<T>, 64, 0));
+  PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_u, pmg::trisolve_upper<T>, 64, 0));
+  const int64_t cl = (int64_t)std::max(per_cu_l, 1) * prop.multiProcessorCount;
+  const int64_t cu = (int64_t)std::max(per_cu_u, 1) * prop.multiProcessorCount;
+  const int gl = (int)std::max<int64_t>(1, std::min<int64_t>(cl, (int64_t)L.nseg * L.nch));
+  const int gu = (int)std::max<int64_t>(1, std::min<int64_t>(cu, (int64_t)U.nseg * U.nch));
+  (sizeof(T) == 8 ? L.grid64 : L.grid32) = gl;
+  (sizeof(T) == 8 ? U.grid64 : U.grid32) = gu;
   return PMG_OK;
 }
 
@@ -228,28 +370,35 @@ double read_norm(Workspace& ws, hipStream_t st) {
   return std::sqrt(ws.host_scalar[0]);
 }
 
+// Marks every entry of a solve's output as not final (pmg::kPending).
+void fill_pending(double* p, int64_t n, hipStream_t st) {
+  fill<unsigned long long>(reinterpret_cast<unsigned long long*>(p), n, pmg::kPending64, st);
+}
+void fill_pending(float* p, int64_t n, hipStream_t st) {
+  fill<unsigned>(reinterpret_cast<unsigned*>(p), n, pmg::kPending32, st);
+}
+
 template <typename T>
-void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, bool fp32, hipStream_t st) {
+void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_LOWER, st);
-  const T* lv = fp32 ? (const T*)h->L.v32 : (const T*)h->L.v;
-  pmg::trisolve_lower<T><<<h->tl.nseg, 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, h->L.rp, h->L.ci, lv, h->tl.d_ks,
-                                                     h->d_perm, r, y, h->tl.d_wptr, h->tl.d_waits, ws.prog_l,
-                                                     ws.tickets);
+  fill_pending(y, h->H.n, st);
+  pmg::trisolve_lower<T><<<tri_grid<T>(h->tl), 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, tri_dev<T>(h->tl), h->d_perm, r, y,
+                                                             ws.tickets);
 }
 
 template <typename T>
-void upper_impl(pmg_handle h, Workspace& ws, T* y, T* x, bool fp32, hipStream_t st) {
+void upper_impl(pmg_handle h, Workspace& ws, const T* y, T* e, T* x, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_UPPER, st);
-  const T* uv = fp32 ? (const T*)h->U.v32 : (const T*)h->U.v;
-  pmg::trisolve_upper<T><<<h->tu.nseg, 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, h->U.rp, h->U.ci, uv, h->tu.d_ks,
-                                                     h->d_perm, y, x, h->tu.d_wptr, h->tu.d_waits, ws.prog_u,
-                                                     ws.tickets + 2);
+  fill_pending(e, h->H.n, st);
+  pmg::trisolve_upper<T><<<tri_grid<T>(h->tu), 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, tri_dev<T>(h->tu), h->d_perm, y, e,
+                                                             x, ws.tickets + 2);
 }
 
+// x += U^{-1} L^{-1} P r (then permuted back) with work vectors y, e.
 template <typename T>
-void smooth_impl(pmg_handle h, Workspace& ws, const T* r, T* x, T* y, bool fp32, hipStream_t st) {
-  lower_impl<T>(h, ws, r, y, fp32, st);
-  upper_impl<T>(h, ws, y, x, fp32, st);
+void smooth_impl(pmg_handle h, Workspace& ws, const T* r, T* x, T* y, T* e, hipStream_t st) {
+  lower_impl<T>(h, ws, r, y, st);
+  upper_impl<T>(h, ws, y, e, x, st);
 }
 
 void gs_sweeps(pmg_handle h, int l, const double* b, double* e, int nsweep, hipStream_t st) {
@@ -306,7 +455,7 @@ void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
   const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
   const float* cur = ws.r32;  // residual of the correction equation at c = 0
   for (int k = 0; k < nu1; ++k) {
-    smooth_impl<float>(h, ws, cur, c, ws.y32, true, st);
+    smooth_impl<float>(h, ws, cur, c, ws.y32, ws.e32, st);
     csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
     cur = t;
   }
@@ -322,7 +471,7 @@ void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
     cur = t;
   }
   for (int k = 0; k < nu2; ++k) {
-    smooth_impl<float>(h, ws, cur, c, ws.y32, true, st);
+    smooth_impl<float>(h, ws, cur, c, ws.y32, ws.e32, st);
     if (k + 1 < nu2) {
       csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
       cur = t;
@@ -354,10 +503,10 @@ namespace pmgdev {
 
 size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors) {
   const pmg::HostOps& H = h->H;
-  size_t b = 8 * (2 * (size_t)H.n + 2 * (size_t)std::max(H.n1, 1)) + 8 * (size_t)h->partial_cap + 32;
+  size_t b = 8 * (3 * (size_t)H.n + 2 * (size_t)std::max(H.n1, 1)) + 8 * (size_t)h->partial_cap + 32;
   for (int l = 0; l < H.nlev; ++l) b += 8 * (size_t)H.ln[l] * (l == 0 ? 1 : 3);
-  b += 4 * (size_t)(h->tl.nseg + h->tu.nseg + 2) + 16;
-  if (mixed) b += 4 * (4 * (size_t)H.n + (size_t)std::max(H.n1, 1));
+  b += 16;
+  if (mixed) b += 4 * (5 * (size_t)H.n + (size_t)std::max(H.n1, 1));
   if (request_vectors) b += 16 * (size_t)H.n;
   return b;
 }
@@ -373,6 +522,7 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
   pmg_status s;
   DevArena& m = ws.mem;
   if ((s = m.alloc(&ws.y, n))) return s;
+  if ((s = m.alloc(&ws.e, n))) return s;
   if ((s = m.alloc(&ws.r, n))) return s;
   if ((s = m.alloc(&ws.r1, n1))) return s;
   if ((s = m.alloc(&ws.e1, n1))) return s;
@@ -387,17 +537,14 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
   }
   for (int l = 0; l < H.nlev; ++l)
     if ((s = m.alloc(&ws.hr[l], H.ln[l]))) return s;
-  if ((s = m.alloc(&ws.prog_l, h->tl.nseg + 1))) return s;
-  if ((s = m.alloc(&ws.prog_u, h->tu.nseg + 1))) return s;
   if ((s = m.alloc(&ws.tickets, 4))) return s;
-  fill<int>(ws.prog_l, h->tl.nseg + 1, 0, st);
-  fill<int>(ws.prog_u, h->tu.nseg + 1, 0, st);
   fill<unsigned>(ws.tickets, 4, 0u, st);
   PMG_HIP_OK(hipGetLastError());
   if (mixed) {
     if ((s = m.alloc(&ws.r32, n))) return s;
     if ((s = m.alloc(&ws.c32, n))) return s;
     if ((s = m.alloc(&ws.y32, n))) return s;
+    if ((s = m.alloc(&ws.e32, n))) return s;
     if ((s = m.alloc(&ws.t32, n))) return s;
     if ((s = m.alloc(&ws.q32, n1))) return s;
   }
@@ -425,7 +572,7 @@ void enqueue_norm_readback(Workspace& ws, hipStream_t st) {
 void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st) {
   const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
   for (int k = 0; k < nu1; ++k) {
-    smooth_impl<double>(h, ws, r, x, ws.y, false, st);
+    smooth_impl<double>(h, ws, r, x, ws.y, ws.e, st);
     residual64(h, ws, b, x, r, false, st);
   }
   if (h->H.n1 > 0) {
@@ -435,7 +582,7 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
     residual64(h, ws, b, x, r, nu2 == 0 && norm, st);
   }
   for (int k = 0; k < nu2; ++k) {
-    smooth_impl<double>(h, ws, r, x, ws.y, false, st);
+    smooth_impl<double>(h, ws, r, x, ws.y, ws.e, st);
     residual64(h, ws, b, x, r, k == nu2 - 1 && norm, st);
   }
   if (nu2 == 0 && h->H.n1 == 0) residual64(h, ws, b, x, r, norm, st);
@@ -539,8 +686,11 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     if (rc) return fail(PMG_EZEROPIVOT, "ILUT: zero or non-finite pivot in row " + std::to_string(bad));
   }
   const int seg_len = prob->n_elem + prob->degree - 2;
-  build_schedule(H.L, seg_len, false, h->tl);
-  build_schedule(H.U, seg_len, true, h->tu);
+  {
+    pmg_status bs = build_schedule(H.L, seg_len, false, h->tl);
+    if (bs == PMG_OK) bs = build_schedule(H.U, seg_len, true, h->tu);
+    if (bs != PMG_OK) return bs;
+  }
   h->colors = 1 << prob->dim;
   h->partial_cap = (int)csr_grid(H.n, pick_group((double)H.A.nnz() / std::max(H.n, 1))) + 16;
   for (int l = 0; l < H.nlev; ++l) {
@@ -601,8 +751,10 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     pmgdev::DevArena& m = h->ops;
     pmg_status s;
     if ((s = upload_mat(m, H.A, h->A, mixed))) return s;
-    if ((s = upload_mat(m, H.L, h->L, mixed))) return s;
-    if ((s = upload_mat(m, H.U, h->U, mixed))) return s;
+    if ((s = upload_tri(m, h->tl, false, mixed))) return s;
+    if ((s = upload_tri(m, h->tu, true, mixed))) return s;
+    if ((s = size_tri_grid<double>(o.device, h->tl, h->tu))) return s;
+    if (mixed && (s = size_tri_grid<float>(o.device, h->tl, h->tu))) return s;
     if (n1 > 0) {
       if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
       if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
@@ -647,12 +799,6 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
       if ((s = m.upload(&h->mlp_inv32, a.data(), a.size()))) return s;
       if ((s = m.upload(&h->ml1_inv32, b.data(), b.size()))) return s;
     }
-    if ((s = m.upload(&h->tl.d_wptr, h->tl.wptr.data(), h->tl.wptr.size()))) return s;
-    if ((s = m.upload(&h->tl.d_waits, h->tl.waits.data(), h->tl.waits.size()))) return s;
-    if ((s = m.upload(&h->tu.d_wptr, h->tu.wptr.data(), h->tu.wptr.size()))) return s;
-    if ((s = m.upload(&h->tu.d_waits, h->tu.waits.data(), h->tu.waits.size()))) return s;
-    if ((s = m.upload(&h->tl.d_ks, h->tl.ks.data(), h->tl.ks.size()))) return s;
-    if ((s = m.upload(&h->tu.d_ks, h->tu.ks.data(), h->tu.ks.size()))) return s;
     if ((s = m.upload(&h->d_perm, H.perm.data(), H.perm.size()))) return s;
     if ((s = pmgdev::alloc_workspace(h.get(), h->ws, mixed, false))) return s;
     PMG_HIP_OK(hipDeviceSynchronize());
@@ -717,6 +863,40 @@ pmg_status pmg_export_vec(pmg_handle h, int32_t which, double* out) {
   return PMG_OK;
 }
 
+pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int64_t* count, void* out) {
+  if (!h || !count) return fail(PMG_EINVAL, "NULL argument");
+  if (factor != 0 && factor != 1) return fail(PMG_EINVAL, "factor must be 0 (lower) or 1 (upper)");
+  const TriSched& S = factor ? h->tu : h->tl;
+  const std::vector<int>* iv = nullptr;
+  const std::vector<double>* dv = nullptr;
+  switch (field) {
+    case 0: iv = &S.order; break;
+    case 1: iv = &S.wptr; break;
+    case 2:
+      *count = 2 * (int64_t)S.waits.size();
+      if (out) std::memcpy(out, S.waits.data(), sizeof(int2) * S.waits.size());
+      return PMG_OK;
+    case 3: iv = &S.off_ptr; break;
+    case 4: iv = &S.off_w; break;
+    case 5: iv = &S.off_col; break;
+    case 6: iv = &S.in_ptr; break;
+    case 7: iv = &S.in_w; break;
+    case 8: iv = &S.in_j; break;
+    case 9: dv = &S.off_val; break;
+    case 10: dv = &S.in_val; break;
+    case 11: dv = &S.diag; break;
+    default: return fail(PMG_EINVAL, "unknown schedule field " + std::to_string(field));
+  }
+  if (iv) {
+    *count = (int64_t)iv->size();
+    if (out) std::memcpy(out, iv->data(), sizeof(int) * iv->size());
+  } else {
+    *count = (int64_t)dv->size();
+    if (out) std::memcpy(out, dv->data(), sizeof(double) * dv->size());
+  }
+  return PMG_OK;
+}
+
 pmg_status pmg_export_perm(pmg_handle h, int32_t* out) {
   if (!h || !out) return fail(PMG_EINVAL, "NULL argument");
   std::memcpy(out, h->H.perm.data(), sizeof(int32_t) * h->H.perm.size());
@@ -750,7 +930,7 @@ pmg_status pmg_residual(pmg_handle h, const double* b, const double* x, double* 
 pmg_status pmg_smooth(pmg_handle h, const double* r, double* x, void* stream) {
   NEED_DEVICE(h);
   if (!r || !x) return fail(PMG_EINVAL, "NULL vector");
-  smooth_impl<double>(h, h->ws, r, x, h->ws.y, false, (hipStream_t)stream);
+  smooth_impl<double>(h, h->ws, r, x, h->ws.y, h->ws.e, (hipStream_t)stream);
   PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
@@ -758,7 +938,7 @@ pmg_status pmg_smooth(pmg_handle h, const double* r, double* x, void* stream) {
 pmg_status pmg_lower_solve(pmg_handle h, const double* r, double* y, void* stream) {
   NEED_DEVICE(h);
   if (!r || !y) return fail(PMG_EINVAL, "NULL vector");
-  lower_impl<double>(h, h->ws, r, y, false, (hipStream_t)stream);
+  lower_impl<double>(h, h->ws, r, y, (hipStream_t)stream);
   PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
@@ -766,7 +946,8 @@ pmg_status pmg_lower_solve(pmg_handle h, const double* r, double* y, void* strea
 pmg_status pmg_upper_solve(pmg_handle h, double* y, double* x, void* stream) {
   NEED_DEVICE(h);
   if (!y || !x) return fail(PMG_EINVAL, "NULL vector");
-  upper_impl<double>(h, h->ws, y, x, false, (hipStream_t)stream);
+  upper_impl<double>(h, h->ws, y, h->ws.e, x, (hipStream_t)stream);
+  PMG_HIP_OK(hipMemcpyAsync(y, h->ws.e, sizeof(double) * h->H.n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/pmg.h"
+#include "tri_layout.hpp"
 #include "pmg_host.hpp"
 
 namespace pmgdev {
@@ -61,14 +62,19 @@ struct DevMat {
   int G = 8;
 };
 
+// Schedule and chunk-sliced factor of one triangular solve (see TriDev).
 struct TriSched {
-  int nseg = 0, seg_len = 0, nch = 0, nwaits = 0, dag_levels = 0;
-  std::vector<int> wptr;
+  int nseg = 0, seg_len = 0, nch = 0, nwaits = 0, dag_levels = 0, chunk_levels = 0;
+  int grid64 = 1, grid32 = 1;  // persistent waves per launch (all resident)
+  // all by natural chunk index
+  std::vector<int> wptr, order;  // dependency lists; ticket -> chunk
   std::vector<int2> waits;
-  std::vector<int> ks;  // per row: split between in-chunk and off-chunk entries
-  int* d_wptr = nullptr;
-  int2* d_waits = nullptr;
-  int* d_ks = nullptr;
+  std::vector<int> off_ptr, off_w, off_col, in_ptr, in_w, in_j;
+  std::vector<double> off_val, in_val, diag;
+  int64_t slots = 0;  // stored off-chunk slots (entries + padding)
+  int off_pad = 0, in_pad = 0;  // start of the 64 padding entries
+  pmg::TriDev<double> dev64{};
+  pmg::TriDev<float> dev32{};
 };
 
 // Everything one solve in flight writes: vectors, norm partials, the
@@ -77,14 +83,14 @@ struct TriSched {
 struct Workspace {
   DevArena mem;
   int n = 0, n1 = 0;
-  double *y = nullptr, *r = nullptr, *r1 = nullptr, *e1 = nullptr, *partial = nullptr, *scalar = nullptr;
+  // y, e: outputs of the lower and upper triangular solves
+  double *y = nullptr, *e = nullptr, *r = nullptr, *r1 = nullptr, *e1 = nullptr, *partial = nullptr,
+         *scalar = nullptr;
   double *b = nullptr, *x = nullptr;  // request vectors (server slots only)
   double* host_scalar = nullptr;      // pinned
   std::vector<double*> hb, he, hr;
-  int* prog_l = nullptr;
-  int* prog_u = nullptr;
-  unsigned* tickets = nullptr;  // lower: [0] ticket, [1] finished; upper: [2], [3]
-  float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *t32 = nullptr, *q32 = nullptr;
+  unsigned* tickets = nullptr;  // lower: [0] ticket, [1] exited waves; upper: [2], [3]
+  float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *e32 = nullptr, *t32 = nullptr, *q32 = nullptr;
   bool mixed = false;
   ~Workspace() {
     mem.release();

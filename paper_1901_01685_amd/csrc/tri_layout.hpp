@@ -1,0 +1,59 @@
+// Device view of a factor in the chunk-sliced layout used by the triangular
+// solves (shared by the kernels and the host code that builds it).
+#pragma once
+
+namespace pmg {
+
+// Off-chunk slots are gathered in batches of this many per lane.
+constexpr int kTriBatch = 32;
+
+// Marker of a solution entry that is not final yet.  Before a triangular
+// solve the output vector is filled with it; a wave that needs an entry
+// reloads it until the marker is gone, so the values themselves carry the
+// readiness and no flags or fences are needed.  Both are signalling NaNs,
+// which no arithmetic produces (results are quiet NaNs at worst), and a
+// stored value with the marker's bits is replaced by the canonical quiet NaN.
+constexpr unsigned long long kPending64 = 0x7FF0DEAD0000DEADull;
+constexpr unsigned kPending32 = 0x7F80DEADu;
+
+// Factors in the chunk-sliced layout of the triangular solves.  A chunk is
+// up to 64 consecutive rows of one segment, lane = row - chunk start; q is
+// the chunk's natural index (segment * chunks per segment + chunk).  Chunks
+// are taken in a topological order of the chunk dependency graph, by level,
+// so a wave only ever waits for chunks taken before its own.
+//   Off-chunk entries: slot u of lane l at off_ptr[q] + 64 u + l for
+//   u < off_w[q], per row sorted by the level of the chunk holding the
+//   source row (ties: lower factor ascending columns, upper descending), so
+//   entries that are final early come first; padding has column -1, value 0.
+//   In-chunk entries: slot u of lane l at in_ptr[q] + 64 u + l for
+//   u < in_w[q], the position j of the source row inside the chunk (-1 for
+//   padding) and the value.  For the upper factor the value is divided by
+//   the diagonal of its column, U_ij / U_jj, so the in-chunk recurrence runs
+//   on undivided partial sums and each row is divided by its own diagonal
+//   once at the end.
+// Loads of one slot by the 64 lanes are contiguous (coalesced).  off_col /
+// off_val and in_j / in_val end with 64 padding entries (one per lane) at
+// off_pad and in_pad, which lanes without an entry load instead, so every
+// load is unconditional and its value needs no select.
+//
+// The per-chunk scalars are packed in ticket order, one 32-byte record per
+// ticket, so a wave reads all of them with one scalar load.
+struct alignas(32) TriMeta {
+  int q;               // natural chunk index
+  int off_ptr, off_w;  // off-chunk slots
+  int in_ptr, in_w;    // in-chunk slots
+  int unused[3];
+};
+
+template <typename T>
+struct TriDev {
+  int off_pad, in_pad;
+  const TriMeta* meta;  // by ticket
+  const int* off_col;
+  const T* off_val;
+  const int* in_j;
+  const T* in_val;
+  const T* diag;  // upper factor only
+};
+
+}  // namespace pmg
