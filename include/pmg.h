@@ -93,6 +93,8 @@ typedef struct {
   int32_t setup_threads;    /* host threads for setup; 0 = hardware concurrency */
   int32_t ordering;         /* ILUT permutation: PMG_ORDER_* (default nested dissection) */
   int32_t nd_leaf;          /* nested dissection: lines per undivided block (default 8) */
+  int32_t graphs;           /* 1 (default): each outer step of pmg_vcycle / pmg_solve is
+                               enqueued as a cached HIP graph; 0: kernel by kernel */
 } pmg_options;
 
 typedef struct {

@@ -588,6 +588,66 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
   if (nu2 == 0 && h->H.n1 == 0) residual64(h, ws, b, x, r, norm, st);
 }
 
+// Captures the step enqueued by `enqueue` into ws.gexec; false if capture or
+// instantiation is refused (the capture stream is left usable either way).
+template <typename F>
+bool capture_step(Workspace& ws, F&& enqueue) {
+  if (!ws.cap && hipStreamCreateWithFlags(&ws.cap, hipStreamNonBlocking) != hipSuccess) {
+    ws.cap = nullptr;
+    return false;
+  }
+  if (ws.gexec) {
+    hipGraphExecDestroy(ws.gexec);
+    ws.gexec = nullptr;
+  }
+  if (hipStreamBeginCapture(ws.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  enqueue(ws.cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ws.cap, &g);
+  if (e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    hipGetLastError();
+    return false;
+  }
+  const hipError_t ei = hipGraphInstantiate(&ws.gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    ws.gexec = nullptr;
+    hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+void outer_step(pmg_handle h, Workspace& ws, bool mixed, const double* b, double* x, double* r, bool norm,
+                hipStream_t st) {
+  auto enqueue = [&](hipStream_t s) {
+    if (mixed)
+      mixed_step(h, ws, b, x, s);
+    else
+      vcycle64(h, ws, b, x, r, norm, s);
+  };
+  if (!h->opt.graphs || h->profiling || ws.graph_failed) {
+    enqueue(st);
+    return;
+  }
+  const intptr_t kind = mixed ? 2 : (norm ? 1 : 0);
+  const void* key[5] = {h, (const void*)kind, b, x, mixed ? ws.r : r};
+  if (!ws.gexec || !std::equal(key, key + 5, ws.gkey)) {
+    if (!capture_step(ws, enqueue)) {
+      ws.graph_failed = true;
+      enqueue(st);
+      return;
+    }
+    std::copy(key, key + 5, ws.gkey);
+  }
+  if (hipGraphLaunch(ws.gexec, st) != hipSuccess) {
+    hipGetLastError();
+    ws.graph_failed = true;
+    enqueue(st);
+  }
+}
+
 void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st) {
   const int n = h->H.n;
   pmg::cast_kernel<double, float><<<nblocks(n, 256), 256, 0, st>>>(n, ws.r, ws.r32);
@@ -638,6 +698,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->setup_threads = 0;
   o->ordering = PMG_ORDER_NESTED_DISSECTION;
   o->nd_leaf = 8;
+  o->graphs = 1;
   return PMG_OK;
 }
 
@@ -1009,7 +1070,7 @@ pmg_status pmg_vcycle(pmg_handle h, const double* b, double* x, double* r, doubl
   NEED_DEVICE(h);
   if (!b || !x || !r) return fail(PMG_EINVAL, "NULL vector");
   hipStream_t st = (hipStream_t)stream;
-  pmgdev::vcycle64(h, h->ws, b, x, r, rnorm != nullptr, st);
+  pmgdev::outer_step(h, h->ws, false, b, x, r, rnorm != nullptr, st);
   PMG_HIP_OK(hipGetLastError());
   if (rnorm) *rnorm = read_norm(h->ws, st);
   return PMG_OK;
@@ -1038,10 +1099,7 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
   } else {
     const bool mixed = h->opt.precision == PMG_FP32_IN_FP64;
     for (int it = 1; it <= h->opt.max_iter; ++it) {
-      if (!mixed)
-        pmgdev::vcycle64(h, ws, b, x, ws.r, true, st);
-      else
-        pmgdev::mixed_step(h, ws, b, x, st);
+      pmgdev::outer_step(h, ws, mixed, b, x, ws.r, true, st);
       PMG_HIP_OK(hipGetLastError());
       const double rel = read_norm(ws, st) / r0;
       R.iterations = it;

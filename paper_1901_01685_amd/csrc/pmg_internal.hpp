@@ -92,7 +92,15 @@ struct Workspace {
   unsigned* tickets = nullptr;  // lower: [0] ticket, [1] exited waves; upper: [2], [3]
   float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *e32 = nullptr, *t32 = nullptr, *q32 = nullptr;
   bool mixed = false;
+  // cached graph of one outer step (outer_step), captured on `cap` and valid
+  // for the handle and vectors it was captured with
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey[5] = {};
+  bool graph_failed = false;
   ~Workspace() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (cap) hipStreamDestroy(cap);
     mem.release();
     if (host_scalar) hipHostFree(host_scalar);
   }
@@ -158,5 +166,13 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
 void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st);
 // Enqueues the copy of the last norm^2 into ws.host_scalar.
 void enqueue_norm_readback(Workspace& ws, hipStream_t st);
+// One outer step of the solve on st: the FP64 V-cycle (vcycle64 with b, x,
+// r, norm) or, with mixed, the defect-correction step (mixed_step; r is
+// ws.r and the norm is always taken).  With the handle's graphs option the
+// step's kernels are captured once into a HIP graph cached in ws (keyed by
+// the handle, the kind of step and the vectors) and replayed; while
+// profiling, or if capture fails, they are launched one by one.
+void outer_step(pmg_handle h, Workspace& ws, bool mixed, const double* b, double* x, double* r, bool norm,
+                hipStream_t st);
 
 }  // namespace pmgdev

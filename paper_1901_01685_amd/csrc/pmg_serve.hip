@@ -230,10 +230,7 @@ struct pmg_server_s {
 
   void launch_step(Slot& s) {
     pmg_handle h = s.cls->h;
-    if (precision == PMG_FP32_IN_FP64)
-      pmgdev::mixed_step(h, *s.ws, s.ws->b, s.ws->x, s.stream);
-    else
-      pmgdev::vcycle64(h, *s.ws, s.ws->b, s.ws->x, s.ws->r, true, s.stream);
+    pmgdev::outer_step(h, *s.ws, precision == PMG_FP32_IN_FP64, s.ws->b, s.ws->x, s.ws->r, true, s.stream);
     pmgdev::enqueue_norm_readback(*s.ws, s.stream);
     hipEventRecord(s.ev, s.stream);
     s.phase = 2;
