@@ -113,7 +113,9 @@ typedef struct {
   int64_t nnz_a1;             /* nnz of the finest p = 1 operator */
   int32_t segments;           /* lines of the triangular-solve schedule */
   int32_t seg_len;            /* rows per line */
-  int32_t dag_levels_l, dag_levels_u; /* depth of the L and U dependency DAGs */
+  int32_t dag_levels_l, dag_levels_u; /* depth of the L and U dependency DAGs (rows) */
+  int32_t chunks_l, chunks_u;             /* chunks of the triangular-solve schedules */
+  int32_t chunk_levels_l, chunk_levels_u; /* depth of their chunk dependency graphs */
   int64_t bytes_vcycle;       /* algorithmic HBM bytes of one FP64 V-cycle */
   int64_t bytes_spmv, bytes_trisolve_l, bytes_trisolve_u, bytes_restrict, bytes_prolong,
       bytes_coarse;
@@ -215,13 +217,13 @@ pmg_status pmg_export_perm(pmg_handle h, int32_t *out);
 
 /* Host copies of the schedule and chunk-sliced layout of a triangular solve
  * (test hook; layout of each field as the kernels read it).  factor: 0 lower,
- * 1 upper.  field: 0 chunk order (ticket -> chunk), 1 wptr and 2 waits (per
- * chunk, pairs of segment and rows of it read), 3 off_ptr, 4 off_w,
- * 5 off_col, 6 in_ptr, 7 in_w, 8 in_j (int32 elements), 9 off_val,
- * 10 in_val, 11 diag (double elements; diag for the upper factor only).  *count receives the
- * number of elements; out, when non-NULL, must hold that many.  Chunks are
- * numbered segment * ceil(seg_len / 64) + chunk (segments and seg_len in
- * pmg_info).  EINVAL for an unknown factor or field. */
+ * 1 upper.  field: 0 chunk order (ticket -> chunk), 1 wptr and 2 deps (per
+ * chunk, the chunks it reads), 3 off_ptr, 4 off_w, 5 off_col, 6 in_ptr,
+ * 7 in_w, 8 in_j (int32 elements), 9 off_val, 10 in_val, 11 diag (double
+ * elements; diag for the upper factor only), 12 chunk_row, 13 chunk_len
+ * (first row and rows of each chunk, int32).  *count receives the number of
+ * elements; out, when non-NULL, must hold that many.  Chunks are numbered
+ * by first row.  EINVAL for an unknown factor or field. */
 pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int64_t *count, void *out);
 
 /* Per-step timing with HIP events recorded on the launch stream around each

@@ -57,6 +57,8 @@ class Info(C.Structure):
                 ("nnz_u", C.c_int64), ("nnz_r", C.c_int64), ("nnz_p", C.c_int64), ("nlev", C.c_int32),
                 ("n_coarsest", C.c_int32), ("nnz_a1", C.c_int64), ("segments", C.c_int32),
                 ("seg_len", C.c_int32), ("dag_levels_l", C.c_int32), ("dag_levels_u", C.c_int32),
+                ("chunks_l", C.c_int32), ("chunks_u", C.c_int32), ("chunk_levels_l", C.c_int32),
+                ("chunk_levels_u", C.c_int32),
                 ("bytes_vcycle", C.c_int64), ("bytes_spmv", C.c_int64), ("bytes_trisolve_l", C.c_int64),
                 ("bytes_trisolve_u", C.c_int64), ("bytes_restrict", C.c_int64),
                 ("bytes_prolong", C.c_int64), ("bytes_coarse", C.c_int64), ("device_bytes", C.c_int64),
@@ -289,8 +291,8 @@ class Solver:
         _check(lib().pmg_export_perm(self._h, out.ctypes.data_as(_I32P)))
         return out
 
-    SCHEDULE_FIELDS = ("order", "wptr", "waits", "off_ptr", "off_w", "off_col",
-                       "in_ptr", "in_w", "in_j", "off_val", "in_val", "diag")
+    SCHEDULE_FIELDS = ("order", "wptr", "deps", "off_ptr", "off_w", "off_col",
+                       "in_ptr", "in_w", "in_j", "off_val", "in_val", "diag", "chunk_row", "chunk_len")
 
     def export_schedule(self, factor):
         """Schedule and chunk-sliced layout of the lower (0) or upper (1)
@@ -299,11 +301,11 @@ class Solver:
         for f, name in enumerate(self.SCHEDULE_FIELDS):
             cnt = np.zeros(1, dtype=np.int64)
             _check(lib().pmg_export_schedule(self._h, factor, f, cnt.ctypes.data_as(_I64P), None))
-            dt = np.float64 if f >= 9 else np.int32
+            dt = np.float64 if 9 <= f <= 11 else np.int32
             a = np.zeros(max(int(cnt[0]), 1), dtype=dt)
             _check(lib().pmg_export_schedule(self._h, factor, f, cnt.ctypes.data_as(_I64P), a.ctypes.data_as(C.c_void_p)))
             a = a[: int(cnt[0])]
-            out[name] = a.reshape(-1, 2) if name == "waits" else a
+            out[name] = a
         return out
 
     def export_vec(self, which):

@@ -222,11 +222,12 @@ __device__ __forceinline__ void finish_grid(unsigned* state, int lane) {
 __device__ __forceinline__ TriMeta ld_meta(const TriMeta* p) {
   const auto* w = (const __attribute__((address_space(4))) int*)p;
   TriMeta m;
-  m.q = w[0];
-  m.off_ptr = w[1];
-  m.off_w = w[2];
-  m.in_ptr = w[3];
-  m.in_w = w[4];
+  m.row0 = w[0];
+  m.nrow = w[1];
+  m.off_ptr = w[2];
+  m.off_w = w[3];
+  m.in_ptr = w[4];
+  m.in_w = w[5];
   return m;
 }
 
@@ -349,20 +350,15 @@ __device__ __forceinline__ T serial_backward(T t, const T* tile, int lane) {
 // y must hold kPending in every entry at launch.
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_lower(
-    int nseg, int seg_len, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y,
-    unsigned* state) {
+    int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y, unsigned* state) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
-  const int nch = (seg_len + kWave - 1) / kWave;
-  const int nq = nseg * nch;
   for (;;) {
     const int tk = wave_ticket(state);
     if (tk >= nq) break;
     const TriMeta m = ld_meta(F.meta + tk);
-    const int s = m.q / nch, c = m.q - s * nch;
-    const int row = s * seg_len + c * kWave + lane;
-    const int nrow = min(kWave, seg_len - c * kWave);
-    const bool act = lane < nrow;
+    const int row = m.row0 + lane;
+    const bool act = lane < m.nrow;
     // every independent load of the chunk first
     const int pr = perm[act ? row : row - lane];  // lanes past the end read the chunk's first row
     int cc[kTriBatch];
@@ -385,20 +381,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // every entry at launch; y is only read.
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_upper(
-    int nseg, int seg_len, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ y, T* e,
-    T* __restrict__ x, unsigned* state) {
+    int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ y, T* e, T* __restrict__ x,
+    unsigned* state) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
-  const int nch = (seg_len + kWave - 1) / kWave;
-  const int nq = nseg * nch;
   for (;;) {
     const int tk = wave_ticket(state);
     if (tk >= nq) break;
     const TriMeta m = ld_meta(F.meta + tk);
-    const int s = m.q / nch, c = m.q - s * nch;
-    const int row = s * seg_len + c * kWave + lane;
-    const int nrow = min(kWave, seg_len - c * kWave);
-    const bool act = lane < nrow;
+    const int row = m.row0 + lane;
+    const bool act = lane < m.nrow;
     const int ra = act ? row : row - lane;  // lanes past the end read the chunk's first row
     const T t0 = y[ra];
     const T d0 = F.diag[ra];

@@ -71,18 +71,114 @@ unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 unsigned csr_grid(int nrows, int G) { return std::min<unsigned>(nblocks(nrows, 256 / G), kMaxCsrBlocks); }
 
+// Chunk boundaries of the segment-ordered triangular solves.  A segment is
+// cut into chunks of 64 rows, counted in processing coordinates (forward
+// solve: position in the segment; backward solve: position from its end),
+// with the first chunk shortened by an offset o in [0, 64).  The offset of
+// each segment is chosen, in processing order, among multiples of 4 so that
+// the segment's chunks reach the lowest levels of the chunk dependency graph
+// given the chunks of the segments before it: a chunk of one grid line reads
+// a few rows past its own end in the previous lines, and with aligned
+// boundaries it would wait for two chunks of each of them instead of one.
+// Returns per segment the processing-coordinate chunk starts (plus seg_len).
+std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int nseg, bool upper) {
+  // per segment: for each segment it reads, the furthest processing position
+  // read by the row at each processing position (-1: none)
+  struct Dep {
+    int t;
+    std::vector<int> reach;
+  };
+  std::vector<std::vector<Dep>> deps(nseg);
+  std::vector<int> slot(nseg, -1);
+  for (int s = 0; s < nseg; ++s) {
+    std::vector<int> touched;
+    for (int x = 0; x < seg_len; ++x) {
+      const int row = s * seg_len + x;
+      const int xp = upper ? seg_len - 1 - x : x;
+      for (int64_t k = T.rp[row] + (upper ? 1 : 0); k < T.rp[row + 1]; ++k) {
+        const int t = T.ci[k] / seg_len, y = T.ci[k] % seg_len;
+        if (t == s) continue;
+        if (slot[t] < 0) {
+          slot[t] = (int)deps[s].size();
+          deps[s].push_back(Dep{t, std::vector<int>(seg_len, -1)});
+          touched.push_back(t);
+        }
+        int& r = deps[s][slot[t]].reach[xp];
+        r = std::max(r, upper ? seg_len - 1 - y : y);
+      }
+    }
+    for (int t : touched) slot[t] = -1;
+  }
+  std::vector<std::vector<int>> bounds(nseg), levels(nseg);
+  auto cut = [&](int o) {
+    std::vector<int> b{0};
+    for (int a = 64 - o; a < seg_len; a += 64)
+      if (a > 0) b.push_back(a);
+    b.push_back(seg_len);
+    return b;
+  };
+  std::vector<int> lv;
+  for (int qq = 0; qq < nseg; ++qq) {
+    const int s = upper ? nseg - 1 - qq : qq;
+    int best_last = INT32_MAX;
+    int64_t best_sum = 0;
+    for (int o = 0; o < 64; o += 4) {
+      const std::vector<int> b = cut(o);
+      lv.assign(b.size() - 1, 0);
+      int prev = 0;
+      int64_t sum = 0;
+      for (size_t k = 0; k + 1 < b.size(); ++k) {
+        int l = prev;
+        for (const Dep& d : deps[s]) {
+          int need = -1;
+          for (int x = b[k]; x < b[k + 1]; ++x) need = std::max(need, d.reach[x]);
+          if (need < 0) continue;
+          const std::vector<int>& tb = bounds[d.t];
+          const size_t kk = std::upper_bound(tb.begin(), tb.end(), need) - tb.begin() - 1;
+          l = std::max(l, levels[d.t][kk]);
+        }
+        lv[k] = prev = l + 1;
+        sum += l + 1;
+      }
+      if (lv.back() < best_last || (lv.back() == best_last && sum < best_sum)) {
+        best_last = lv.back();
+        best_sum = sum;
+        bounds[s] = b;
+        levels[s] = lv;
+      }
+    }
+  }
+  return bounds;
+}
+
 // Schedule and chunk-sliced layout of one segment-ordered triangular solve
 // (the layout is described with pmg::TriDev).  Forward: row i reads rows
-// j < i; a segment's progress counts its leading rows that are final.
-// Backward (upper == true): row i reads rows j > i, chunks are finished from
-// the end of the segment, and progress counts rows final from its end.
+// j < i; backward (upper == true): row i reads rows j > i and chunks are
+// finished from the end of their segment.
 pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
   const int n = T.nrows;
   S.seg_len = seg_len;
   S.nseg = n / seg_len;
-  S.nch = (seg_len + 63) / 64;
-  const int nch = S.nch;
-  const int nq = S.nseg * nch;
+  // chunk geometry in natural order (segment-major, ascending rows)
+  const std::vector<std::vector<int>> bounds = choose_chunks(T, seg_len, S.nseg, upper);
+  S.chunk_row.clear();
+  S.chunk_len.clear();
+  for (int s = 0; s < S.nseg; ++s) {
+    const std::vector<int>& b = bounds[s];
+    const int K = (int)b.size() - 1;
+    for (int k = 0; k < K; ++k) {
+      const int kp = upper ? K - 1 - k : k;  // processing index of the k-th chunk by rows
+      const int a = upper ? seg_len - b[kp + 1] : b[kp];
+      const int e = upper ? seg_len - b[kp] : b[kp + 1];
+      S.chunk_row.push_back(s * seg_len + a);
+      S.chunk_len.push_back(e - a);
+    }
+  }
+  const int nq = (int)S.chunk_row.size();
+  S.nch = nq;
+  std::vector<int> row_chunk(n);
+  for (int q = 0; q < nq; ++q)
+    for (int r = S.chunk_row[q]; r < S.chunk_row[q] + S.chunk_len[q]; ++r) row_chunk[r] = q;
   S.wptr.assign((size_t)nq + 1, 0);
   S.off_ptr.assign(nq, 0);
   S.off_w.assign(nq, 0);
@@ -93,8 +189,7 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
     for (int row = 0; row < n; ++row) S.diag[row] = T.v[T.rp[row]];
   // slot counts first, so the sliced arrays are written in place below
   for (int q = 0; q < nq; ++q) {
-    const int r0 = (q / nch) * seg_len + (q % nch) * 64;
-    const int r1 = std::min((q / nch) * seg_len + seg_len, r0 + 64);
+    const int r0 = S.chunk_row[q], r1 = r0 + S.chunk_len[q];
     int wo = 0, wi = 0;
     for (int row = r0; row < r1; ++row) {
       int ni = 0, no = 0;
@@ -123,38 +218,36 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
   S.in_j.assign(ni_tot + 64, -1);
   S.in_val.assign(ni_tot + 64, 0.0);
   // per chunk, in a topological order (forward: ascending q, backward:
-  // descending q): its dependencies, their levels and the sliced entries
-  std::vector<int> level(nq, 0), need(nq, 0), touched;
-  std::vector<std::vector<int2>> waits_q(nq);
+  // descending q): the chunks it reads, its level and the sliced entries
+  std::vector<int> level(nq, 0), mark(nq, 0), touched;
+  std::vector<std::vector<int>> deps_q(nq);
   std::vector<std::vector<int>> oc(64), ic(64);
-  auto chunk_of = [&](int col) { return (col / seg_len) * nch + (col % seg_len) / 64; };
   for (int qq = 0; qq < nq; ++qq) {
     const int q = upper ? nq - 1 - qq : qq;
-    const int s = q / nch, c = q % nch;
-    const int r0 = s * seg_len + c * 64;
-    const int r1 = std::min(s * seg_len + seg_len, r0 + 64);
+    const int r0 = S.chunk_row[q], r1 = r0 + S.chunk_len[q];
+    const int s = r0 / seg_len;
     touched.clear();
-    auto add_need = [&](int qd, int req) {
-      if (need[qd] == 0) touched.push_back(qd);
-      need[qd] = std::max(need[qd], req);
+    auto add_dep = [&](int qd) {
+      if (!mark[qd]) {
+        mark[qd] = 1;
+        touched.push_back(qd);
+      }
     };
     // the previous chunk of the own segment, always
-    if (!upper && c > 0) add_need(q - 1, c * 64);
-    if (upper && c < nch - 1) add_need(q + 1, seg_len - (c + 1) * 64);
+    if (!upper && r0 > s * seg_len) add_dep(q - 1);
+    if (upper && r1 < (s + 1) * seg_len) add_dep(q + 1);
     for (int row = r0; row < r1; ++row) {
       const int l = row - r0;
       oc[l].clear();
       ic[l].clear();
-      const int64_t k0 = T.rp[row] + (upper ? 1 : 0), k1 = T.rp[row + 1];
-      for (int64_t k = k0; k < k1; ++k) {
+      for (int64_t k = T.rp[row] + (upper ? 1 : 0); k < T.rp[row + 1]; ++k) {
         const int col = T.ci[k];
         if (col >= r0 && col < r1) {
           ic[l].push_back((int)k);
-          continue;
+        } else {
+          oc[l].push_back((int)k);
+          add_dep(row_chunk[col]);
         }
-        oc[l].push_back((int)k);
-        const int sc = col / seg_len;
-        add_need(chunk_of(col), upper ? (sc * seg_len + seg_len - col) : (col - sc * seg_len + 1));
       }
     }
     int lv = 0;
@@ -166,14 +259,12 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
       return upper ? a > b : a < b;
     };
     std::sort(touched.begin(), touched.end(), earlier);
-    for (size_t i = 0; i < touched.size(); ++i) {
-      waits_q[q].push_back(make_int2(touched[i] / nch, need[touched[i]]));
-      need[touched[i]] = 0;
-    }
+    for (int qd : touched) mark[qd] = 0;
+    deps_q[q] = touched;
     // slots of each row by the level of their chunk, then by column
     for (int l = 0; l < r1 - r0; ++l)
       std::sort(oc[l].begin(), oc[l].end(), [&](int ka, int kb) {
-        const int qa = chunk_of(T.ci[ka]), qb = chunk_of(T.ci[kb]);
+        const int qa = row_chunk[T.ci[ka]], qb = row_chunk[T.ci[kb]];
         if (qa != qb) return earlier(qa, qb);
         return upper ? T.ci[ka] > T.ci[kb] : T.ci[ka] < T.ci[kb];
       });
@@ -193,17 +284,16 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
   }
   // dependency lists by natural chunk index (they define the order; the
   // kernels find readiness in the data)
-  S.waits.clear();
+  S.deps.clear();
   for (int q = 0; q < nq; ++q) {
-    S.waits.insert(S.waits.end(), waits_q[q].begin(), waits_q[q].end());
-    S.wptr[q + 1] = (int)S.waits.size();
+    S.deps.insert(S.deps.end(), deps_q[q].begin(), deps_q[q].end());
+    S.wptr[q + 1] = (int)S.deps.size();
   }
   // ticket order: by level, ties in processing order
   S.order.resize(nq);
   for (int i = 0; i < nq; ++i) S.order[i] = upper ? nq - 1 - i : i;
   std::stable_sort(S.order.begin(), S.order.end(), [&](int a, int b) { return level[a] < level[b]; });
   S.chunk_levels = nq ? *std::max_element(level.begin(), level.end()) : 0;
-  S.nwaits = (int)S.waits.size();
   S.slots = (int64_t)S.off_pad;
   // depth of the row dependency DAG (for the record)
   std::vector<int> lev(n, 0);
@@ -251,7 +341,7 @@ pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with3
   std::vector<pmg::TriMeta> meta(nq);
   for (int tk = 0; tk < nq; ++tk) {
     const int q = S.order[tk];
-    meta[tk] = pmg::TriMeta{q, S.off_ptr[q], S.off_w[q], S.in_ptr[q], S.in_w[q], {0, 0, 0}};
+    meta[tk] = pmg::TriMeta{S.chunk_row[q], S.chunk_len[q], S.off_ptr[q], S.off_w[q], S.in_ptr[q], S.in_w[q], {0, 0}};
   }
   pmg::TriMeta* md;
   int *oc, *ij;
@@ -299,8 +389,8 @@ pmg_status size_tri_grid(int device, TriSched& L, TriSched& U) {
   PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_u, pmg::trisolve_upper<T>, 64, 0));
   const int64_t cl = (int64_t)std::max(per_cu_l, 1) * prop.multiProcessorCount;
   const int64_t cu = (int64_t)std::max(per_cu_u, 1) * prop.multiProcessorCount;
-  const int gl = (int)std::max<int64_t>(1, std::min<int64_t>(cl, (int64_t)L.nseg * L.nch));
-  const int gu = (int)std::max<int64_t>(1, std::min<int64_t>(cu, (int64_t)U.nseg * U.nch));
+  const int gl = (int)std::max<int64_t>(1, std::min<int64_t>(cl, (int64_t)L.nch));
+  const int gu = (int)std::max<int64_t>(1, std::min<int64_t>(cu, (int64_t)U.nch));
   (sizeof(T) == 8 ? L.grid64 : L.grid32) = gl;
   (sizeof(T) == 8 ? U.grid64 : U.grid32) = gu;
   return PMG_OK;
@@ -382,16 +472,15 @@ template <typename T>
 void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_LOWER, st);
   fill_pending(y, h->H.n, st);
-  pmg::trisolve_lower<T><<<tri_grid<T>(h->tl), 64, 0, st>>>(h->tl.nseg, h->tl.seg_len, tri_dev<T>(h->tl), h->d_perm, r, y,
-                                                             ws.tickets);
+  pmg::trisolve_lower<T><<<tri_grid<T>(h->tl), 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, ws.tickets);
 }
 
 template <typename T>
 void upper_impl(pmg_handle h, Workspace& ws, const T* y, T* e, T* x, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_UPPER, st);
   fill_pending(e, h->H.n, st);
-  pmg::trisolve_upper<T><<<tri_grid<T>(h->tu), 64, 0, st>>>(h->tu.nseg, h->tu.seg_len, tri_dev<T>(h->tu), h->d_perm, y, e,
-                                                             x, ws.tickets + 2);
+  pmg::trisolve_upper<T><<<tri_grid<T>(h->tu), 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x,
+                                                             ws.tickets + 2);
 }
 
 // x += U^{-1} L^{-1} P r (then permuted back) with work vectors y, e.
@@ -775,6 +864,10 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   I.seg_len = seg_len;
   I.dag_levels_l = h->tl.dag_levels;
   I.dag_levels_u = h->tu.dag_levels;
+  I.chunks_l = h->tl.nch;
+  I.chunks_u = h->tu.nch;
+  I.chunk_levels_l = h->tl.chunk_levels;
+  I.chunk_levels_u = h->tu.chunk_levels;
   const int64_t n = H.n, n1 = H.n1;
   I.bytes_spmv = 12 * I.nnz_a + 4 * (n + 1) + 24 * n;
   I.bytes_trisolve_l = 12 * I.nnz_l + 4 * (n + 1) + 16 * n;
@@ -933,10 +1026,7 @@ pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int6
   switch (field) {
     case 0: iv = &S.order; break;
     case 1: iv = &S.wptr; break;
-    case 2:
-      *count = 2 * (int64_t)S.waits.size();
-      if (out) std::memcpy(out, S.waits.data(), sizeof(int2) * S.waits.size());
-      return PMG_OK;
+    case 2: iv = &S.deps; break;
     case 3: iv = &S.off_ptr; break;
     case 4: iv = &S.off_w; break;
     case 5: iv = &S.off_col; break;
@@ -946,6 +1036,8 @@ pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int6
     case 9: dv = &S.off_val; break;
     case 10: dv = &S.in_val; break;
     case 11: dv = &S.diag; break;
+    case 12: iv = &S.chunk_row; break;
+    case 13: iv = &S.chunk_len; break;
     default: return fail(PMG_EINVAL, "unknown schedule field " + std::to_string(field));
   }
   if (iv) {

@@ -64,11 +64,12 @@ struct DevMat {
 
 // Schedule and chunk-sliced factor of one triangular solve (see TriDev).
 struct TriSched {
-  int nseg = 0, seg_len = 0, nch = 0, nwaits = 0, dag_levels = 0, chunk_levels = 0;
+  int nseg = 0, seg_len = 0, dag_levels = 0, chunk_levels = 0;
+  int nch = 0;  // chunks in all
   int grid64 = 1, grid32 = 1;  // persistent waves per launch (all resident)
   // all by natural chunk index
-  std::vector<int> wptr, order;  // dependency lists; ticket -> chunk
-  std::vector<int2> waits;
+  std::vector<int> chunk_row, chunk_len;  // first row and rows of each chunk
+  std::vector<int> wptr, deps, order;     // chunks read by each chunk; ticket -> chunk
   std::vector<int> off_ptr, off_w, off_col, in_ptr, in_w, in_j;
   std::vector<double> off_val, in_val, diag;
   int64_t slots = 0;  // stored off-chunk slots (entries + padding)

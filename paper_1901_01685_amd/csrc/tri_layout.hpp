@@ -18,9 +18,9 @@ constexpr unsigned kPending32 = 0x7F80DEADu;
 
 // Factors in the chunk-sliced layout of the triangular solves.  A chunk is
 // up to 64 consecutive rows of one segment, lane = row - chunk start; q is
-// the chunk's natural index (segment * chunks per segment + chunk).  Chunks
-// are taken in a topological order of the chunk dependency graph, by level,
-// so a wave only ever waits for chunks taken before its own.
+// the chunk's natural index (chunks numbered by first row).  Chunks are taken
+// in a topological order of the chunk dependency graph, by level, so a wave
+// only ever waits for chunks taken before its own.
 //   Off-chunk entries: slot u of lane l at off_ptr[q] + 64 u + l for
 //   u < off_w[q], per row sorted by the level of the chunk holding the
 //   source row (ties: lower factor ascending columns, upper descending), so
@@ -39,10 +39,10 @@ constexpr unsigned kPending32 = 0x7F80DEADu;
 // The per-chunk scalars are packed in ticket order, one 32-byte record per
 // ticket, so a wave reads all of them with one scalar load.
 struct alignas(32) TriMeta {
-  int q;               // natural chunk index
+  int row0, nrow;      // first row and rows of the chunk
   int off_ptr, off_w;  // off-chunk slots
   int in_ptr, in_w;    // in-chunk slots
-  int unused[3];
+  int unused[2];
 };
 
 template <typename T>

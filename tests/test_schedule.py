@@ -25,10 +25,16 @@ CASES = [(2, 2, 16), (2, 3, 40), (2, 5, 24), (3, 2, 12)]
 
 def _emulate(s, factor, rhs):
     S = s.export_schedule(factor)
-    nseg, seg = s.info.segments, s.info.seg_len
-    nch = (seg + 63) // 64
-    nq = nseg * nch
+    seg = s.info.seg_len
     upper = factor == 1
+    row0, nrows = S["chunk_row"], S["chunk_len"]
+    nq = len(row0)
+    assert nq == (s.info.chunks_u if upper else s.info.chunks_l)
+    # chunks tile the rows, never cross a segment, hold at most 64 rows
+    assert row0[0] == 0 and np.all(row0[1:] == row0[:-1] + nrows[:-1]) and row0[-1] + nrows[-1] == s.n
+    assert np.all((nrows >= 1) & (nrows <= 64))
+    assert np.all(row0 // seg == (row0 + nrows - 1) // seg)
+    row_chunk = np.repeat(np.arange(nq), nrows)
     order = S["order"]
     assert np.array_equal(np.sort(order), np.arange(nq)), "ticket order is not a permutation of the chunks"
     ticket = np.empty(nq, dtype=np.int64)
@@ -36,17 +42,14 @@ def _emulate(s, factor, rhs):
     final = np.zeros(s.n, dtype=bool)
     out = np.zeros(s.n)
     for tk, q in enumerate(order):
-        sg, c = divmod(int(q), nch)
-        r0, nrow = sg * seg + c * 64, min(64, seg - c * 64)
+        r0, nrow = int(row0[q]), int(nrows[q])
+        sg = r0 // seg
         # dependency list: chunks of other tickets, all earlier
-        W = S["waits"][S["wptr"][q]:S["wptr"][q + 1]]
-        deps = set()
-        for (sc, need) in W:
-            dq = sc * nch + ((need - 1) // 64 if not upper else (seg - need) // 64)
+        deps = set(int(d) for d in S["deps"][S["wptr"][q]:S["wptr"][q + 1]])
+        for dq in deps:
             assert ticket[dq] < tk, "chunk %d waits for chunk %d taken later" % (q, dq)
-            deps.add(int(dq))
-        own_prev = (q - 1 if c > 0 else None) if not upper else (q + 1 if c < nch - 1 else None)
-        if own_prev is not None:
+        own_prev = q - 1 if not upper else q + 1
+        if 0 <= own_prev < nq and row0[own_prev] // seg == sg:
             assert own_prev in deps, "chunk %d does not wait for its segment's previous chunk" % q
         w, base = S["off_w"][q], S["off_ptr"][q]
         t = np.zeros(64)
@@ -62,7 +65,7 @@ def _emulate(s, factor, rhs):
                 assert l < nrow
                 col = int(cols[l])
                 assert final[col], "ticket %d reads entry %d before it is final" % (tk, col)
-                read.add((col // seg) * nch + (col % seg) // 64)
+                read.add(int(row_chunk[col]))
                 t[l] -= vals[l] * out[col]
         assert read <= deps, "chunk %d reads chunks missing from its dependency list" % q
         tile = np.zeros((64, 64))
@@ -109,17 +112,40 @@ def test_schedule_is_deadlock_free_and_layout_solves(case):
 
 def test_chunk_order_is_by_level():
     """Tickets follow the level of the chunk dependency graph, so the waves in
-    flight at any time work on the same few levels."""
+    flight at any time work on the same few levels; the reported depth is
+    that graph's."""
     s = pmg.Solver(2, 3, 64, device=-1)
     for f in (0, 1):
         S = s.export_schedule(f)
-        seg = s.info.seg_len
-        nch = (seg + 63) // 64
-        nq = s.info.segments * nch
+        nq = len(S["chunk_row"])
         lev = np.zeros(nq, dtype=np.int64)
         for q in S["order"]:
-            W = S["waits"][S["wptr"][q]:S["wptr"][q + 1]]
-            if len(W):
-                dq = W[:, 0] * nch + ((W[:, 1] - 1) // 64 if f == 0 else (seg - W[:, 1]) // 64)
-                lev[q] = lev[dq].max() + 1
+            d = S["deps"][S["wptr"][q]:S["wptr"][q + 1]]
+            lev[q] = (lev[d].max() if len(d) else 0) + 1
         assert np.all(np.diff(lev[S["order"]]) >= 0)
+        assert lev.max() == (s.info.chunk_levels_u if f else s.info.chunk_levels_l)
+
+
+def test_skewed_chunks_shorten_the_chain():
+    """Chunk boundaries shifted per segment (first chunk shorter) so that a
+    chunk waits for one chunk of each previous grid line instead of two:
+    the chunk graph is markedly shallower than with aligned 64-row chunks,
+    whose depth is recomputed here from the exported factors."""
+    s = pmg.Solver(2, 5, 128, device=-1)
+    seg = s.info.seg_len
+    for f, T in ((0, s.export(pmg.OP_L)), (1, s.export(pmg.OP_U))):
+        T = T.tocsr()
+        nch = (seg + 63) // 64
+        chunk = lambda i: (i // seg) * nch + (i % seg) // 64
+        nq = s.info.segments * nch
+        lev = np.zeros(nq, dtype=np.int64)
+        qs = range(nq) if f == 0 else range(nq - 1, -1, -1)
+        for q in qs:
+            sg, c = divmod(q, nch)
+            r0, r1 = sg * seg + c * 64, min(sg * seg + seg, sg * seg + c * 64 + 64)
+            cols = T.indices[T.indptr[r0] + (1 if f else 0): T.indptr[r1]] if not f else \
+                np.concatenate([T.indices[T.indptr[i] + 1: T.indptr[i + 1]] for i in range(r0, r1)])
+            cq = np.unique([chunk(c_) for c_ in cols if not (r0 <= c_ < r1)])
+            lev[q] = (lev[cq].max() if len(cq) else 0) + 1
+        skewed = s.info.chunk_levels_u if f else s.info.chunk_levels_l
+        assert skewed <= 0.85 * lev.max(), (skewed, lev.max())
