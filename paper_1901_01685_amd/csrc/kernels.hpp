@@ -90,6 +90,48 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
   }
 }
 
+// Residual r = b - A x with A in stencil layout.  With the tensor-product
+// B-spline basis of degree p, row i (grid position (ix, iy, iz), x fastest,
+// nx * ny per plane) couples only to the rows at offsets |dx|, |dy|, |dz| <=
+// p; the value of offset k of row i is V[k * n + i] (k lexicographic in
+// (dz, dy, dx), 0 where the offset leaves the grid), so no column indices
+// are stored and both V and x are read contiguously across a wave's rows.
+// Sums run over dz, dy, dx ascending; block partials of sum(r^2) as for the
+// CSR residual.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void stencil_resid(int n, int nx, int ny, int p, const T* __restrict__ V,
+                                                     const T* __restrict__ x, const T* __restrict__ b,
+                                                     T* __restrict__ r, double* __restrict__ partial) {
+  const int w = 2 * p + 1;
+  const int nz = DIM == 3 ? n / (nx * ny) : 1;
+  double sq = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int ix = i % nx, t = i / nx, iy = t % ny, iz = t / ny;
+    const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
+    const int dy0 = max(-p, -iy), dy1 = min(p, ny - 1 - iy);
+    const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
+    T acc = 0;
+    for (int dz = dz0; dz <= dz1; ++dz)
+      for (int dy = dy0; dy <= dy1; ++dy) {
+        const int k0 = ((DIM == 3 ? (dz + p) * w : 0) + (dy + p)) * w + p;  // offset index of dx = 0
+        const T* vr = V + (size_t)k0 * n + i;
+        const T* xr = x + i + (dz * ny + dy) * nx;
+        for (int dx = dx0; dx <= dx1; ++dx) acc += vr[(int64_t)dx * n] * xr[dx];
+      }
+    const T res = b[i] - acc;
+    r[i] = res;
+    sq += (double)res * (double)res;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // Sums n block partials in a fixed order into out[0] (one block).
 __global__ __launch_bounds__(256) void reduce_partials(int n, const double* __restrict__ partial,
                                                        double* __restrict__ out) {

@@ -22,6 +22,7 @@
 
 using pmgdev::DevMat;
 using pmgdev::TriSched;
+using pmgdev::DevStencil;
 using pmgdev::Workspace;
 using pmgdev::fail;
 
@@ -335,6 +336,54 @@ pmg_status upload_mat(pmgdev::DevArena& mem, const pmg::Csr& M, DevMat& D, bool 
   return PMG_OK;
 }
 
+// Offsets of A's stencil layout (see pmg::stencil_resid), or 0 when it is
+// not used: every entry must lie within the degree-p offsets of its row, and
+// the layout must read fewer bytes than CSR (8 bytes per offset slot against
+// 12 per non-zero; the zero slots at the boundary make it lose on small grids).
+int stencil_slots(const pmg::HostOps& H) {
+  const int d = H.dim, p = H.p, nx = H.nel + p - 2;
+  const int w = 2 * p + 1;
+  const int S = d == 2 ? w * w : w * w * w;
+  const int64_t n = H.n;
+  if ((int64_t)8 * S * n >= (int64_t)12 * H.A.nnz()) return 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t ix = i % nx, iy = (i / nx) % nx, iz = i / ((int64_t)nx * nx);
+    for (int64_t k = H.A.rp[i]; k < H.A.rp[i + 1]; ++k) {
+      const int64_t j = H.A.ci[k];
+      const int64_t dx = j % nx - ix, dy = (j / nx) % nx - iy, dz = j / ((int64_t)nx * nx) - iz;
+      if (std::abs(dx) > p || std::abs(dy) > p || std::abs(dz) > p) return 0;
+    }
+  }
+  return S;
+}
+
+pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, DevStencil& D, bool with32) {
+  if (S == 0) return PMG_OK;
+  const int d = H.dim, p = H.p, nx = H.nel + p - 2, w = 2 * p + 1;
+  const int64_t n = H.n;
+  std::vector<double> V((size_t)S * n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t ix = i % nx, iy = (i / nx) % nx, iz = i / ((int64_t)nx * nx);
+    for (int64_t k = H.A.rp[i]; k < H.A.rp[i + 1]; ++k) {
+      const int64_t j = H.A.ci[k];
+      const int64_t dx = j % nx - ix, dy = (j / nx) % nx - iy, dz = j / ((int64_t)nx * nx) - iz;
+      const int64_t off = ((d == 3 ? (dz + p) * w : 0) + (dy + p)) * w + (dx + p);
+      V[(size_t)off * n + i] = H.A.v[k];
+    }
+  }
+  pmg_status s;
+  if ((s = mem.upload(&D.v, V.data(), V.size()))) return s;
+  if (with32) {
+    std::vector<float> V32(V.begin(), V.end());
+    if ((s = mem.upload(&D.v32, V32.data(), V32.size()))) return s;
+  }
+  D.dim = d;
+  D.p = p;
+  D.nx = D.ny = nx;
+  D.S = S;
+  return PMG_OK;
+}
+
 pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with32) {
   pmg_status s;
   const int nq = (int)S.order.size();
@@ -449,6 +498,28 @@ void csr_launch(int mode, int nrows, const int* rows, const DevMat& M, const T* 
   }
 }
 
+// r = b - A_{h,p} x with block partials of sum(r^2) in partial; returns the
+// number of partials written.
+template <typename T>
+unsigned resid_a(pmg_handle h, const T* x, const T* b, T* r, double* partial, hipStream_t st) {
+  const DevStencil& S = h->As;
+  if (S.v) {
+    const T* V;
+    if constexpr (sizeof(T) == 8) V = S.v; else V = S.v32;
+    const int n = h->A.nrows;
+    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    if (S.dim == 2)
+      pmg::stencil_resid<T, 2><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
+    else
+      pmg::stencil_resid<T, 3><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
+    return grid;
+  }
+  const T* v;
+  if constexpr (sizeof(T) == 8) v = h->A.v; else v = h->A.v32;
+  csr_launch<T>(pmg::kResid, h->A.nrows, nullptr, h->A, v, x, b, nullptr, r, partial, st);
+  return csr_grid(h->A.nrows, h->A.G);
+}
+
 template <typename T>
 void fill(T* p, int64_t n, T val, hipStream_t st) {
   if (n > 0) pmg::fill_kernel<T><<<nblocks(n, 256), 256, 0, st>>>(n, p, val);
@@ -545,7 +616,7 @@ void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
   const float* cur = ws.r32;  // residual of the correction equation at c = 0
   for (int k = 0; k < nu1; ++k) {
     smooth_impl<float>(h, ws, cur, c, ws.y32, ws.e32, st);
-    csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
+    resid_a<float>(h, c, ws.r32, t, ws.partial, st);
     cur = t;
   }
   if (n1 > 0) {
@@ -556,13 +627,13 @@ void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
     pmg::cast_kernel<double, float><<<nblocks(n1, 256), 256, 0, st>>>(n1, ws.e1, ws.q32);
     csr_launch<float>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v32, ws.q32, nullptr, h->mlp_inv32, c,
                       nullptr, st);
-    csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
+    resid_a<float>(h, c, ws.r32, t, ws.partial, st);
     cur = t;
   }
   for (int k = 0; k < nu2; ++k) {
     smooth_impl<float>(h, ws, cur, c, ws.y32, ws.e32, st);
     if (k + 1 < nu2) {
-      csr_launch<float>(pmg::kResid, n, nullptr, h->A, h->A.v32, c, ws.r32, nullptr, t, ws.partial, st);
+      resid_a<float>(h, c, ws.r32, t, ws.partial, st);
       cur = t;
     }
   }
@@ -649,8 +720,8 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
 void residual64(pmg_handle h, Workspace& ws, const double* b, const double* x, double* r, bool norm,
                 hipStream_t st) {
   ProfScope ps(h, PMG_PROF_RESIDUAL, st);
-  csr_launch<double>(pmg::kResid, h->A.nrows, nullptr, h->A, h->A.v, x, b, nullptr, r, ws.partial, st);
-  if (norm) pmg::reduce_partials<<<1, 256, 0, st>>>((int)csr_grid(h->A.nrows, h->A.G), ws.partial, ws.scalar);
+  const unsigned np = resid_a<double>(h, x, b, r, ws.partial, st);
+  if (norm) pmg::reduce_partials<<<1, 256, 0, st>>>((int)np, ws.partial, ws.scalar);
 }
 
 void enqueue_norm_readback(Workspace& ws, hipStream_t st) {
@@ -869,7 +940,9 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   I.chunk_levels_l = h->tl.chunk_levels;
   I.chunk_levels_u = h->tu.chunk_levels;
   const int64_t n = H.n, n1 = H.n1;
-  I.bytes_spmv = 12 * I.nnz_a + 4 * (n + 1) + 24 * n;
+  h->a_stencil = stencil_slots(H);
+  I.bytes_spmv = h->a_stencil ? 8 * (int64_t)h->a_stencil * H.n + 24 * (int64_t)H.n
+                              : 12 * I.nnz_a + 4 * (n + 1) + 24 * n;
   I.bytes_trisolve_l = 12 * I.nnz_l + 4 * (n + 1) + 16 * n;
   I.bytes_trisolve_u = 12 * I.nnz_u + 4 * (n + 1) + 32 * n;
   I.bytes_restrict = 12 * I.nnz_r + 4 * (n1 + 1) + 8 * n + 16 * n1;
@@ -905,6 +978,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     pmgdev::DevArena& m = h->ops;
     pmg_status s;
     if ((s = upload_mat(m, H.A, h->A, mixed))) return s;
+    if ((s = upload_stencil(m, H, h->a_stencil, h->As, mixed))) return s;
     if ((s = upload_tri(m, h->tl, false, mixed))) return s;
     if ((s = upload_tri(m, h->tu, true, mixed))) return s;
     if ((s = size_tri_grid<double>(o.device, h->tl, h->tu))) return s;

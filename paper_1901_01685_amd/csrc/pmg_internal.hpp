@@ -62,6 +62,14 @@ struct DevMat {
   int G = 8;
 };
 
+// A_{h,p} in stencil layout (pmg::stencil_resid), used instead of CSR when
+// it reads fewer bytes.
+struct DevStencil {
+  int dim = 0, p = 0, nx = 0, ny = 0, S = 0;  // S = (2p+1)^dim offsets
+  double* v = nullptr;
+  float* v32 = nullptr;
+};
+
 // Schedule and chunk-sliced factor of one triangular solve (see TriDev).
 struct TriSched {
   int nseg = 0, seg_len = 0, dag_levels = 0, chunk_levels = 0;
@@ -118,6 +126,8 @@ struct pmg_handle_s {
   int colors = 4;
   pmgdev::DevArena ops;  // operators (read-only during solves)
   pmgdev::DevMat A, L, U, R, P;
+  pmgdev::DevStencil As;  // A in stencil layout (As.v == nullptr: CSR is used)
+  int a_stencil = 0;      // offsets of that layout, 0 if CSR is used
   std::vector<pmgdev::DevMat> A1, Ph, Rh;
   std::vector<std::vector<int*>> color_rows;
   std::vector<std::vector<int>> color_cnt;
