@@ -96,8 +96,15 @@ def test_info_sizes_and_bytes():
     assert i.seg_len == 67 and i.segments == 67
     # lower bound on the natural-order DAG depth of the ILU(0) pattern
     assert i.dag_levels_l >= (5 + 2) * (67 - 1) + 1
-    assert i.bytes_spmv == 12 * i.nnz_a + 4 * (i.n + 1) + 24 * i.n
+    # the residual reads A in stencil layout (8 bytes per offset slot, 11^2
+    # slots per row) when that is fewer bytes than CSR (12 per non-zero)
+    stencil = 8 * 11 ** 2 * i.n + 24 * i.n
+    csr = 12 * i.nnz_a + 4 * (i.n + 1) + 24 * i.n
+    assert stencil < csr and i.bytes_spmv == stencil
     assert i.bytes_vcycle > 3 * i.bytes_spmv
+    # on a small 3-D grid the zero slots at the boundary make CSR cheaper
+    j = P.Solver(3, 3, 8, device=-1).info
+    assert j.bytes_spmv == 12 * j.nnz_a + 4 * (j.n + 1) + 24 * j.n
 
 
 def test_status_codes_host():
