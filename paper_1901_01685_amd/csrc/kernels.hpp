@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "tri_layout.hpp"
+#include "grid_layout.hpp"
 
 namespace pmg {
 
@@ -179,6 +180,154 @@ __global__ __launch_bounds__(256) void dense_matvec(int n, const double* __restr
     for (int j = 0; j < n; ++j) s += a[j] * bs[j];
     e[i] = s;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Degree-1 h-multigrid on the structured grids of its levels.
+//
+// A level's interior nodes form an nx^d grid (x fastest).  Its operator
+// couples a node only to the nodes at offsets in {-1, 0, 1}^d, stored per
+// colour (parity of the grid position along each axis: colour bit a = parity
+// along axis a): the t-th node of colour c (x fastest within the colour) has
+// the value of offset k (lexicographic in (dz, dy, dx)) at
+// V[voff[c] + k * cnt[c] + t].  A colour's nodes are not coupled to each
+// other, so a Gauss-Seidel half-sweep over one colour is one parallel pass
+// reading its values contiguously.  The canonical transfers (weights 1/2, 1,
+// 1/2 per axis: coarse node c sits on fine node 2c + 1) are applied from
+// their definition, without a matrix.
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+__device__ __forceinline__ void colour_node(const GridLevel& L, int c, int t, int& ix, int& iy, int& iz) {
+  const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+  const int mx = (L.nx - cx + 1) / 2, my = (L.nx - cy + 1) / 2;
+  const int tx = t % mx, r = t / mx;
+  ix = 2 * tx + cx;
+  iy = 2 * (DIM == 3 ? r % my : r) + cy;
+  iz = DIM == 3 ? 2 * (r / my) + cz : 0;
+}
+
+// sum over the offsets of node (ix, iy, iz), the centre left out when
+// skip_centre (its value returned in *centre)
+template <int DIM>
+__device__ __forceinline__ double grid_dot(const GridLevel& L, const double* vc, int cnt, int t, int ix, int iy,
+                                           int iz, const double* x, bool skip_centre, double* centre) {
+  const int nx = L.nx;
+  const int i = (iz * nx + iy) * nx + ix;
+  double acc = 0.0;
+  int k = 0;
+#pragma unroll
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx, ++k) {
+        const bool ok = ix + dx >= 0 && ix + dx < nx && iy + dy >= 0 && iy + dy < nx &&
+                        (DIM == 2 || (iz + dz >= 0 && iz + dz < nx));
+        const double a = vc[(size_t)k * cnt + t];
+        if (dx == 0 && dy == 0 && dz == 0 && skip_centre) {
+          *centre = a;
+        } else if (ok) {
+          acc += a * x[i + (dz * nx + dy) * nx + dx];
+        }
+      }
+  return acc;
+}
+
+// One multicolour Gauss-Seidel half-sweep: e_i = (b_i - sum_{j != i} a_ij e_j) / a_ii
+// for the nodes of colour c.
+template <int DIM>
+__global__ __launch_bounds__(256) void grid_gs(GridLevel L, int c, const double* __restrict__ b, double* e) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= L.cnt[c]) return;
+  int ix, iy, iz;
+  colour_node<DIM>(L, c, t, ix, iy, iz);
+  const int i = (iz * L.nx + iy) * L.nx + ix;
+  double centre = 1.0;
+  const double acc = grid_dot<DIM>(L, L.v + L.voff[c], L.cnt[c], t, ix, iy, iz, e, true, &centre);
+  e[i] = (b[i] - acc) / centre;
+}
+
+// r = b - A e over all nodes (threads in colour-major order).
+template <int DIM>
+__global__ __launch_bounds__(256) void grid_resid(GridLevel L, const double* __restrict__ b,
+                                                  const double* __restrict__ e, double* __restrict__ r) {
+  int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= L.n) return;
+  int c = 0;
+  while (g >= L.cnt[c]) g -= L.cnt[c++];
+  int ix, iy, iz;
+  colour_node<DIM>(L, c, g, ix, iy, iz);
+  const int i = (iz * L.nx + iy) * L.nx + ix;
+  r[i] = b[i] - grid_dot<DIM>(L, L.v + L.voff[c], L.cnt[c], g, ix, iy, iz, e, false, nullptr);
+}
+
+// Coarse right-hand side bc = R_h r (R_h = P_h^T: coarse node c collects fine
+// nodes 2c, 2c+1, 2c+2 with weights 1/2, 1, 1/2 per axis) and the coarse
+// iterate ec = 0.  nf = 2 nc + 1 fine nodes per axis.
+template <int DIM>
+__global__ __launch_bounds__(256) void grid_restrict(int nc, const double* __restrict__ r, double* __restrict__ bc,
+                                                     double* __restrict__ ec) {
+  const int C = blockIdx.x * 256 + threadIdx.x;
+  const int ncell = DIM == 3 ? nc * nc * nc : nc * nc;
+  if (C >= ncell) return;
+  const int nf = 2 * nc + 1;
+  const int cx = C % nc, cy = (C / nc) % nc, cz = DIM == 3 ? C / (nc * nc) : 0;
+  const double w[3] = {0.5, 1.0, 0.5};
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < (DIM == 3 ? 3 : 1); ++a)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const int fz = DIM == 3 ? 2 * cz + a : 0;
+        const double wz = DIM == 3 ? w[a] : 1.0;
+        acc += (wz * w[bb] * w[cc]) * r[((size_t)fz * nf + 2 * cy + bb) * nf + 2 * cx + cc];
+      }
+  bc[C] = acc;
+  ec[C] = 0.0;
+}
+
+// e_f += P_h ec: fine node f along an axis takes coarse (f-1)/2 with weight 1
+// if f is odd, else coarse f/2 - 1 and f/2 (those that exist) with 1/2.
+template <int DIM>
+__global__ __launch_bounds__(256) void grid_prolong_add(int nc, const double* __restrict__ ec, double* __restrict__ ef) {
+  const int nf = 2 * nc + 1;
+  const int F = blockIdx.x * 256 + threadIdx.x;
+  const int nfine = DIM == 3 ? nf * nf * nf : nf * nf;
+  if (F >= nfine) return;
+  const int f[3] = {F % nf, (F / nf) % nf, DIM == 3 ? F / (nf * nf) : 0};
+  int cs[3][2], m[3];
+  double ws[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m[a] = 0;
+    if (a == 2 && DIM == 2) {
+      cs[a][0] = 0;
+      ws[a][0] = 1.0;
+      m[a] = 1;
+    } else if (f[a] & 1) {
+      cs[a][0] = (f[a] - 1) / 2;
+      ws[a][0] = 1.0;
+      m[a] = 1;
+    } else {
+      if (f[a] / 2 - 1 >= 0) {
+        cs[a][m[a]] = f[a] / 2 - 1;
+        ws[a][m[a]++] = 0.5;
+      }
+      if (f[a] / 2 < nc) {
+        cs[a][m[a]] = f[a] / 2;
+        ws[a][m[a]++] = 0.5;
+      }
+    }
+  }
+  double acc = 0.0;
+  for (int a2 = 0; a2 < m[2]; ++a2)
+    for (int a1 = 0; a1 < m[1]; ++a1)
+      for (int a0 = 0; a0 < m[0]; ++a0)
+        acc += (ws[2][a2] * ws[1][a1] * ws[0][a0]) * ec[((size_t)cs[2][a2] * nc + cs[1][a1]) * nc + cs[0][a0]];
+  ef[F] += acc;
 }
 
 // ---------------------------------------------------------------------------

@@ -384,6 +384,64 @@ pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, D
   return PMG_OK;
 }
 
+// Degree-1 levels in colour-major stencil layout (see the structured
+// h-multigrid kernels).  Leaves G empty, so the CSR path is taken, unless
+// every level's operator couples nodes only within {-1, 0, 1}^d and the
+// levels halve (nx_l = 2 nx_{l+1} + 1).
+pmg_status upload_grid_levels(pmgdev::DevArena& mem, const pmg::HostOps& H, int dim, std::vector<pmg::GridLevel>& G) {
+  G.clear();
+  const int nl = H.nlev - 1;  // levels with smoothing (the last is solved directly)
+  for (int l = 0; l + 1 < H.nlev; ++l)
+    if (H.lnel[l] != 2 * H.lnel[l + 1]) return PMG_OK;
+  const int K = dim == 2 ? 9 : 27;
+  std::vector<pmg::GridLevel> out(nl);
+  std::vector<std::vector<double>> vals(nl);
+  for (int l = 0; l < nl; ++l) {
+    const pmg::Csr& A = H.A1[l];
+    const int nx = H.lnel[l] - 1;
+    pmg::GridLevel& L = out[l];
+    L.nx = nx;
+    L.n = (int)H.ln[l];
+    for (int c = 0; c < 8; ++c) {
+      const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+      if (dim == 2 && cz) {
+        L.cnt[c] = 0;
+        continue;
+      }
+      int64_t m = (int64_t)((nx - cx + 1) / 2) * ((nx - cy + 1) / 2);
+      if (dim == 3) m *= (nx - cz + 1) / 2;
+      L.cnt[c] = (int)m;
+    }
+    int64_t off = 0;
+    for (int c = 0; c < 8; ++c) {
+      L.voff[c] = (int)off;
+      off += (int64_t)K * L.cnt[c];
+    }
+    vals[l].assign(off, 0.0);
+    for (int64_t i = 0; i < L.n; ++i) {
+      const int ix = (int)(i % nx), iy = (int)((i / nx) % nx), iz = (int)(i / ((int64_t)nx * nx));
+      const int c = (ix & 1) | ((iy & 1) << 1) | (dim == 3 ? (iz & 1) << 2 : 0);
+      const int mx = (nx - (c & 1) + 1) / 2, my = (nx - ((c >> 1) & 1) + 1) / 2;
+      const int64_t t = ix / 2 + (int64_t)mx * (iy / 2 + (int64_t)my * (dim == 3 ? iz / 2 : 0));
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int64_t j = A.ci[k];
+        const int dx = (int)(j % nx) - ix, dy = (int)((j / nx) % nx) - iy, dz = (int)(j / ((int64_t)nx * nx)) - iz;
+        if (std::abs(dx) > 1 || std::abs(dy) > 1 || std::abs(dz) > 1) return PMG_OK;  // not a stencil
+        const int kk = ((dim == 3 ? (dz + 1) * 3 : 0) + (dy + 1)) * 3 + (dx + 1);
+        vals[l][L.voff[c] + (int64_t)kk * L.cnt[c] + t] = A.v[k];
+      }
+    }
+  }
+  for (int l = 0; l < nl; ++l) {
+    double* d;
+    pmg_status s = mem.upload(&d, vals[l].data(), vals[l].size());
+    if (s) return s;
+    out[l].v = d;
+  }
+  G = out;
+  return PMG_OK;
+}
+
 pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with32) {
   pmg_status s;
   const int nq = (int)S.order.size();
@@ -568,8 +626,53 @@ void gs_sweeps(pmg_handle h, int l, const double* b, double* e, int nsweep, hipS
                          nullptr, e, nullptr, st);
 }
 
+// The h-multigrid V-cycle from level l on the structured grids (pmg::grid_*).
+void hcycle_grid(pmg_handle h, Workspace& ws, int l, const double* b, double* e, hipStream_t st) {
+  const pmg::HostOps& H = h->H;
+  if (l == H.nlev - 1) {
+    pmg::dense_matvec<<<1, 256, 0, st>>>(H.n_coarse, h->coarse_inv, b, e);
+    return;
+  }
+  const pmg::GridLevel& L = h->grid[l];
+  const bool d3 = h->prob.dim == 3;
+  auto sweeps = [&](int nsweep) {
+    for (int sw = 0; sw < nsweep; ++sw)
+      for (int c = 0; c < h->colors; ++c) {
+        if (!L.cnt[c]) continue;
+        if (d3)
+          pmg::grid_gs<3><<<nblocks(L.cnt[c], 256), 256, 0, st>>>(L, c, b, e);
+        else
+          pmg::grid_gs<2><<<nblocks(L.cnt[c], 256), 256, 0, st>>>(L, c, b, e);
+      }
+  };
+  sweeps(h->opt.nu1);
+  double* r = ws.hr[l];
+  if (d3)
+    pmg::grid_resid<3><<<nblocks(L.n, 256), 256, 0, st>>>(L, b, e, r);
+  else
+    pmg::grid_resid<2><<<nblocks(L.n, 256), 256, 0, st>>>(L, b, e, r);
+  double* bc = ws.hb[l + 1];
+  double* ec = ws.he[l + 1];
+  const int nc = H.lnel[l + 1] - 1;
+  const int64_t ncell = H.ln[l + 1];
+  if (d3)
+    pmg::grid_restrict<3><<<nblocks(ncell, 256), 256, 0, st>>>(nc, r, bc, ec);
+  else
+    pmg::grid_restrict<2><<<nblocks(ncell, 256), 256, 0, st>>>(nc, r, bc, ec);
+  hcycle_grid(h, ws, l + 1, bc, ec, st);
+  if (d3)
+    pmg::grid_prolong_add<3><<<nblocks(L.n, 256), 256, 0, st>>>(nc, ec, e);
+  else
+    pmg::grid_prolong_add<2><<<nblocks(L.n, 256), 256, 0, st>>>(nc, ec, e);
+  sweeps(h->opt.nu2);
+}
+
 void hcycle(pmg_handle h, Workspace& ws, int l, const double* b, double* e, hipStream_t st) {
   const pmg::HostOps& H = h->H;
+  if (!h->grid.empty()) {
+    hcycle_grid(h, ws, l, b, e, st);
+    return;
+  }
   if (l == H.nlev - 1) {
     pmg::dense_matvec<<<1, 256, 0, st>>>(H.n_coarse, h->coarse_inv, b, e);
     return;
@@ -1015,6 +1118,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
         if ((s = m.upload(&h->color_rows[l][c], lists[c].data(), lists[c].size()))) return s;
       }
     }
+    if ((s = upload_grid_levels(m, H, prob->dim, h->grid))) return s;
     std::vector<double> inv(H.n), inv1(std::max<int64_t>(n1, 1));
     for (int64_t i = 0; i < n; ++i) inv[i] = 1.0 / H.mlp[i];
     for (int64_t i = 0; i < n1; ++i) inv1[i] = 1.0 / H.ml1[i];

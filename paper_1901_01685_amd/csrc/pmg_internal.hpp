@@ -8,6 +8,7 @@
 
 #include "../../include/pmg.h"
 #include "tri_layout.hpp"
+#include "grid_layout.hpp"
 #include "pmg_host.hpp"
 
 namespace pmgdev {
@@ -129,6 +130,7 @@ struct pmg_handle_s {
   pmgdev::DevStencil As;  // A in stencil layout (As.v == nullptr: CSR is used)
   int a_stencil = 0;      // offsets of that layout, 0 if CSR is used
   std::vector<pmgdev::DevMat> A1, Ph, Rh;
+  std::vector<pmg::GridLevel> grid;  // degree-1 levels in stencil layout (empty: CSR path)
   std::vector<std::vector<int*>> color_rows;
   std::vector<std::vector<int>> color_cnt;
   double *f = nullptr, *mlp_inv = nullptr, *ml1_inv = nullptr, *coarse_inv = nullptr;
