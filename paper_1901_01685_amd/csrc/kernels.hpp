@@ -133,6 +133,32 @@ __global__ __launch_bounds__(256) void stencil_resid(int n, int nx, int ny, int 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// y = d .* (M x) (or y += d .* (M x) with ADD) for a transfer M between the
+// degree-p and degree-1 grids (nxr nodes per axis for the rows, nxc for the
+// columns).  Row i at grid position (ix, iy, iz) couples only to the column
+// nodes (ix + o + kx, iy + o + ky, iz + o + kz), 0 <= k < W per axis; the
+// value of slot k (lexicographic in (kz, ky, kx)) is V[k * nrow + i], 0 where
+// the column node leaves its grid.
+template <typename T, int DIM, bool ADD>
+__global__ __launch_bounds__(256) void xgrid_spmv(int nrow, int nxr, int nxc, int o, int W, const T* __restrict__ V,
+                                                  const T* __restrict__ x, const T* __restrict__ d, T* out) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nrow; i += gridDim.x * 256) {
+    const int ix = i % nxr, t = i / nxr, iy = t % nxr, iz = t / nxr;
+    const int jx = ix + o, jy = iy + o, jz = DIM == 3 ? iz + o : 0;
+    const int kx0 = max(0, -jx), kx1 = min(W, nxc - jx);
+    const int ky0 = max(0, -jy), ky1 = min(W, nxc - jy);
+    const int kz0 = DIM == 3 ? max(0, -jz) : 0, kz1 = DIM == 3 ? min(W, nxc - jz) : 1;
+    T acc = 0;
+    for (int kz = kz0; kz < kz1; ++kz)
+      for (int ky = ky0; ky < ky1; ++ky) {
+        const T* vr = V + (size_t)((DIM == 3 ? kz * W : 0) + ky) * W * nrow + i;
+        const T* xr = x + ((size_t)(jz + kz) * nxc + (jy + ky)) * nxc + jx;
+        for (int kx = kx0; kx < kx1; ++kx) acc += vr[(int64_t)kx * nrow] * xr[kx];
+      }
+    out[i] = ADD ? out[i] + d[i] * acc : d[i] * acc;
+  }
+}
+
 // Sums n block partials in a fixed order into out[0] (one block).
 __global__ __launch_bounds__(256) void reduce_partials(int n, const double* __restrict__ partial,
                                                        double* __restrict__ out) {

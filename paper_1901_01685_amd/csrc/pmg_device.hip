@@ -23,6 +23,7 @@
 using pmgdev::DevMat;
 using pmgdev::TriSched;
 using pmgdev::DevStencil;
+using pmgdev::DevXStencil;
 using pmgdev::Workspace;
 using pmgdev::fail;
 
@@ -442,6 +443,57 @@ pmg_status upload_grid_levels(pmgdev::DevArena& mem, const pmg::HostOps& H, int 
   return PMG_OK;
 }
 
+// Shape of a transfer M between grids (rows on an nxr^d grid, columns on an
+// nxc^d grid) in stencil layout: every row couples only to a W^d block of
+// column nodes at offset lo from its own position.  Returns the number of
+// slots W^d if that layout reads fewer bytes than CSR, else 0.
+int64_t xstencil_shape(const pmg::Csr& M, int dim, int nxr, int nxc, int& lo, int& W) {
+  auto pos = [&](int64_t i, int nx, int a) {
+    return (int)(a == 0 ? i % nx : a == 1 ? (i / nx) % nx : i / ((int64_t)nx * nx));
+  };
+  lo = INT32_MAX;
+  int hi = INT32_MIN;
+  for (int64_t i = 0; i < M.nrows; ++i)
+    for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k)
+      for (int a = 0; a < dim; ++a) {
+        const int dlt = pos(M.ci[k], nxc, a) - pos(i, nxr, a);
+        lo = std::min(lo, dlt);
+        hi = std::max(hi, dlt);
+      }
+  if (M.nnz() == 0) return 0;
+  W = hi - lo + 1;
+  const int64_t S = dim == 2 ? (int64_t)W * W : (int64_t)W * W * W;
+  return 8 * S * M.nrows < 12 * M.nnz() ? S : 0;
+}
+
+pmg_status upload_xstencil(pmgdev::DevArena& mem, const pmg::Csr& M, int dim, int nxr, int nxc, DevXStencil& D,
+                           bool with32) {
+  auto pos = [&](int64_t i, int nx, int a) {
+    return (int)(a == 0 ? i % nx : a == 1 ? (i / nx) % nx : i / ((int64_t)nx * nx));
+  };
+  int lo = 0, W = 0;
+  const int64_t S = xstencil_shape(M, dim, nxr, nxc, lo, W);
+  if (S == 0) return PMG_OK;
+  std::vector<double> V((size_t)S * M.nrows, 0.0);
+  for (int64_t i = 0; i < M.nrows; ++i)
+    for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) {
+      int64_t slot = 0;
+      for (int a = dim - 1; a >= 0; --a) slot = slot * W + (pos(M.ci[k], nxc, a) - pos(i, nxr, a) - lo);
+      V[(size_t)slot * M.nrows + i] = M.v[k];
+    }
+  pmg_status s;
+  if ((s = mem.upload(&D.v, V.data(), V.size()))) return s;
+  if (with32) {
+    std::vector<float> V32(V.begin(), V.end());
+    if ((s = mem.upload(&D.v32, V32.data(), V32.size()))) return s;
+  }
+  D.nxr = nxr;
+  D.nxc = nxc;
+  D.o = lo;
+  D.W = W;
+  return PMG_OK;
+}
+
 pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with32) {
   pmg_status s;
   const int nq = (int)S.order.size();
@@ -554,6 +606,32 @@ void csr_launch(int mode, int nrows, const int* rows, const DevMat& M, const T* 
     case 32: csr_launch_g<T, 32>(mode, nrows, rows, M, v, x, b, d, out, partial, st); break;
     default: csr_launch_g<T, 64>(mode, nrows, rows, M, v, x, b, d, out, partial, st); break;
   }
+}
+
+// out = d .* (M x) (add: out += d .* (M x)) for a p-transfer, stencil or CSR.
+template <typename T>
+void transfer(const DevMat& M, const DevXStencil& X, int dim, const T* x, const T* d, T* out, bool add,
+              hipStream_t st) {
+  if (X.v) {
+    const T* V;
+    if constexpr (sizeof(T) == 8) V = X.v; else V = X.v32;
+    const unsigned grid = std::min<unsigned>(nblocks(M.nrows, 256), kMaxCsrBlocks);
+    if (dim == 2) {
+      if (add)
+        pmg::xgrid_spmv<T, 2, true><<<grid, 256, 0, st>>>(M.nrows, X.nxr, X.nxc, X.o, X.W, V, x, d, out);
+      else
+        pmg::xgrid_spmv<T, 2, false><<<grid, 256, 0, st>>>(M.nrows, X.nxr, X.nxc, X.o, X.W, V, x, d, out);
+    } else {
+      if (add)
+        pmg::xgrid_spmv<T, 3, true><<<grid, 256, 0, st>>>(M.nrows, X.nxr, X.nxc, X.o, X.W, V, x, d, out);
+      else
+        pmg::xgrid_spmv<T, 3, false><<<grid, 256, 0, st>>>(M.nrows, X.nxr, X.nxc, X.o, X.W, V, x, d, out);
+    }
+    return;
+  }
+  const T* v;
+  if constexpr (sizeof(T) == 8) v = M.v; else v = M.v32;
+  csr_launch<T>(add ? pmg::kScaleAdd : pmg::kScale, M.nrows, nullptr, M, v, x, nullptr, d, out, nullptr, st);
 }
 
 // r = b - A_{h,p} x with block partials of sum(r^2) in partial; returns the
@@ -699,12 +777,12 @@ void coarse_impl(pmg_handle h, Workspace& ws, const double* r1, double* e1, hipS
 
 void restrict64(pmg_handle h, const double* r, double* r1, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_RESTRICT, st);
-  csr_launch<double>(pmg::kScale, h->R.nrows, nullptr, h->R, h->R.v, r, nullptr, h->ml1_inv, r1, nullptr, st);
+  transfer<double>(h->R, h->Rs, h->prob.dim, r, h->ml1_inv, r1, false, st);
 }
 
 void prolong64(pmg_handle h, const double* e1, double* x, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_PROLONG, st);
-  csr_launch<double>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v, e1, nullptr, h->mlp_inv, x, nullptr, st);
+  transfer<double>(h->P, h->Ps, h->prob.dim, e1, h->mlp_inv, x, true, st);
 }
 
 // One FP32 V-cycle on A c = r32 from c = 0 (inner step of defect
@@ -723,13 +801,11 @@ void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
     cur = t;
   }
   if (n1 > 0) {
-    csr_launch<float>(pmg::kScale, h->R.nrows, nullptr, h->R, h->R.v32, cur, nullptr, h->ml1_inv32, ws.q32,
-                      nullptr, st);
+    transfer<float>(h->R, h->Rs, h->prob.dim, cur, h->ml1_inv32, ws.q32, false, st);
     pmg::cast_kernel<float, double><<<nblocks(n1, 256), 256, 0, st>>>(n1, ws.q32, ws.r1);
     coarse_impl(h, ws, ws.r1, ws.e1, st);
     pmg::cast_kernel<double, float><<<nblocks(n1, 256), 256, 0, st>>>(n1, ws.e1, ws.q32);
-    csr_launch<float>(pmg::kScaleAdd, h->P.nrows, nullptr, h->P, h->P.v32, ws.q32, nullptr, h->mlp_inv32, c,
-                      nullptr, st);
+    transfer<float>(h->P, h->Ps, h->prob.dim, ws.q32, h->mlp_inv32, c, true, st);
     resid_a<float>(h, c, ws.r32, t, ws.partial, st);
     cur = t;
   }
@@ -1048,8 +1124,14 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
                               : 12 * I.nnz_a + 4 * (n + 1) + 24 * n;
   I.bytes_trisolve_l = 12 * I.nnz_l + 4 * (n + 1) + 16 * n;
   I.bytes_trisolve_u = 12 * I.nnz_u + 4 * (n + 1) + 32 * n;
-  I.bytes_restrict = 12 * I.nnz_r + 4 * (n1 + 1) + 8 * n + 16 * n1;
-  I.bytes_prolong = 12 * I.nnz_p + 4 * (n + 1) + 8 * n1 + 24 * n;
+  {
+    const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem - 1;
+    int lo, W;
+    const int64_t sr = n1 > 0 ? xstencil_shape(H.R, prob->dim, nx1, nxp, lo, W) : 0;
+    const int64_t sp = n1 > 0 ? xstencil_shape(H.P, prob->dim, nxp, nx1, lo, W) : 0;
+    I.bytes_restrict = (sr ? 8 * sr * n1 : 12 * I.nnz_r + 4 * (n1 + 1)) + 8 * n + 16 * n1;
+    I.bytes_prolong = (sp ? 8 * sp * n : 12 * I.nnz_p + 4 * (n + 1)) + 8 * n1 + 24 * n;
+  }
   int64_t bc = 0;
   for (int l = 0; l < H.nlev; ++l) {
     const int64_t nl = H.ln[l];
@@ -1089,6 +1171,9 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     if (n1 > 0) {
       if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
       if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
+      const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem - 1;
+      if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
+      if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
     }
     h->A1.resize(H.nlev);
     h->Ph.resize(H.Ph.size());

@@ -71,6 +71,14 @@ struct DevStencil {
   float* v32 = nullptr;
 };
 
+// A transfer between the degree-p and degree-1 grids in stencil layout
+// (pmg::xgrid_spmv); v == nullptr: CSR is used.
+struct DevXStencil {
+  int nxr = 0, nxc = 0, o = 0, W = 0;
+  double* v = nullptr;
+  float* v32 = nullptr;
+};
+
 // Schedule and chunk-sliced factor of one triangular solve (see TriDev).
 struct TriSched {
   int nseg = 0, seg_len = 0, dag_levels = 0, chunk_levels = 0;
@@ -129,6 +137,7 @@ struct pmg_handle_s {
   pmgdev::DevMat A, L, U, R, P;
   pmgdev::DevStencil As;  // A in stencil layout (As.v == nullptr: CSR is used)
   int a_stencil = 0;      // offsets of that layout, 0 if CSR is used
+  pmgdev::DevXStencil Rs, Ps;  // P_p^1 and P_1^p in stencil layout
   std::vector<pmgdev::DevMat> A1, Ph, Rh;
   std::vector<pmg::GridLevel> grid;  // degree-1 levels in stencil layout (empty: CSR path)
   std::vector<std::vector<int*>> color_rows;
