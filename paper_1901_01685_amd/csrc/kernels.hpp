@@ -357,6 +357,186 @@ __global__ __launch_bounds__(256) void grid_prolong_add(int nc, const double* __
 }
 
 // ---------------------------------------------------------------------------
+// The smallest levels of the structured h-multigrid V-cycle in one workgroup.
+//
+// Below a few thousand nodes a level's phases are too short to fill the GPU,
+// and a launch per phase costs more than the phase.  This kernel runs the
+// V-cycle from level 0 of its list down to the coarsest and back (the same
+// steps as the launch-per-phase path) with every level's iterate and
+// right-hand side in LDS; only the stencil values (L2-resident) and the
+// coarsest inverse are read from global memory.  Phases are separated by
+// workgroup barriers.
+// ---------------------------------------------------------------------------
+
+constexpr int kLdsLevels = 6;
+constexpr int kLdsThreads = 1024;
+
+struct LdsCycle {
+  int nl;               // levels in the list, the last solved directly
+  int colors, nu1, nu2;
+  int ncoarse;          // unknowns of the coarsest level
+  const double* cinv;   // its inverse, row-major
+  const double* b0;     // right-hand side of the first level (global)
+  double* e0;           // iterate of the first level (global, read and written)
+  GridLevel lev[kLdsLevels - 1];  // smoothing levels
+  int nx[kLdsLevels];   // nodes per axis of every level
+  int eoff[kLdsLevels], boff[kLdsLevels], roff;  // LDS offsets (doubles)
+};
+
+template <int DIM>
+__device__ __forceinline__ int grid_index(int nx, int ix, int iy, int iz) {
+  return (iz * nx + iy) * nx + ix;
+}
+
+// sum over the offsets of node (ix, iy, iz) of a level held in LDS (x), the
+// centre left out when skip_centre
+template <int DIM>
+__device__ __forceinline__ double lds_dot(const GridLevel& L, const double* vc, int cnt, int t, int ix, int iy, int iz,
+                                          const double* x, bool skip_centre, double* centre) {
+  const int nx = L.nx;
+  double a[DIM == 3 ? 27 : 9];
+  int k = 0;
+#pragma unroll
+  for (int q = 0; q < (DIM == 3 ? 27 : 9); ++q) a[q] = vc[(size_t)q * cnt + t];
+  double acc = 0.0;
+#pragma unroll
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx, ++k) {
+        const bool ok = ix + dx >= 0 && ix + dx < nx && iy + dy >= 0 && iy + dy < nx &&
+                        (DIM == 2 || (iz + dz >= 0 && iz + dz < nx));
+        if (dx == 0 && dy == 0 && dz == 0 && skip_centre)
+          *centre = a[k];
+        else if (ok)
+          acc += a[k] * x[grid_index<DIM>(nx, ix + dx, iy + dy, iz + dz)];
+      }
+  return acc;
+}
+
+template <int DIM>
+__device__ void lds_sweeps(const LdsCycle& S, int k, double* sm, int nsweep) {
+  const GridLevel& L = S.lev[k];
+  double* e = sm + S.eoff[k];
+  const double* b = sm + S.boff[k];
+  for (int sw = 0; sw < nsweep; ++sw)
+    for (int c = 0; c < S.colors; ++c) {
+      for (int t = threadIdx.x; t < L.cnt[c]; t += kLdsThreads) {
+        int ix, iy, iz;
+        colour_node<DIM>(L, c, t, ix, iy, iz);
+        double centre = 1.0;
+        const double acc = lds_dot<DIM>(L, L.v + L.voff[c], L.cnt[c], t, ix, iy, iz, e, true, &centre);
+        const int i = grid_index<DIM>(L.nx, ix, iy, iz);
+        e[i] = (b[i] - acc) / centre;
+      }
+      __syncthreads();
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kLdsThreads) void hcycle_lds(LdsCycle S) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x;
+  const int n0 = DIM == 3 ? S.nx[0] * S.nx[0] * S.nx[0] : S.nx[0] * S.nx[0];
+  for (int i = tid; i < n0; i += kLdsThreads) {
+    sm[S.boff[0] + i] = S.b0[i];
+    sm[S.eoff[0] + i] = S.e0[i];
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < S.nl; ++k) {
+    const GridLevel& L = S.lev[k];
+    lds_sweeps<DIM>(S, k, sm, S.nu1);
+    // residual into the scratch, all nodes in colour-major order
+    double* r = sm + S.roff;
+    const double* e = sm + S.eoff[k];
+    const double* b = sm + S.boff[k];
+    for (int g0 = tid; g0 < L.n; g0 += kLdsThreads) {
+      int g = g0, c = 0;
+      while (g >= L.cnt[c]) g -= L.cnt[c++];
+      int ix, iy, iz;
+      colour_node<DIM>(L, c, g, ix, iy, iz);
+      const int i = grid_index<DIM>(L.nx, ix, iy, iz);
+      r[i] = b[i] - lds_dot<DIM>(L, L.v + L.voff[c], L.cnt[c], g, ix, iy, iz, e, false, nullptr);
+    }
+    __syncthreads();
+    // restriction (weights 1/2, 1, 1/2 per axis) and a zero coarse iterate
+    const int nc = S.nx[k + 1], nf = 2 * nc + 1;
+    const int ncell = DIM == 3 ? nc * nc * nc : nc * nc;
+    double* bc = sm + S.boff[k + 1];
+    double* ec = sm + S.eoff[k + 1];
+    const double w[3] = {0.5, 1.0, 0.5};
+    for (int C = tid; C < ncell; C += kLdsThreads) {
+      const int cx = C % nc, cy = (C / nc) % nc, cz = DIM == 3 ? C / (nc * nc) : 0;
+      double acc = 0.0;
+      for (int a = 0; a < (DIM == 3 ? 3 : 1); ++a)
+        for (int bb = 0; bb < 3; ++bb)
+          for (int cc = 0; cc < 3; ++cc) {
+            const int fz = DIM == 3 ? 2 * cz + a : 0;
+            const double wz = DIM == 3 ? w[a] : 1.0;
+            acc += (wz * w[bb] * w[cc]) * r[(fz * nf + 2 * cy + bb) * nf + 2 * cx + cc];
+          }
+      bc[C] = acc;
+      ec[C] = 0.0;
+    }
+    __syncthreads();
+  }
+  {  // coarsest: e = A^{-1} b
+    const int kc = S.nl - 1;
+    const double* bc = sm + S.boff[kc];
+    double* ec = sm + S.eoff[kc];
+    for (int i = tid; i < S.ncoarse; i += kLdsThreads) {
+      const double* a = S.cinv + (size_t)i * S.ncoarse;
+      double acc = 0.0;
+      for (int j = 0; j < S.ncoarse; ++j) acc += a[j] * bc[j];
+      ec[i] = acc;
+    }
+    __syncthreads();
+  }
+  for (int k = S.nl - 2; k >= 0; --k) {
+    const int nc = S.nx[k + 1], nf = 2 * nc + 1;
+    const int nfine = DIM == 3 ? nf * nf * nf : nf * nf;
+    const double* ec = sm + S.eoff[k + 1];
+    double* ef = sm + S.eoff[k];
+    for (int F = tid; F < nfine; F += kLdsThreads) {
+      const int f[3] = {F % nf, (F / nf) % nf, DIM == 3 ? F / (nf * nf) : 0};
+      int cs[3][2], m[3];
+      double ws[3][2];
+      for (int a = 0; a < 3; ++a) {
+        m[a] = 0;
+        if (a == 2 && DIM == 2) {
+          cs[a][0] = 0;
+          ws[a][0] = 1.0;
+          m[a] = 1;
+        } else if (f[a] & 1) {
+          cs[a][0] = (f[a] - 1) / 2;
+          ws[a][0] = 1.0;
+          m[a] = 1;
+        } else {
+          if (f[a] / 2 - 1 >= 0) {
+            cs[a][m[a]] = f[a] / 2 - 1;
+            ws[a][m[a]++] = 0.5;
+          }
+          if (f[a] / 2 < nc) {
+            cs[a][m[a]] = f[a] / 2;
+            ws[a][m[a]++] = 0.5;
+          }
+        }
+      }
+      double acc = 0.0;
+      for (int a2 = 0; a2 < m[2]; ++a2)
+        for (int a1 = 0; a1 < m[1]; ++a1)
+          for (int a0 = 0; a0 < m[0]; ++a0)
+            acc += (ws[2][a2] * ws[1][a1] * ws[0][a0]) * ec[(cs[2][a2] * nc + cs[1][a1]) * nc + cs[0][a0]];
+      ef[F] += acc;
+    }
+    __syncthreads();
+    lds_sweeps<DIM>(S, k, sm, S.nu2);
+  }
+  for (int i = tid; i < n0; i += kLdsThreads) S.e0[i] = sm[S.eoff[0] + i];
+}
+
+// ---------------------------------------------------------------------------
 // Sparse triangular solves with the ILUT factors (Section 3, "Smoother").
 //
 // Rows are grouped in segments (grid lines of the tensor numbering, seg_len

@@ -77,7 +77,7 @@ unsigned csr_grid(int nrows, int G) { return std::min<unsigned>(nblocks(nrows, 2
 // cut into chunks of 64 rows, counted in processing coordinates (forward
 // solve: position in the segment; backward solve: position from its end),
 // with the first chunk shortened by an offset o in [0, 64).  The offset of
-// each segment is chosen, in processing order, among multiples of 4 so that
+// each segment is chosen, in processing order, among even values so that
 // the segment's chunks reach the lowest levels of the chunk dependency graph
 // given the chunks of the segments before it: a chunk of one grid line reads
 // a few rows past its own end in the previous lines, and with aligned
@@ -124,7 +124,7 @@ std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int 
     const int s = upper ? nseg - 1 - qq : qq;
     int best_last = INT32_MAX;
     int64_t best_sum = 0;
-    for (int o = 0; o < 64; o += 4) {
+    for (int o = 0; o < 64; o += 2) {
       const std::vector<int> b = cut(o);
       lv.assign(b.size() - 1, 0);
       int prev = 0;
@@ -704,9 +704,42 @@ void gs_sweeps(pmg_handle h, int l, const double* b, double* e, int nsweep, hipS
                          nullptr, e, nullptr, st);
 }
 
+// Levels l_lds.. of the structured V-cycle in one launch (pmg::hcycle_lds).
+void hcycle_lds(pmg_handle h, const double* b, double* e, hipStream_t st) {
+  const pmg::HostOps& H = h->H;
+  pmg::LdsCycle S{};
+  S.nl = H.nlev - h->l_lds;
+  S.colors = h->colors;
+  S.nu1 = h->opt.nu1;
+  S.nu2 = h->opt.nu2;
+  S.ncoarse = H.n_coarse;
+  S.cinv = h->coarse_inv;
+  S.b0 = b;
+  S.e0 = e;
+  int off = 0;
+  for (int k = 0; k < S.nl; ++k) {
+    const int l = h->l_lds + k;
+    S.nx[k] = H.lnel[l] - 1;
+    if (k + 1 < S.nl) S.lev[k] = h->grid[l];
+    S.eoff[k] = off;
+    off += (int)H.ln[l];
+    S.boff[k] = off;
+    off += (int)H.ln[l];
+  }
+  S.roff = off;
+  if (h->prob.dim == 3)
+    pmg::hcycle_lds<3><<<1, pmg::kLdsThreads, h->lds_bytes, st>>>(S);
+  else
+    pmg::hcycle_lds<2><<<1, pmg::kLdsThreads, h->lds_bytes, st>>>(S);
+}
+
 // The h-multigrid V-cycle from level l on the structured grids (pmg::grid_*).
 void hcycle_grid(pmg_handle h, Workspace& ws, int l, const double* b, double* e, hipStream_t st) {
   const pmg::HostOps& H = h->H;
+  if (l == h->l_lds) {
+    hcycle_lds(h, b, e, st);
+    return;
+  }
   if (l == H.nlev - 1) {
     pmg::dense_matvec<<<1, 256, 0, st>>>(H.n_coarse, h->coarse_inv, b, e);
     return;
@@ -1204,6 +1237,28 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
       }
     }
     if ((s = upload_grid_levels(m, H, prob->dim, h->grid))) return s;
+    // the smallest levels in one workgroup: from the coarsest upwards while
+    // their iterates, right-hand sides and one residual fit 128 KiB of LDS
+    if (!h->grid.empty()) {
+      int64_t need = 0;
+      int ll = -1;
+      for (int l = H.nlev - 1; l >= 0 && H.nlev - l <= pmg::kLdsLevels; --l) {
+        const int64_t dbl = need + 2 * H.ln[l] + H.ln[l];  // this level's e, b and the residual scratch
+        if (dbl * 8 > (128 << 10)) break;
+        need += 2 * H.ln[l];
+        ll = l;
+        h->lds_bytes = (size_t)dbl * 8;
+      }
+      h->l_lds = ll;
+      if (ll >= 0) {
+        auto k2 = pmg::hcycle_lds<2>;
+        auto k3 = pmg::hcycle_lds<3>;
+        if (prob->dim == 3)
+          PMG_HIP_OK(hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_bytes));
+        else
+          PMG_HIP_OK(hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_bytes));
+      }
+    }
     std::vector<double> inv(H.n), inv1(std::max<int64_t>(n1, 1));
     for (int64_t i = 0; i < n; ++i) inv[i] = 1.0 / H.mlp[i];
     for (int64_t i = 0; i < n1; ++i) inv1[i] = 1.0 / H.ml1[i];

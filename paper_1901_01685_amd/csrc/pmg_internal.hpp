@@ -140,6 +140,8 @@ struct pmg_handle_s {
   pmgdev::DevXStencil Rs, Ps;  // P_p^1 and P_1^p in stencil layout
   std::vector<pmgdev::DevMat> A1, Ph, Rh;
   std::vector<pmg::GridLevel> grid;  // degree-1 levels in stencil layout (empty: CSR path)
+  int l_lds = -1;                    // levels l_lds.. run in one workgroup from LDS (-1: none)
+  size_t lds_bytes = 0;              // its dynamic LDS
   std::vector<std::vector<int*>> color_rows;
   std::vector<std::vector<int>> color_cnt;
   double *f = nullptr, *mlp_inv = nullptr, *ml1_inv = nullptr, *coarse_inv = nullptr;
