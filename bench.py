@@ -31,18 +31,27 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "V-cycle DOF·iter/s + HBM GB/s frac; served solves/s, p50/p99 latency vs plain"
 
 # kernel class -> (kernel name in the rocprofv3 trace, info field of its bytes per launch)
-KERNELS = {
-    "residual": ("csr_kernel<double, 32, 0>", "bytes_spmv"),
-    "lower": ("trisolve_lower<double>", "bytes_trisolve_l"),
-    "upper": ("trisolve_upper<double>", "bytes_trisolve_u"),
-    "restrict": ("csr_kernel<double, 32, 2>", "bytes_restrict"),
-    "prolong": ("csr_kernel<double, 32, 3>", "bytes_prolong"),
-}
+def kernel_map(info, dim):
+    """Residual and p-transfers use the stencil kernels whenever the library
+    chose that layout (it reads fewer bytes than CSR), which shows in the
+    algorithmic byte counts it reports."""
+    stencil_a = info.bytes_spmv != 12 * info.nnz_a + 4 * (info.n + 1) + 24 * info.n
+    stencil_r = info.bytes_restrict != 12 * info.nnz_r + 4 * (info.n1 + 1) + 8 * info.n + 16 * info.n1
+    stencil_p = info.bytes_prolong != 12 * info.nnz_p + 4 * (info.n + 1) + 8 * info.n1 + 24 * info.n
+    return {
+        "residual": (f"stencil_resid<double, {dim}>" if stencil_a else "csr_kernel<double, G, 0>", "bytes_spmv"),
+        "lower": ("trisolve_lower<double>", "bytes_trisolve_l"),
+        "upper": ("trisolve_upper<double>", "bytes_trisolve_u"),
+        "restrict": (f"xgrid_spmv<double, {dim}, false>" if stencil_r else "csr_kernel<double, G, 2>",
+                     "bytes_restrict"),
+        "prolong": (f"xgrid_spmv<double, {dim}, true>" if stencil_p else "csr_kernel<double, G, 3>",
+                    "bytes_prolong"),
+    }
 
 
 def _kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "pmg_device.hip"):
+    for f in ("kernels.hpp", "tri_layout.hpp", "grid_layout.hpp", "pmg_device.hip"):
         h.update(open(os.path.join(ROOT, "paper_1901_01685_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -307,6 +316,7 @@ def main():
     s.profile_enable(False)
 
     # dominant kernel by total time per V-cycle
+    KERNELS = kernel_map(info, args.dim)
     per_class = {c: (ms, cnt) for c, (ms, cnt) in prof.items() if cnt > 0}
     dom = max((c for c in per_class if c in KERNELS), key=lambda c: per_class[c][0])
     ms_tot, cnt = per_class[dom]
@@ -325,6 +335,7 @@ def main():
         "traffic": _traffic(dom, workload),
         "avg_launch_ms": round(1e3 * avg_s, 4),
         "bytes_per_launch": int(nbytes),
+        "bytes_per_launch_by_class": {c: int(getattr(info, KERNELS[c][1])) for c in KERNELS},
         "per_step_ms": {c: round(v[0] / args.steps, 4) for c, v in per_class.items()},
         "ms_per_step_kernel_by_kernel": round(1e3 * el_eager / args.steps, 4),
         "vcycle_bytes": int(info.bytes_vcycle),
