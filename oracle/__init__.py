@@ -72,6 +72,7 @@ def lib():
         L.orc_solve.argtypes = [vp, dp, dp, C.c_double, C.c_int, dp, ip]
         L.orc_vcycle.argtypes = [vp, dp, dp, dp]
         L.orc_cg.argtypes = [vp, dp, dp, C.c_double, C.c_int, C.c_int, ip]
+        L.orc_bicgstab.argtypes = [vp, dp, dp, C.c_double, C.c_int, C.c_int, dp, ip]
         L.orc_l2_error.restype = C.c_double
         L.orc_l2_error.argtypes = [vp, dp]
         L.orc_residual.argtypes = [vp, dp, dp, dp]
@@ -331,6 +332,16 @@ class Oracle:
         hist = np.zeros(maxit + 1)
         it = C.c_int(0)
         st = lib().orc_solve(self._h, _dp(b), _dp(x), tol, maxit, _dp(hist), C.byref(it))
+        return x, st, it.value, hist[: it.value + 1].copy()
+
+    def bicgstab(self, b, x0=None, tol=1e-8, maxit=100, precond=True):
+        """BiCGSTAB right-preconditioned by one V-cycle (precond=False: none);
+        returns (x, status, iters, hist)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        hist = np.zeros(maxit + 1)
+        it = C.c_int(0)
+        st = lib().orc_bicgstab(self._h, _dp(b), _dp(x), tol, maxit, 1 if precond else 0, _dp(hist), C.byref(it))
         return x, st, it.value, hist[: it.value + 1].copy()
 
     def cg(self, b, tol=1e-13, maxit=100000, jacobi=True):

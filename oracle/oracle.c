@@ -1198,6 +1198,105 @@ int orc_solve(orc *s, const double *b, double *x, double tol, int maxit, double 
   return ORC_EMAXIT;
 }
 
+static double dotv(const double *a, const double *b, int n) {
+  double t = 0.0;
+  for (int i = 0; i < n; ++i) t += a[i] * b[i];
+  return t;
+}
+
+/* z = M^{-1} v for the preconditioner of orc_bicgstab: one V-cycle on A z = v
+ * from z = 0 (precond != 0), or z = v (precond == 0). */
+static void bicg_precond(orc *s, int precond, const double *v, double *z, double *w) {
+  int n = s->n;
+  if (!precond) {
+    memcpy(z, v, sizeof(double) * n);
+    return;
+  }
+  memset(z, 0, sizeof(double) * n);
+  memcpy(w, v, sizeof(double) * n); /* residual of z = 0 */
+  orc_vcycle(s, v, z, w);
+}
+
+/* BiCGSTAB (van der Vorst) on A u = f, right-preconditioned by one p-multigrid
+ * V-cycle per preconditioning phase (Section 5: the method as a preconditioner
+ * of a Krylov solver for non-symmetric problems, one V-cycle applied in each
+ * preconditioning phase).  Shadow residual r^ = r_0.  One iteration:
+ *   rho = (r^, r);  beta = (rho / rho_prev) (alpha / omega)
+ *   p = r + beta (p - omega v);  y = M^{-1} p;  v = A y;  alpha = rho / (r^, v)
+ *   s = r - alpha v;  x += alpha y;  z = M^{-1} s;  t = A z
+ *   omega = (t, s) / (t, t)  (0 when t = 0, i.e. s = 0);  x += omega z;  r = s - omega t
+ * with rho_prev = alpha = omega = 1 and p = v = 0 at the start.  Stops when
+ * ||r|| / ||r_0|| <= tol (hist[k] as for orc_solve); rho = 0 or (r^, v) = 0
+ * is a breakdown, reported as ORC_EDIVERGED. */
+int orc_bicgstab(orc *s, const double *b, double *x, double tol, int maxit, int precond, double *hist, int *iters) {
+  int n = s->n, rc = ORC_EMAXIT;
+  double *r = calloc(n, sizeof(double)), *rh = calloc(n, sizeof(double)), *pv = calloc(n, sizeof(double)),
+         *v = calloc(n, sizeof(double)), *y = calloc(n, sizeof(double)), *z = calloc(n, sizeof(double)),
+         *t = calloc(n, sizeof(double)), *w = calloc(n, sizeof(double));
+  residual(&s->A, b, x, r);
+  double r0 = norm2(r, n);
+  memcpy(rh, r, sizeof(double) * n);
+  double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+  *iters = 0;
+  if (hist) hist[0] = 1.0;
+  if (!isfinite(r0)) {
+    rc = ORC_ENAN;
+    goto done;
+  }
+  if (r0 == 0.0) {
+    rc = ORC_OK;
+    goto done;
+  }
+  for (int it = 1; it <= maxit; ++it) {
+    double rho = dotv(rh, r, n);
+    if (rho == 0.0) {
+      rc = ORC_EDIVERGED;
+      break;
+    }
+    double beta = (rho / rho_prev) * (alpha / omega);
+    for (int i = 0; i < n; ++i) pv[i] = r[i] + beta * (pv[i] - omega * v[i]);
+    bicg_precond(s, precond, pv, y, w);
+    csr_mv(&s->A, y, v);
+    double rv = dotv(rh, v, n);
+    if (rv == 0.0) {
+      rc = ORC_EDIVERGED;
+      break;
+    }
+    alpha = rho / rv;
+    for (int i = 0; i < n; ++i) {
+      r[i] -= alpha * v[i]; /* s */
+      x[i] += alpha * y[i];
+    }
+    bicg_precond(s, precond, r, z, w);
+    csr_mv(&s->A, z, t);
+    double tt = dotv(t, t, n);
+    omega = tt > 0.0 ? dotv(t, r, n) / tt : 0.0;
+    for (int i = 0; i < n; ++i) {
+      x[i] += omega * z[i];
+      r[i] -= omega * t[i];
+    }
+    rho_prev = rho;
+    double rel = norm2(r, n) / r0;
+    *iters = it;
+    if (hist) hist[it] = rel;
+    if (!isfinite(rel) || rel > 1e10) {
+      rc = ORC_EDIVERGED;
+      break;
+    }
+    if (rel <= tol) {
+      rc = ORC_OK;
+      break;
+    }
+    if (omega == 0.0) { /* s = 0 but the test above failed: cannot continue */
+      rc = ORC_EDIVERGED;
+      break;
+    }
+  }
+done:
+  free(r); free(rh); free(pv); free(v); free(y); free(z); free(t); free(w);
+  return rc;
+}
+
 /* Conjugate gradients on A u = f (an independent FP64 reference solution);
  * jacobi != 0 uses diag(A) as preconditioner.  Stops at ||r|| <= tol ||f||. */
 int orc_cg(orc *s, const double *b, double *x, double tol, int maxit, int jacobi, int *iters) {
