@@ -197,6 +197,22 @@ pmg_status pmg_vcycle(pmg_handle h, const double *b, double *x, double *r, doubl
 pmg_status pmg_solve(pmg_handle h, const double *b, double *x, double tol, pmg_result *res,
                      double *hist, void *stream);
 
+/* BiCGSTAB on A u = f, right-preconditioned by one p-multigrid V-cycle (from
+ * a zero initial guess) in each preconditioning phase (Section 5, the method
+ * as a preconditioner of a Krylov solver suited to its non-symmetric coarse
+ * correction; two V-cycles per iteration).  Textbook BiCGSTAB with shadow
+ * residual r_0:
+ *   rho = (r^, r); beta = (rho / rho_prev)(alpha / omega); p = r + beta (p - omega v)
+ *   y = M^{-1} p; v = A y; alpha = rho / (r^, v); s = r - alpha v; x += alpha y
+ *   z = M^{-1} s; t = A z; omega = (t, s)/(t, t) (0 if t = 0); x += omega z; r = s - omega t.
+ * FP64 throughout; the method's scalars stay on the device and the host
+ * reads ||r|| once per iteration.  Stops when ||r|| / ||r_0|| <= tol; hist
+ * (host, length max_iter + 1, or NULL) receives that ratio per iteration.
+ * Status as pmg_solve; a breakdown (rho = 0, or omega = 0 before
+ * convergence) and a non-finite residual give PMG_EDIVERGED. */
+pmg_status pmg_bicgstab(pmg_handle h, const double *b, double *x, double tol, pmg_result *res,
+                        double *hist, void *stream);
+
 /* Sizes, DAG depths, algorithmic bytes and setup times. */
 pmg_status pmg_get_info(pmg_handle h, pmg_info *info);
 

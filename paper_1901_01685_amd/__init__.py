@@ -114,6 +114,7 @@ SIGNATURES = {
     "pmg_export": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _I64P, _I32P, _DP]),
     "pmg_export_vec": (C.c_int, [_VP, C.c_int32, _DP]),
     "pmg_export_perm": (C.c_int, [_VP, _I32P]),
+    "pmg_bicgstab": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(Result), _DP, _VP]),
     "pmg_export_schedule": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _VP]),
     "pmg_server_default_options": (C.c_int, [C.POINTER(ServerOptions)]),
     "pmg_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(_VP)]),
@@ -269,6 +270,17 @@ class Solver:
         hist = np.zeros(int(self.options.max_iter) + 1)
         st = lib().pmg_solve(self._h, _ptr(b), _ptr(x), tol, C.byref(res),
                              hist.ctypes.data_as(_DP), _stream(stream))
+        if check and st not in (OK, EMAXIT, EDIVERGED, ENAN):
+            _check(st)
+        return st, res.iterations, res.relres, res.r0, res.seconds, hist[: res.iterations + 1].copy()
+
+    def bicgstab(self, b, x, tol=1e-8, stream=None, check=True):
+        """BiCGSTAB preconditioned by one V-cycle per preconditioning phase;
+        returns (status, iterations, relres, r0, seconds, hist)."""
+        res = Result()
+        hist = np.zeros(int(self.options.max_iter) + 1)
+        st = lib().pmg_bicgstab(self._h, _ptr(b), _ptr(x), tol, C.byref(res),
+                                hist.ctypes.data_as(_DP), _stream(stream))
         if check and st not in (OK, EMAXIT, EDIVERGED, ENAN):
             _check(st)
         return st, res.iterations, res.relres, res.r0, res.seconds, hist[: res.iterations + 1].copy()

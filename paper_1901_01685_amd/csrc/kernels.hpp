@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
   }
 }
 
-// Residual r = b - A x with A in stencil layout.  With the tensor-product
+// Residual r = b - A x (PLAIN: r = A x) with A in stencil layout.  With the tensor-product
 // B-spline basis of degree p, row i (grid position (ix, iy, iz), x fastest,
 // nx * ny per plane) couples only to the rows at offsets |dx|, |dy|, |dz| <=
 // p; the value of offset k of row i is V[k * n + i] (k lexicographic in
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
 // are stored and both V and x are read contiguously across a wave's rows.
 // Sums run over dz, dy, dx ascending; block partials of sum(r^2) as for the
 // CSR residual.
-template <typename T, int DIM>
+template <typename T, int DIM, bool PLAIN = false>
 __global__ __launch_bounds__(256) void stencil_resid(int n, int nx, int ny, int p, const T* __restrict__ V,
                                                      const T* __restrict__ x, const T* __restrict__ b,
                                                      T* __restrict__ r, double* __restrict__ partial) {
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void stencil_resid(int n, int nx, int ny, int 
         const T* xr = x + i + (dz * ny + dy) * nx;
         for (int dx = dx0; dx <= dx1; ++dx) acc += vr[(int64_t)dx * n] * xr[dx];
       }
-    const T res = b[i] - acc;
+    const T res = PLAIN ? acc : b[i] - acc;  // PLAIN: r = A x
     r[i] = res;
     sq += (double)res * (double)res;
   }
@@ -157,6 +157,118 @@ __global__ __launch_bounds__(256) void xgrid_spmv(int nrow, int nxr, int nxc, in
       }
     out[i] = ADD ? out[i] + d[i] * acc : d[i] * acc;
   }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB vector steps.  The method's scalars live in device memory
+// (S[0] rho, S[1] previous rho, S[2] alpha, S[3] omega, S[4] (r^, v),
+// S[5] (t, s), S[6] (t, t), S[7] ||r||^2); each kernel derives the scalars it
+// needs from them, so an iteration needs the host only for the stopping test.
+// Dot products are block partials in a fixed tree order (bit-reproducible).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_sum2(double a, double b, double* pa, double* pb) {
+  __shared__ double ra[256], rb[256];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      ra[threadIdx.x] += ra[threadIdx.x + k];
+      rb[threadIdx.x] += rb[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pa[blockIdx.x] = ra[0];
+    if (pb) pb[blockIdx.x] = rb[0];
+  }
+}
+
+// S[0] = rho = ||r_0||^2 (from the residual norm), S[1..3] = 1 (one thread)
+__global__ void bicg_init(const double* __restrict__ rr, double* S) {
+  S[0] = rr[0];
+  S[1] = S[2] = S[3] = 1.0;
+  S[4] = S[5] = S[6] = 0.0;
+  S[7] = rr[0];
+}
+
+// partials of (a, b) and, if c, of (c, d)
+__global__ __launch_bounds__(256) void dot2_partials(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                                     const double* __restrict__ c, const double* __restrict__ d,
+                                                     double* __restrict__ pa, double* __restrict__ pb) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    s1 += a[i] * b[i];
+    if (c) s2 += c[i] * d[i];
+  }
+  block_sum2(s1, s2, pa, c ? pb : nullptr);
+}
+
+// S[ia] = sum of pa (and S[ib] = sum of pb if ib >= 0); with shift_rho the
+// old S[0] is first saved in S[1].  One block.
+__global__ __launch_bounds__(256) void bicg_reduce(int nb, const double* __restrict__ pa, const double* __restrict__ pb,
+                                                   double* S, int ia, int ib, int shift_rho) {
+  __shared__ double ra[256], rb[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a += pa[i];
+    if (ib >= 0) b += pb[i];
+  }
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      ra[threadIdx.x] += ra[threadIdx.x + k];
+      rb[threadIdx.x] += rb[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (shift_rho) S[1] = S[0];
+    S[ia] = ra[0];
+    if (ib >= 0) S[ib] = rb[0];
+  }
+}
+
+// p = r + beta (p - omega v), beta = (rho / rho_prev) (alpha / omega)
+__global__ __launch_bounds__(256) void bicg_p(int64_t n, const double* __restrict__ S, const double* __restrict__ r,
+                                              const double* __restrict__ v, double* __restrict__ p) {
+  const double beta = (S[0] / S[1]) * (S[2] / S[3]), omega = S[3];
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// alpha = rho / (r^, v); s = r - alpha v (over r); x += alpha y
+__global__ __launch_bounds__(256) void bicg_s(int64_t n, double* S, const double* __restrict__ v,
+                                              const double* __restrict__ y, double* __restrict__ r,
+                                              double* __restrict__ x) {
+  const double alpha = S[0] / S[4];
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    r[i] -= alpha * v[i];
+    x[i] += alpha * y[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) S[2] = alpha;
+}
+
+// omega = (t, s) / (t, t) (0 if t = 0); x += omega z; r = s - omega t (s is
+// in r); partials of (r, r) and (r^, r) for the stopping test and next rho
+__global__ __launch_bounds__(256) void bicg_x(int64_t n, double* S, const double* __restrict__ z,
+                                              const double* __restrict__ t, const double* __restrict__ rh,
+                                              double* __restrict__ x, double* __restrict__ r, double* __restrict__ pa,
+                                              double* __restrict__ pb) {
+  const double omega = S[6] > 0.0 ? S[5] / S[6] : 0.0;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] += omega * z[i];
+    const double ri = r[i] - omega * t[i];
+    r[i] = ri;
+    s1 += ri * ri;
+    s2 += rh[i] * ri;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) S[3] = omega;
+  block_sum2(s1, s2, pa, pb);
 }
 
 // Sums n block partials in a fixed order into out[0] (one block).
@@ -315,45 +427,57 @@ __global__ __launch_bounds__(256) void grid_restrict(int nc, const double* __res
   ec[C] = 0.0;
 }
 
-// e_f += P_h ec: fine node f along an axis takes coarse (f-1)/2 with weight 1
-// if f is odd, else coarse f/2 - 1 and f/2 (those that exist) with 1/2.
+// (P_h ec) at fine node F: along an axis fine node f takes coarse (f-1)/2 with
+// weight 1 if f is odd, else coarse f/2 - 1 and f/2 (those that exist) with
+// 1/2.  Written with two parents per axis (a missing one has weight 0 and adds
+// an exact zero), so the indices stay in registers.
+template <int DIM>
+__device__ __forceinline__ double prolong_at(int nc, int F, const double* ec) {
+  const int nf = 2 * nc + 1;
+  const int f[3] = {F % nf, (F / nf) % nf, DIM == 3 ? F / (nf * nf) : 0};
+  int c0[3], c1[3];
+  double w0[3], w1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a == 2 && DIM == 2) {
+      c0[a] = c1[a] = 0;
+      w0[a] = 1.0;
+      w1[a] = 0.0;
+    } else if (f[a] & 1) {
+      c0[a] = c1[a] = (f[a] - 1) / 2;
+      w0[a] = 1.0;
+      w1[a] = 0.0;
+    } else {
+      const int lo = f[a] / 2 - 1, hi = f[a] / 2;
+      c0[a] = lo >= 0 ? lo : 0;
+      w0[a] = lo >= 0 ? 0.5 : 0.0;
+      c1[a] = hi < nc ? hi : 0;
+      w1[a] = hi < nc ? 0.5 : 0.0;
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int kz = 0; kz < (DIM == 3 ? 2 : 1); ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx) {
+        const double w = (kz ? w1[2] : w0[2]) * (ky ? w1[1] : w0[1]) * (kx ? w1[0] : w0[0]);
+        const int c = ((kz ? c1[2] : c0[2]) * nc + (ky ? c1[1] : c0[1])) * nc + (kx ? c1[0] : c0[0]);
+        acc += w * ec[c];
+      }
+  return acc;
+}
+
+// e_f += P_h ec (canonical prolongation, see prolong_at); nf = 2 nc + 1 fine
+// nodes per axis.
 template <int DIM>
 __global__ __launch_bounds__(256) void grid_prolong_add(int nc, const double* __restrict__ ec, double* __restrict__ ef) {
   const int nf = 2 * nc + 1;
   const int F = blockIdx.x * 256 + threadIdx.x;
   const int nfine = DIM == 3 ? nf * nf * nf : nf * nf;
   if (F >= nfine) return;
-  const int f[3] = {F % nf, (F / nf) % nf, DIM == 3 ? F / (nf * nf) : 0};
-  int cs[3][2], m[3];
-  double ws[3][2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    m[a] = 0;
-    if (a == 2 && DIM == 2) {
-      cs[a][0] = 0;
-      ws[a][0] = 1.0;
-      m[a] = 1;
-    } else if (f[a] & 1) {
-      cs[a][0] = (f[a] - 1) / 2;
-      ws[a][0] = 1.0;
-      m[a] = 1;
-    } else {
-      if (f[a] / 2 - 1 >= 0) {
-        cs[a][m[a]] = f[a] / 2 - 1;
-        ws[a][m[a]++] = 0.5;
-      }
-      if (f[a] / 2 < nc) {
-        cs[a][m[a]] = f[a] / 2;
-        ws[a][m[a]++] = 0.5;
-      }
-    }
-  }
-  double acc = 0.0;
-  for (int a2 = 0; a2 < m[2]; ++a2)
-    for (int a1 = 0; a1 < m[1]; ++a1)
-      for (int a0 = 0; a0 < m[0]; ++a0)
-        acc += (ws[2][a2] * ws[1][a1] * ws[0][a0]) * ec[((size_t)cs[2][a2] * nc + cs[1][a1]) * nc + cs[0][a0]];
-  ef[F] += acc;
+  ef[F] += prolong_at<DIM>(nc, F, ec);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,38 +622,7 @@ __global__ __launch_bounds__(kLdsThreads) void hcycle_lds(LdsCycle S) {
     const int nfine = DIM == 3 ? nf * nf * nf : nf * nf;
     const double* ec = sm + S.eoff[k + 1];
     double* ef = sm + S.eoff[k];
-    for (int F = tid; F < nfine; F += kLdsThreads) {
-      const int f[3] = {F % nf, (F / nf) % nf, DIM == 3 ? F / (nf * nf) : 0};
-      int cs[3][2], m[3];
-      double ws[3][2];
-      for (int a = 0; a < 3; ++a) {
-        m[a] = 0;
-        if (a == 2 && DIM == 2) {
-          cs[a][0] = 0;
-          ws[a][0] = 1.0;
-          m[a] = 1;
-        } else if (f[a] & 1) {
-          cs[a][0] = (f[a] - 1) / 2;
-          ws[a][0] = 1.0;
-          m[a] = 1;
-        } else {
-          if (f[a] / 2 - 1 >= 0) {
-            cs[a][m[a]] = f[a] / 2 - 1;
-            ws[a][m[a]++] = 0.5;
-          }
-          if (f[a] / 2 < nc) {
-            cs[a][m[a]] = f[a] / 2;
-            ws[a][m[a]++] = 0.5;
-          }
-        }
-      }
-      double acc = 0.0;
-      for (int a2 = 0; a2 < m[2]; ++a2)
-        for (int a1 = 0; a1 < m[1]; ++a1)
-          for (int a0 = 0; a0 < m[0]; ++a0)
-            acc += (ws[2][a2] * ws[1][a1] * ws[0][a0]) * ec[(cs[2][a2] * nc + cs[1][a1]) * nc + cs[0][a0]];
-      ef[F] += acc;
-    }
+    for (int F = tid; F < nfine; F += kLdsThreads) ef[F] += prolong_at<DIM>(nc, F, ec);
     __syncthreads();
     lds_sweeps<DIM>(S, k, sm, S.nu2);
   }

@@ -941,7 +941,8 @@ void enqueue_norm_readback(Workspace& ws, hipStream_t st) {
 }
 
 // One FP64 V-cycle; r holds b - A x on entry and exit.
-void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st) {
+void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st,
+              bool final_resid) {
   const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
   for (int k = 0; k < nu1; ++k) {
     smooth_impl<double>(h, ws, r, x, ws.y, ws.e, st);
@@ -951,13 +952,73 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
     restrict64(h, r, ws.r1, st);
     coarse_impl(h, ws, ws.r1, ws.e1, st);
     prolong64(h, ws.e1, x, st);
-    residual64(h, ws, b, x, r, nu2 == 0 && norm, st);
+    if (nu2 > 0 || final_resid) residual64(h, ws, b, x, r, nu2 == 0 && norm, st);
   }
   for (int k = 0; k < nu2; ++k) {
     smooth_impl<double>(h, ws, r, x, ws.y, ws.e, st);
-    residual64(h, ws, b, x, r, k == nu2 - 1 && norm, st);
+    if (k + 1 < nu2 || final_resid) residual64(h, ws, b, x, r, k == nu2 - 1 && norm, st);
   }
-  if (nu2 == 0 && h->H.n1 == 0) residual64(h, ws, b, x, r, norm, st);
+  if (nu2 == 0 && h->H.n1 == 0 && final_resid) residual64(h, ws, b, x, r, norm, st);
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB right-preconditioned by one V-cycle (pmg_bicgstab).
+
+// y = A x (plain product, FP64)
+void matvec_a(pmg_handle h, Workspace& ws, const double* x, double* y, hipStream_t st) {
+  const DevStencil& S = h->As;
+  if (S.v) {
+    const int n = h->A.nrows;
+    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    if (S.dim == 2)
+      pmg::stencil_resid<double, 2, true><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, S.v, x, x, y, ws.partial);
+    else
+      pmg::stencil_resid<double, 3, true><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, S.v, x, x, y, ws.partial);
+    return;
+  }
+  csr_launch<double>(pmg::kPlain, h->A.nrows, nullptr, h->A, h->A.v, x, nullptr, nullptr, y, nullptr, st);
+}
+
+pmg_status alloc_bicg(pmg_handle h, Workspace& ws) {
+  if (ws.bc_S) return PMG_OK;
+  const int64_t n = h->H.n;
+  DevArena& m = ws.mem;
+  pmg_status s;
+  for (double** v : {&ws.bc_rh, &ws.bc_p, &ws.bc_v, &ws.bc_y, &ws.bc_z, &ws.bc_t, &ws.bc_w})
+    if ((s = m.alloc(v, n))) return s;
+  if ((s = m.alloc(&ws.bc_S, 8))) return s;
+  if ((s = m.alloc(&ws.bc_pa, kMaxCsrBlocks))) return s;
+  if ((s = m.alloc(&ws.bc_pb, kMaxCsrBlocks))) return s;
+  PMG_HIP_OK(hipHostMalloc((void**)&ws.bc_host, 8 * sizeof(double), hipHostMallocDefault));
+  return PMG_OK;
+}
+
+// z = M^{-1} v: one V-cycle on A z = v from z = 0 (w: residual scratch)
+void bicg_precond(pmg_handle h, Workspace& ws, const double* v, double* z, double* w, hipStream_t st) {
+  const int64_t n = h->H.n;
+  fill<double>(z, n, 0.0, st);
+  pmg::cast_kernel<double, double><<<nblocks(n, 256), 256, 0, st>>>(n, v, w);  // copy (a kernel, graph-safe)
+  vcycle64(h, ws, v, z, w, false, st, false);
+}
+
+// One BiCGSTAB iteration (the steps of the textbook method, as listed with
+// pmg_bicgstab), all on st; the residual lives in ws.r.
+void bicg_iteration(pmg_handle h, Workspace& ws, double* x, hipStream_t st) {
+  const int64_t n = h->H.n;
+  const unsigned g = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+  double* S = ws.bc_S;
+  pmg::bicg_p<<<g, 256, 0, st>>>(n, S, ws.r, ws.bc_v, ws.bc_p);
+  bicg_precond(h, ws, ws.bc_p, ws.bc_y, ws.bc_w, st);
+  matvec_a(h, ws, ws.bc_y, ws.bc_v, st);
+  pmg::dot2_partials<<<g, 256, 0, st>>>(n, ws.bc_rh, ws.bc_v, nullptr, nullptr, ws.bc_pa, ws.bc_pb);
+  pmg::bicg_reduce<<<1, 256, 0, st>>>((int)g, ws.bc_pa, ws.bc_pb, S, 4, -1, 0);
+  pmg::bicg_s<<<g, 256, 0, st>>>(n, S, ws.bc_v, ws.bc_y, ws.r, x);
+  bicg_precond(h, ws, ws.r, ws.bc_z, ws.bc_w, st);
+  matvec_a(h, ws, ws.bc_z, ws.bc_t, st);
+  pmg::dot2_partials<<<g, 256, 0, st>>>(n, ws.bc_t, ws.r, ws.bc_t, ws.bc_t, ws.bc_pa, ws.bc_pb);
+  pmg::bicg_reduce<<<1, 256, 0, st>>>((int)g, ws.bc_pa, ws.bc_pb, S, 5, 6, 0);
+  pmg::bicg_x<<<g, 256, 0, st>>>(n, S, ws.bc_z, ws.bc_t, ws.bc_rh, x, ws.r, ws.bc_pa, ws.bc_pb);
+  pmg::bicg_reduce<<<1, 256, 0, st>>>((int)g, ws.bc_pa, ws.bc_pb, S, 7, 0, 1);
 }
 
 // Captures the step enqueued by `enqueue` into ws.gexec; false if capture or
@@ -991,20 +1052,14 @@ bool capture_step(Workspace& ws, F&& enqueue) {
   return true;
 }
 
-void outer_step(pmg_handle h, Workspace& ws, bool mixed, const double* b, double* x, double* r, bool norm,
-                hipStream_t st) {
-  auto enqueue = [&](hipStream_t s) {
-    if (mixed)
-      mixed_step(h, ws, b, x, s);
-    else
-      vcycle64(h, ws, b, x, r, norm, s);
-  };
+// Enqueues the work of `enqueue` on st, from the graph cached in ws when the
+// key matches (capturing it first otherwise), or kernel by kernel.
+template <typename F>
+void run_cached(pmg_handle h, Workspace& ws, const void* const (&key)[5], F&& enqueue, hipStream_t st) {
   if (!h->opt.graphs || h->profiling || ws.graph_failed) {
     enqueue(st);
     return;
   }
-  const intptr_t kind = mixed ? 2 : (norm ? 1 : 0);
-  const void* key[5] = {h, (const void*)kind, b, x, mixed ? ws.r : r};
   if (!ws.gexec || !std::equal(key, key + 5, ws.gkey)) {
     if (!capture_step(ws, enqueue)) {
       ws.graph_failed = true;
@@ -1018,6 +1073,19 @@ void outer_step(pmg_handle h, Workspace& ws, bool mixed, const double* b, double
     ws.graph_failed = true;
     enqueue(st);
   }
+}
+
+void outer_step(pmg_handle h, Workspace& ws, bool mixed, const double* b, double* x, double* r, bool norm,
+                hipStream_t st) {
+  auto enqueue = [&](hipStream_t s) {
+    if (mixed)
+      mixed_step(h, ws, b, x, s);
+    else
+      vcycle64(h, ws, b, x, r, norm, s);
+  };
+  const intptr_t kind = mixed ? 2 : (norm ? 1 : 0);
+  const void* const key[5] = {h, (const void*)kind, b, x, mixed ? ws.r : r};
+  run_cached(h, ws, key, enqueue, st);
 }
 
 void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st) {
@@ -1521,6 +1589,67 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
       }
       if (rel <= tol) {
         status = PMG_OK;
+        break;
+      }
+    }
+  }
+  R.status = status;
+  R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (res) *res = R;
+  if (status != PMG_OK) pmgdev::set_error(pmg_status_str(status));
+  return status;
+}
+
+pmg_status pmg_bicgstab(pmg_handle h, const double* b, double* x, double tol, pmg_result* res, double* hist,
+                        void* stream) {
+  NEED_DEVICE(h);
+  if (!b || !x || !(tol >= 0)) return fail(PMG_EINVAL, "invalid argument");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = h->ws;
+  pmg_status s;
+  if ((s = pmgdev::alloc_bicg(h, ws))) return s;
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = h->H.n;
+  pmg_result R{};
+  // r = b - A x, r^ = r, rho = (r^, r) = ||r||^2, rho_prev = alpha = omega = 1, p = v = 0
+  pmgdev::residual64(h, ws, b, x, ws.r, true, st);
+  pmg::cast_kernel<double, double><<<nblocks(n, 256), 256, 0, st>>>(n, ws.r, ws.bc_rh);
+  fill<double>(ws.bc_p, n, 0.0, st);
+  fill<double>(ws.bc_v, n, 0.0, st);
+  pmg::bicg_init<<<1, 1, 0, st>>>(ws.scalar, ws.bc_S);
+  PMG_HIP_OK(hipGetLastError());
+  const double r0 = read_norm(ws, st);
+  R.r0 = r0;
+  R.relres = 1.0;
+  if (hist) hist[0] = 1.0;
+  pmg_status status = PMG_EMAXIT;
+  if (!std::isfinite(r0)) {
+    status = PMG_ENAN;
+  } else if (r0 == 0.0) {
+    status = PMG_OK;
+    R.relres = 0.0;
+  } else {
+    const void* const key[5] = {h, (const void*)(intptr_t)3, b, x, ws.bc_S};
+    for (int it = 1; it <= h->opt.max_iter; ++it) {
+      pmgdev::run_cached(h, ws, key, [&](hipStream_t q) { pmgdev::bicg_iteration(h, ws, x, q); }, st);
+      PMG_HIP_OK(hipMemcpyAsync(ws.bc_host, ws.bc_S, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+      PMG_HIP_OK(hipStreamSynchronize(st));
+      const double rel = std::sqrt(ws.bc_host[7]) / r0;
+      R.iterations = it;
+      R.relres = rel;
+      if (hist) hist[it] = rel;
+      if (!std::isfinite(rel) || rel > h->opt.diverge_ratio) {
+        status = PMG_EDIVERGED;
+        break;
+      }
+      if (rel <= tol) {
+        status = PMG_OK;
+        break;
+      }
+      // omega = 0 (s = 0 without convergence) or rho = 0 for the next
+      // iteration: breakdown
+      if (ws.bc_host[3] == 0.0 || ws.bc_host[0] == 0.0) {
+        status = PMG_EDIVERGED;
         break;
       }
     }

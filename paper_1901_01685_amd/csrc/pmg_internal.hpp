@@ -110,6 +110,11 @@ struct Workspace {
   unsigned* tickets = nullptr;  // lower: [0] ticket, [1] exited waves; upper: [2], [3]
   float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *e32 = nullptr, *t32 = nullptr, *q32 = nullptr;
   bool mixed = false;
+  // BiCGSTAB (pmg_bicgstab): shadow residual, direction, A y, preconditioned
+  // vectors, A z, a residual scratch for the preconditioner, the device
+  // scalars (see pmg::bicg_*), block partials and a pinned host copy
+  double *bc_rh = nullptr, *bc_p = nullptr, *bc_v = nullptr, *bc_y = nullptr, *bc_z = nullptr, *bc_t = nullptr,
+         *bc_w = nullptr, *bc_S = nullptr, *bc_pa = nullptr, *bc_pb = nullptr, *bc_host = nullptr;
   // cached graph of one outer step (outer_step), captured on `cap` and valid
   // for the handle and vectors it was captured with
   hipStream_t cap = nullptr;
@@ -121,6 +126,7 @@ struct Workspace {
     if (cap) hipStreamDestroy(cap);
     mem.release();
     if (host_scalar) hipHostFree(host_scalar);
+    if (bc_host) hipHostFree(bc_host);
   }
 };
 
@@ -184,7 +190,10 @@ size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors);
 // Solve-phase steps on stream st with workspace ws.
 void residual64(pmg_handle h, Workspace& ws, const double* b, const double* x, double* r, bool norm,
                 hipStream_t st);
-void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st);
+// final_resid = false leaves r stale after the last smoothing step (a
+// V-cycle used as a preconditioner needs only x).
+void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r, bool norm, hipStream_t st,
+              bool final_resid = true);
 // One defect-correction step: r (FP64 residual, in ws.r) -> FP32 V-cycle ->
 // x += c -> r = b - A x and its norm (device scalar).
 void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st);
