@@ -752,12 +752,17 @@ __device__ __forceinline__ void stage_tile(T* tile, int (&jj)[kStage], T (&vv)[k
   }
 }
 
+// Off-chunk batches end at the last slot, so the last batch holds every
+// row's latest entries; the first may start before slot 0 (those read padding).
+__device__ __forceinline__ int first_batch(int w) { return w - (w + kTriBatch - 1) / kTriBatch * kTriBatch; }
+
 template <typename T>
 __device__ __forceinline__ void load_batch(int (&c)[kTriBatch], T (&a)[kTriBatch], int u0, int w, int base,
                                            int lane, const TriDev<T>& F) {
 #pragma unroll
   for (int u = 0; u < kTriBatch; ++u) {
-    const int i = u0 + u < w ? base + (u0 + u) * kWave + lane : F.off_pad + lane;
+    const int v = u0 + u;
+    const int i = v >= 0 && v < w ? base + v * kWave + lane : F.off_pad + lane;
     c[u] = F.off_col[i];
     a[u] = F.off_val[i];
   }
@@ -765,19 +770,21 @@ __device__ __forceinline__ void load_batch(int (&c)[kTriBatch], T (&a)[kTriBatch
 
 // t -= sum over the off-chunk slots of this lane of val * y[col], slot by
 // slot.  Entries still holding the marker are reloaded until they are final
-// (only those lanes issue loads).  The first batch was loaded into cc/aa by
-// the caller.
+// (only those lanes issue loads).  The first batch (from first_batch) was
+// loaded into cc/aa by the caller.  A row's entries fill its last slots, so
+// the entries that become final last all sit in the last batch and, once
+// they arrive, no further batch has to be loaded.
 template <typename T>
 __device__ __forceinline__ T gather_off(T t, int (&cc)[kTriBatch], T (&aa)[kTriBatch], const TriMeta& m, int lane,
                                         const TriDev<T>& F, const T* y) {
   const T* zero = F.off_val + F.off_pad;  // padding reads a 0 here
-  for (int b = 0; b * kTriBatch < m.off_w; ++b) {
+  for (int u0 = first_batch(m.off_w); u0 < m.off_w; u0 += kTriBatch) {
     T yy[kTriBatch];
 #pragma unroll
     for (int u = 0; u < kTriBatch; ++u) yy[u] = ld_dev(cc[u] >= 0 ? y + cc[u] : zero);
     int cn[kTriBatch];
     T an[kTriBatch];
-    load_batch(cn, an, (b + 1) * kTriBatch, m.off_w, m.off_ptr, lane, F);
+    load_batch(cn, an, u0 + kTriBatch, m.off_w, m.off_ptr, lane, F);
     for (;;) {
       bool nan = false;  // cheap first test: the marker is a NaN
 #pragma unroll
@@ -853,7 +860,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     const int pr = perm[act ? row : row - lane];  // lanes past the end read the chunk's first row
     int cc[kTriBatch];
     T aa[kTriBatch];
-    load_batch(cc, aa, 0, m.off_w, m.off_ptr, lane, F);
+    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F);
     int jj[kStage];
     T vv[kStage];
     load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F);
@@ -887,7 +894,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     const int pr = perm[ra];
     int cc[kTriBatch];
     T aa[kTriBatch];
-    load_batch(cc, aa, 0, m.off_w, m.off_ptr, lane, F);
+    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F);
     int jj[kStage];
     T vv[kStage];
     load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F);

@@ -271,8 +271,10 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
         return upper ? T.ci[ka] > T.ci[kb] : T.ci[ka] < T.ci[kb];
       });
     for (int l = 0; l < r1 - r0; ++l) {
+      // right-aligned: padding first, the row's entries in the last slots
+      const size_t pad = (size_t)S.off_w[q] - oc[l].size();
       for (size_t u = 0; u < oc[l].size(); ++u) {
-        const size_t o = S.off_ptr[q] + u * 64 + l;
+        const size_t o = S.off_ptr[q] + (pad + u) * 64 + l;
         S.off_col[o] = T.ci[oc[l][u]];
         S.off_val[o] = T.v[oc[l][u]];
       }

@@ -24,7 +24,9 @@ constexpr unsigned kPending32 = 0x7F80DEADu;
 //   Off-chunk entries: slot u of lane l at off_ptr[q] + 64 u + l for
 //   u < off_w[q], per row sorted by the level of the chunk holding the
 //   source row (ties: lower factor ascending columns, upper descending), so
-//   entries that are final early come first; padding has column -1, value 0.
+//   entries that are final early come first.  Each row's entries fill its
+//   last slots (right-aligned) and padding, column -1 and value 0, the first
+//   ones, so the entries every row waits for longest share the last slots.
 //   In-chunk entries: slot u of lane l at in_ptr[q] + 64 u + l for
 //   u < in_w[q], the position j of the source row inside the chunk (-1 for
 //   padding) and the value.  For the upper factor the value is divided by

@@ -52,6 +52,11 @@ def _emulate(s, factor, rhs):
         if 0 <= own_prev < nq and row0[own_prev] // seg == sg:
             assert own_prev in deps, "chunk %d does not wait for its segment's previous chunk" % q
         w, base = S["off_w"][q], S["off_ptr"][q]
+        if w:
+            # each row's entries fill its last slots: no padding after an entry
+            cw = S["off_col"][base:base + 64 * w].reshape(w, 64)
+            seen = np.maximum.accumulate(cw >= 0, axis=0)
+            assert not np.any(seen & (cw < 0)), "chunk %d: off-chunk slots are not right-aligned" % q
         t = np.zeros(64)
         t[:nrow] = rhs[r0:r0 + nrow]
         read = set()
