@@ -95,6 +95,11 @@ typedef struct {
   int32_t nd_leaf;          /* nested dissection: lines per undivided block (default 8) */
   int32_t graphs;           /* 1 (default): each outer step of pmg_vcycle / pmg_solve is
                                enqueued as a cached HIP graph; 0: kernel by kernel */
+  int32_t tiled_gs;         /* 1 (default): on 2-D degree-1 levels the Gauss-Seidel sweeps
+                               before the restriction run with the residual and the
+                               restriction as one tiled launch, and the prolongation with
+                               the sweeps after it (up to 2 sweeps each); 0: one launch
+                               per colour and per transfer.  Results are identical. */
 } pmg_options;
 
 typedef struct {

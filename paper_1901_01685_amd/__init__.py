@@ -44,7 +44,7 @@ class Options(C.Structure):
                 ("coarse_min_elems", C.c_int32), ("gs_variant", C.c_int32), ("precision", C.c_int32),
                 ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("tiled_gs", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -365,8 +365,12 @@ __device__ __forceinline__ double grid_dot(const GridLevel& L, const double* vc,
         const double a = vc[(size_t)k * cnt + t];
         if (dx == 0 && dy == 0 && dz == 0 && skip_centre) {
           *centre = a;
-        } else if (ok) {
-          acc += a * x[i + (dz * nx + dy) * nx + dx];
+        } else {
+          // branch-free, so all loads of the node are in flight together: a
+          // neighbour outside the grid reads the node itself with weight 0
+          // (acc + 0 * x is acc for finite x, and acc is never -0)
+          const double xv = x[ok ? i + (dz * nx + dy) * nx + dx : i];
+          acc += (ok ? a : 0.0) * xv;
         }
       }
   return acc;
@@ -481,6 +485,192 @@ __global__ __launch_bounds__(256) void grid_prolong_add(int nc, const double* __
 }
 
 // ---------------------------------------------------------------------------
+// Tiled smoothing on 2-D structured degree-1 levels.
+//
+// The launch-per-colour path costs a launch per colour phase, which on the
+// middle levels is most of the time.  Here a workgroup owns the fine nodes
+// 2 C0 .. 2 C1 - 1 per axis under a block C0 .. C1 - 1 of coarse nodes (the
+// last block also the last fine node) and runs all colour phases of the
+// sweeps in LDS on that block widened by a halo: each phase updates a region
+// one node narrower than the one before, so the nodes the block needs at the
+// end hold exactly the values of the launch-per-colour sweeps (halo nodes are
+// computed again by the neighbouring blocks, from the same inputs with the
+// same arithmetic).  The iterate is read from one buffer and written to
+// another, so no block reads a value another block has already replaced.
+// gs_tile_down fuses the pre-smoothing sweeps with the residual and the
+// restriction after them, gs_tile_up the prolongation with the
+// post-smoothing sweeps after it.  Results are identical to the
+// launch-per-phase kernels.
+// ---------------------------------------------------------------------------
+
+constexpr int kTileThreads = 256;
+constexpr int kTileMaxSweeps = 2;  // sweeps per launch (the halo grows with them)
+
+struct TileBox {
+  int f0x, f1x, f0y, f1y;  // owned fine nodes [f0, f1)
+  int c0x, c1x, c0y, c1y;  // coarse nodes of the block [c0, c1)
+  int ox, oy, w;           // LDS origin and row length of the iterate tile
+};
+
+__device__ __forceinline__ TileBox tile_box(int nc, int tcb, int halo) {
+  const int ntx = (nc + tcb - 1) / tcb;
+  const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+  const int nf = 2 * nc + 1;
+  TileBox B;
+  B.c0x = bx * tcb;
+  B.c1x = min(B.c0x + tcb, nc);
+  B.c0y = by * tcb;
+  B.c1y = min(B.c0y + tcb, nc);
+  B.f0x = 2 * B.c0x;
+  B.f1x = B.c1x == nc ? nf : 2 * B.c1x;
+  B.f0y = 2 * B.c0y;
+  B.f1y = B.c1y == nc ? nf : 2 * B.c1y;
+  B.ox = B.f0x - halo;
+  B.oy = B.f0y - halo;
+  B.w = 2 * tcb + 1 + 2 * halo;
+  return B;
+}
+
+// The stencil sum of grid_dot for node (ix, iy), neighbours from the LDS tile.
+__device__ __forceinline__ double tile_dot(const GridLevel& L, int ix, int iy, const double* el, const TileBox& B,
+                                           bool skip_centre, double* centre) {
+  const int c = (ix & 1) | ((iy & 1) << 1);
+  const int mx = (L.nx - (c & 1) + 1) / 2;
+  const int t = (iy >> 1) * mx + (ix >> 1);
+  const int cnt = L.cnt[c];
+  const double* vc = L.v + L.voff[c];
+  const int nx = L.nx;
+  const double* x = el + (iy - B.oy) * B.w + (ix - B.ox);
+  double acc = 0.0;
+  int k = 0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx, ++k) {
+      const bool ok = ix + dx >= 0 && ix + dx < nx && iy + dy >= 0 && iy + dy < nx;
+      const double a = vc[(size_t)k * cnt + t];
+      if (dx == 0 && dy == 0 && skip_centre) {
+        *centre = a;
+      } else {
+        // branch-free as in grid_dot: a neighbour outside the grid reads the
+        // node itself with weight 0
+        const double xv = x[ok ? dy * B.w + dx : 0];
+        acc += (ok ? a : 0.0) * xv;
+      }
+    }
+  return acc;
+}
+
+// Colour phases of nsweep sweeps; after them the nodes within `hend` of the
+// owned range hold their final values.
+__device__ __forceinline__ void tile_sweeps(const GridLevel& L, int colors, int nsweep, int hend,
+                                            const double* __restrict__ b, double* el, const TileBox& B) {
+  const int nf = L.nx, K = colors * nsweep;
+  for (int k = 0; k < K; ++k) {
+    const int c = k % colors, h = hend + K - 1 - k;
+    const int x0 = max(B.f0x - h, 0), x1 = min(B.f1x + h, nf);
+    const int y0 = max(B.f0y - h, 0), y1 = min(B.f1y + h, nf);
+    const int xs = x0 + ((x0 & 1) != (c & 1)), ys = y0 + ((y0 & 1) != ((c >> 1) & 1));
+    const int mxr = xs < x1 ? (x1 - xs + 1) / 2 : 0, myr = ys < y1 ? (y1 - ys + 1) / 2 : 0;
+#pragma unroll 2
+    for (int t = threadIdx.x; t < mxr * myr; t += kTileThreads) {
+      const int ix = xs + 2 * (t % mxr), iy = ys + 2 * (t / mxr);
+      double centre = 1.0;
+      const double acc = tile_dot(L, ix, iy, el, B, true, &centre);
+      el[(iy - B.oy) * B.w + (ix - B.ox)] = (b[iy * nf + ix] - acc) / centre;
+    }
+    __syncthreads();
+  }
+}
+
+// Pre-smoothing (nsweep sweeps of e_in, result in e_out), then bc = R_h (b - A e)
+// and ec = 0 on the coarse level.  tcb coarse nodes per block side.
+__global__ __launch_bounds__(kTileThreads) void gs_tile_down(GridLevel L, int nc, int tcb, int colors, int nsweep,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ e_in,
+                                                             double* __restrict__ e_out, double* __restrict__ bc,
+                                                             double* __restrict__ ec) {
+  extern __shared__ double sm[];
+  constexpr int hend = 2;  // the residual reaches one node past the block and reads one further
+  const int halo = hend + colors * nsweep;
+  const TileBox B = tile_box(nc, tcb, halo);
+  const int nf = L.nx;
+  double* el = sm;
+  double* rl = sm + B.w * B.w;
+  const int rw = 2 * tcb + 1;
+  {
+    const int x0 = max(B.ox, 0), x1 = min(B.f1x + halo, nf), y0 = max(B.oy, 0), y1 = min(B.f1y + halo, nf);
+    const int mw = x1 - x0;
+    for (int t = threadIdx.x; t < mw * (y1 - y0); t += kTileThreads) {
+      const int ix = x0 + t % mw, iy = y0 + t / mw;
+      el[(iy - B.oy) * B.w + (ix - B.ox)] = e_in[iy * nf + ix];
+    }
+  }
+  __syncthreads();
+  tile_sweeps(L, colors, nsweep, hend, b, el, B);
+  // residual at fine nodes 2 C0 .. 2 C1 (the block's restriction stencils)
+  {
+    const int x1 = min(2 * B.c1x + 1, nf), y1 = min(2 * B.c1y + 1, nf);
+    const int mw = x1 - B.f0x;
+    for (int t = threadIdx.x; t < mw * (y1 - B.f0y); t += kTileThreads) {
+      const int ix = B.f0x + t % mw, iy = B.f0y + t / mw;
+      rl[(iy - B.f0y) * rw + (ix - B.f0x)] = b[iy * nf + ix] - tile_dot(L, ix, iy, el, B, false, nullptr);
+    }
+  }
+  __syncthreads();
+  {
+    const double w[3] = {0.5, 1.0, 0.5};
+    const int mc = B.c1x - B.c0x;
+    for (int t = threadIdx.x; t < mc * (B.c1y - B.c0y); t += kTileThreads) {
+      const int cx = B.c0x + t % mc, cy = B.c0y + t / mc;
+      const double* r = rl + 2 * (cy - B.c0y) * rw + 2 * (cx - B.c0x);
+      const double wz = 1.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc += (wz * w[bb] * w[cc]) * r[bb * rw + cc];
+      bc[cy * nc + cx] = acc;
+      ec[cy * nc + cx] = 0.0;
+    }
+    const int mw = B.f1x - B.f0x;
+    for (int t = threadIdx.x; t < mw * (B.f1y - B.f0y); t += kTileThreads) {
+      const int ix = B.f0x + t % mw, iy = B.f0y + t / mw;
+      e_out[iy * nf + ix] = el[(iy - B.oy) * B.w + (ix - B.ox)];
+    }
+  }
+}
+
+// e_out = nsweep post-smoothing sweeps of (e_in + P_h ec).
+__global__ __launch_bounds__(kTileThreads) void gs_tile_up(GridLevel L, int nc, int tcb, int colors, int nsweep,
+                                                           const double* __restrict__ b,
+                                                           const double* __restrict__ e_in,
+                                                           const double* __restrict__ ec,
+                                                           double* __restrict__ e_out) {
+  extern __shared__ double sm[];
+  const int halo = colors * nsweep;
+  const TileBox B = tile_box(nc, tcb, halo);
+  const int nf = L.nx;
+  double* el = sm;
+  {
+    const int x0 = max(B.ox, 0), x1 = min(B.f1x + halo, nf), y0 = max(B.oy, 0), y1 = min(B.f1y + halo, nf);
+    const int mw = x1 - x0;
+    for (int t = threadIdx.x; t < mw * (y1 - y0); t += kTileThreads) {
+      const int ix = x0 + t % mw, iy = y0 + t / mw;
+      const int F = iy * nf + ix;
+      el[(iy - B.oy) * B.w + (ix - B.ox)] = e_in[F] + prolong_at<2>(nc, F, ec);
+    }
+  }
+  __syncthreads();
+  tile_sweeps(L, colors, nsweep, 0, b, el, B);
+  const int mw = B.f1x - B.f0x;
+  for (int t = threadIdx.x; t < mw * (B.f1y - B.f0y); t += kTileThreads) {
+    const int ix = B.f0x + t % mw, iy = B.f0y + t / mw;
+    e_out[iy * nf + ix] = el[(iy - B.oy) * B.w + (ix - B.ox)];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The smallest levels of the structured h-multigrid V-cycle in one workgroup.
 //
 // Below a few thousand nodes a level's phases are too short to fill the GPU,
@@ -531,10 +721,12 @@ __device__ __forceinline__ double lds_dot(const GridLevel& L, const double* vc, 
       for (int dx = -1; dx <= 1; ++dx, ++k) {
         const bool ok = ix + dx >= 0 && ix + dx < nx && iy + dy >= 0 && iy + dy < nx &&
                         (DIM == 2 || (iz + dz >= 0 && iz + dz < nx));
-        if (dx == 0 && dy == 0 && dz == 0 && skip_centre)
+        if (dx == 0 && dy == 0 && dz == 0 && skip_centre) {
           *centre = a[k];
-        else if (ok)
-          acc += a[k] * x[grid_index<DIM>(nx, ix + dx, iy + dy, iz + dz)];
+        } else {
+          const double xv = x[ok ? grid_index<DIM>(nx, ix + dx, iy + dy, iz + dz) : grid_index<DIM>(nx, ix, iy, iz)];
+          acc += (ok ? a[k] : 0.0) * xv;  // as in grid_dot
+        }
       }
   return acc;
 }

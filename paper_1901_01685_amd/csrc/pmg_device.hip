@@ -736,6 +736,21 @@ void hcycle_lds(pmg_handle h, const double* b, double* e, hipStream_t st) {
 }
 
 // The h-multigrid V-cycle from level l on the structured grids (pmg::grid_*).
+// Tiled smoothing on 2-D structured levels (pmg::gs_tile_down / gs_tile_up).
+bool tiled_gs(pmg_handle h) {
+  return h->opt.tiled_gs && h->prob.dim == 2 && h->opt.nu1 <= pmg::kTileMaxSweeps &&
+         h->opt.nu2 <= pmg::kTileMaxSweeps;
+}
+
+// Coarse nodes per block side: blocks of up to 30 (about 300 blocks on the
+// finest levels, two per CU in LDS), at least 8 on the smaller levels.
+int tile_block(int nc) { return std::max(1, std::min(30, std::max(8, nc / 16))); }
+
+size_t tile_lds_bytes(int tcb, int colors, int nsweep, bool down) {
+  const int64_t halo = (down ? 2 : 0) + (int64_t)colors * nsweep, w = 2 * tcb + 1 + 2 * halo, rw = 2 * tcb + 1;
+  return (size_t)(w * w + (down ? rw * rw : 0)) * 8;
+}
+
 void hcycle_grid(pmg_handle h, Workspace& ws, int l, const double* b, double* e, hipStream_t st) {
   const pmg::HostOps& H = h->H;
   if (l == h->l_lds) {
@@ -748,6 +763,22 @@ void hcycle_grid(pmg_handle h, Workspace& ws, int l, const double* b, double* e,
   }
   const pmg::GridLevel& L = h->grid[l];
   const bool d3 = h->prob.dim == 3;
+  if (tiled_gs(h)) {
+    // pre-smoothing + residual + restriction, the coarser levels, then
+    // prolongation + post-smoothing; the iterate after the pre-smoothing
+    // lives in ws.hr[l] (no residual vector is needed on this path)
+    const int nc = H.lnel[l + 1] - 1;
+    const int tcb = tile_block(nc);
+    const int nblk = ((nc + tcb - 1) / tcb) * ((nc + tcb - 1) / tcb);
+    double* bc = ws.hb[l + 1];
+    double* ec = ws.he[l + 1];
+    pmg::gs_tile_down<<<nblk, pmg::kTileThreads, tile_lds_bytes(tcb, h->colors, h->opt.nu1, true), st>>>(
+        L, nc, tcb, h->colors, h->opt.nu1, b, e, ws.hr[l], bc, ec);
+    hcycle_grid(h, ws, l + 1, bc, ec, st);
+    pmg::gs_tile_up<<<nblk, pmg::kTileThreads, tile_lds_bytes(tcb, h->colors, h->opt.nu2, false), st>>>(
+        L, nc, tcb, h->colors, h->opt.nu2, b, ws.hr[l], ec, e);
+    return;
+  }
   auto sweeps = [&](int nsweep) {
     for (int sw = 0; sw < nsweep; ++sw)
       for (int c = 0; c < h->colors; ++c) {
@@ -1141,6 +1172,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->ordering = PMG_ORDER_NESTED_DISSECTION;
   o->nd_leaf = 8;
   o->graphs = 1;
+  o->tiled_gs = 1;
   return PMG_OK;
 }
 
@@ -1307,6 +1339,12 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
       }
     }
     if ((s = upload_grid_levels(m, H, prob->dim, h->grid))) return s;
+    if (!h->grid.empty() && tiled_gs(h.get())) {
+      const size_t dn = tile_lds_bytes(30, h->colors, pmg::kTileMaxSweeps, true);
+      const size_t up = tile_lds_bytes(30, h->colors, pmg::kTileMaxSweeps, false);
+      PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::gs_tile_down, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dn));
+      PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::gs_tile_up, hipFuncAttributeMaxDynamicSharedMemorySize, (int)up));
+    }
     // the smallest levels in one workgroup: from the coarsest upwards while
     // their iterates, right-hand sides and one residual fit 128 KiB of LDS
     if (!h->grid.empty()) {

@@ -76,12 +76,24 @@ def test_alone_and_in_the_mix_agree_and_match_oracle():
         # same request alone and in the mix: identical solutions
         assert np.array_equal(results[0][2], x_alone)
         assert np.array_equal(results[6][2], x_alone)
-        # the work overlapped: some request was admitted before another finished
-        infos = [r[1] for r in results]
+        # requests in flight together share the slots: a burst of requests of a
+        # resident class with right-hand sides given by the caller (so every
+        # submit returns at once) is admitted side by side, and equal inputs
+        # give equal results whatever the company
+        dim, p, nel, g, fr = MIX[0]
+        rng = np.random.default_rng(2)
+        bs = [rng.uniform(-1, 1, (nel + p - 2) ** dim) for _ in range(2)]
+        burst = [srv.submit(dim, p, nel, g, b=bs[k % 2]) for k in range(6)]
+        assert all(st == pmg.OK for st, _ in burst)
+        out = [srv.wait(t) for _, t in burst]
+        assert all(st == pmg.OK and info["relres"] <= 1e-10 for st, info, _ in out)
+        for k in range(2, 6):
+            assert np.array_equal(out[k][2], out[k % 2][2])
+        infos = [info for _, info, _ in out]
         assert any(a["t_admit"] < b["t_finish"] and b["t_admit"] < a["t_finish"]
                    for i, a in enumerate(infos) for b in infos[i + 1:])
         stt = srv.stats()
-        assert stt["completed"] == len(MIX) + 1 and stt["failed"] == 0
+        assert stt["completed"] == len(MIX) + 1 + len(burst) and stt["failed"] == 0
     finally:
         srv.close()
 
