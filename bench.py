@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "V-cycle DOF·iter/s + HBM GB/s frac; served solves/s, p50/p99 latency vs plain"
 
 # kernel class -> (kernel name in the rocprofv3 trace, info field of its bytes per launch)
-def kernel_map(info, dim):
+def kernel_map(info, dim, degree):
     """Residual and p-transfers use the stencil kernels whenever the library
     chose that layout (it reads fewer bytes than CSR), which shows in the
     algorithmic byte counts it reports."""
@@ -39,7 +39,10 @@ def kernel_map(info, dim):
     stencil_r = info.bytes_restrict != 12 * info.nnz_r + 4 * (info.n1 + 1) + 8 * info.n + 16 * info.n1
     stencil_p = info.bytes_prolong != 12 * info.nnz_p + 4 * (info.n + 1) + 8 * info.n1 + 24 * info.n
     return {
-        "residual": (f"stencil_resid<double, {dim}>" if stencil_a else "csr_kernel<double, G, 0>", "bytes_spmv"),
+        # the stencil kernel is instantiated per stencil width up to 11 (degree 5)
+        "residual": ((f"stencil_resid<double, {dim}, false, {2 * degree + 1}>" if degree <= 5
+                      else f"stencil_resid<double, {dim}, false, 0>") if stencil_a
+                     else "csr_kernel<double, G, 0>", "bytes_spmv"),
         "lower": ("trisolve_lower<double>", "bytes_trisolve_l"),
         "upper": ("trisolve_upper<double>", "bytes_trisolve_u"),
         "restrict": (f"xgrid_spmv<double, {dim}, false>" if stencil_r else "csr_kernel<double, G, 2>",
@@ -316,7 +319,7 @@ def main():
     s.profile_enable(False)
 
     # dominant kernel by total time per V-cycle
-    KERNELS = kernel_map(info, args.dim)
+    KERNELS = kernel_map(info, args.dim, args.degree)
     per_class = {c: (ms, cnt) for c, (ms, cnt) in prof.items() if cnt > 0}
     dom = max((c for c in per_class if c in KERNELS), key=lambda c: per_class[c][0])
     ms_tot, cnt = per_class[dom]

@@ -99,8 +99,11 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
 // are stored and both V and x are read contiguously across a wave's rows.
 // Sums run over dz, dy, dx ascending; block partials of sum(r^2) as for the
 // CSR residual.
-template <typename T, int DIM, bool PLAIN = false>
-__global__ __launch_bounds__(256) void stencil_resid(int n, int nx, int ny, int p, const T* __restrict__ V,
+// WX > 0: the stencil width 2 p + 1 known at compile time, so the offsets of
+// a stencil row are unrolled and all their loads issued together (offsets
+// outside the grid read offset 0 with weight 0, which adds an exact zero).
+template <typename T, int DIM, bool PLAIN = false, int WX = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void stencil_resid(int n, int nx, int ny, int p, const T* __restrict__ V,
                                                      const T* __restrict__ x, const T* __restrict__ b,
                                                      T* __restrict__ r, double* __restrict__ partial) {
   const int w = 2 * p + 1;
@@ -117,7 +120,23 @@ __global__ __launch_bounds__(256) void stencil_resid(int n, int nx, int ny, int 
         const int k0 = ((DIM == 3 ? (dz + p) * w : 0) + (dy + p)) * w + p;  // offset index of dx = 0
         const T* vr = V + (size_t)k0 * n + i;
         const T* xr = x + i + (dz * ny + dy) * nx;
-        for (int dx = dx0; dx <= dx1; ++dx) acc += vr[(int64_t)dx * n] * xr[dx];
+        if constexpr (WX > 0) {
+          T vv[WX], xx[WX];
+#pragma unroll
+          for (int u = 0; u < WX; ++u) {
+            const int dx = u - WX / 2;
+            const bool ok = dx >= dx0 && dx <= dx1;
+            vv[u] = vr[(int64_t)(ok ? dx : 0) * n];
+            xx[u] = xr[ok ? dx : 0];
+          }
+#pragma unroll
+          for (int u = 0; u < WX; ++u) {
+            const int dx = u - WX / 2;
+            acc += (dx >= dx0 && dx <= dx1 ? vv[u] : (T)0) * xx[u];
+          }
+        } else {
+          for (int dx = dx0; dx <= dx1; ++dx) acc += vr[(int64_t)dx * n] * xr[dx];
+        }
       }
     const T res = PLAIN ? acc : b[i] - acc;  // PLAIN: r = A x
     r[i] = res;

@@ -636,6 +636,27 @@ void transfer(const DevMat& M, const DevXStencil& X, int dim, const T* x, const 
   csr_launch<T>(add ? pmg::kScaleAdd : pmg::kScale, M.nrows, nullptr, M, v, x, nullptr, d, out, nullptr, st);
 }
 
+// stencil_resid with the offset loop unrolled for stencil widths up to 11
+// (degrees 1..5), the runtime loop otherwise.
+template <typename T, int DIM, bool PLAIN>
+void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const T* x, const T* b, T* r,
+                    double* partial, hipStream_t st) {
+  switch (2 * S.p + 1) {
+#define PMG_STENCIL_W(W)                                                                            \
+  case W:                                                                                           \
+    pmg::stencil_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial); \
+    return;
+    PMG_STENCIL_W(3)
+    PMG_STENCIL_W(5)
+    PMG_STENCIL_W(7)
+    PMG_STENCIL_W(9)
+    PMG_STENCIL_W(11)
+#undef PMG_STENCIL_W
+    default:
+      pmg::stencil_resid<T, DIM, PLAIN, 0><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
+  }
+}
+
 // r = b - A_{h,p} x with block partials of sum(r^2) in partial; returns the
 // number of partials written.
 template <typename T>
@@ -647,9 +668,9 @@ unsigned resid_a(pmg_handle h, const T* x, const T* b, T* r, double* partial, hi
     const int n = h->A.nrows;
     const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
     if (S.dim == 2)
-      pmg::stencil_resid<T, 2><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
+      launch_stencil<T, 2, false>(S, n, grid, V, x, b, r, partial, st);
     else
-      pmg::stencil_resid<T, 3><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
+      launch_stencil<T, 3, false>(S, n, grid, V, x, b, r, partial, st);
     return grid;
   }
   const T* v;
@@ -1004,9 +1025,9 @@ void matvec_a(pmg_handle h, Workspace& ws, const double* x, double* y, hipStream
     const int n = h->A.nrows;
     const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
     if (S.dim == 2)
-      pmg::stencil_resid<double, 2, true><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, S.v, x, x, y, ws.partial);
+      launch_stencil<double, 2, true>(S, n, grid, S.v, x, x, y, ws.partial, st);
     else
-      pmg::stencil_resid<double, 3, true><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, S.v, x, x, y, ws.partial);
+      launch_stencil<double, 3, true>(S, n, grid, S.v, x, x, y, ws.partial, st);
     return;
   }
   csr_launch<double>(pmg::kPlain, h->A.nrows, nullptr, h->A, h->A.v, x, nullptr, nullptr, y, nullptr, st);
