@@ -318,6 +318,22 @@ def main():
     prof = s.profile_read()
     s.profile_enable(False)
 
+    # whole solves to a relative residual of 1e-8 on the same problem: V-cycles
+    # alone (stationary p-multigrid) and BiCGSTAB with one V-cycle per
+    # preconditioning; each is run once untimed so its graphs are captured
+    solves = {}
+    for name, fn in (("vcycles", s.solve), ("bicgstab", s.bicgstab)):
+        x.zero_()
+        fn(b, x, tol=1e-8)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, relr, _, _, _ = fn(b, x, tol=1e-8)
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - t0
+        solves[name] = {"status": int(st), "iterations": int(it), "relres": float(relr),
+                        "ms": round(1e3 * el_s, 3), "ms_per_iteration": round(1e3 * el_s / max(it, 1), 4)}
+
     # dominant kernel by total time per V-cycle
     KERNELS = kernel_map(info, args.dim, args.degree)
     per_class = {c: (ms, cnt) for c, (ms, cnt) in prof.items() if cnt > 0}
@@ -362,6 +378,7 @@ def main():
                    "unknowns": n, "precision": "fp64", "ilut": [1e-12, 1.0], "final_relres": rel,
                    "setup_s": round(t_setup, 1), "parallelism": "1 GPU"},
         "roofline": roofline,
+        "solves": solves,
     }
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)

@@ -28,6 +28,7 @@ M_A, M_L, M_U, M_R, M_P, M_A1, M_PH, M_RH = range(8)
 V_F, V_MLP, V_ML1, V_CHOL = range(4)
 GEOM_BOX, GEOM_ANNULUS = 0, 1
 RHS_SINE, RHS_ANNULUS = 0, 1
+PDE_POISSON, PDE_CDR = 0, 1  # operator: Poisson, or the CDR coefficients of benchmark 2
 
 
 def build(force: bool = True) -> str:
@@ -58,7 +59,7 @@ def lib():
         L = C.CDLL(_LIB)
         vp, dp, ip, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
         L.orc_create.restype = vp
-        L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, ip,
+        L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, ip,
                                  C.POINTER(_Opts), C.c_int, ip]
         L.orc_assemble_only.restype = vp
         L.orc_assemble_only.argtypes = [C.c_int] * 8 + [ip]
@@ -87,6 +88,8 @@ def lib():
         L.orc_exact_u.restype = C.c_double
         L.orc_exact_u.argtypes = [C.c_int, C.c_int, ip, dp]
         L.orc_rhs_f.restype = C.c_double
+        L.orc_cdr_f.restype = C.c_double
+        L.orc_cdr_f.argtypes = [ip, dp]
         L.orc_rhs_f.argtypes = [C.c_int, C.c_int, ip, dp]
         _lib = L
     return _lib
@@ -165,6 +168,13 @@ def rhs_f(rhs, dim, k, X):
     return lib().orc_rhs_f(rhs, dim, _ip(kk), _dp(XX))
 
 
+def cdr_f(k, X):
+    """Right-hand side of benchmark 2 (CDR operator, u = sin(k1 pi x) sin(k2 pi y))."""
+    kk = np.ascontiguousarray(list(k) + [1] * (3 - len(k)), dtype=np.int32)
+    XX = np.ascontiguousarray(list(X) + [0.0] * (3 - len(X)), dtype=np.float64)
+    return lib().orc_cdr_f(_ip(kk), _dp(XX))
+
+
 def _get_csr(h, which, lev=0):
     L = lib()
     dims = np.zeros(3, dtype=np.int64)
@@ -216,13 +226,13 @@ class Oracle:
     of the p-multigrid method built by the oracle."""
 
     def __init__(self, dim, p, nel, geom=GEOM_BOX, rhs=RHS_SINE, freq=(1, 1, 1),
-                 opts: Options | None = None, ilut: bool = True):
-        self.dim, self.p, self.nel, self.geom, self.rhs = dim, p, nel, geom, rhs
+                 opts: Options | None = None, ilut: bool = True, pde=PDE_POISSON):
+        self.dim, self.p, self.nel, self.geom, self.rhs, self.pde = dim, p, nel, geom, rhs, pde
         self.opts = opts or Options()
         fr = np.ascontiguousarray(list(freq) + [1] * (3 - len(freq)), dtype=np.int32)
         st = C.c_int(0)
         o = self.opts.c()
-        self._h = lib().orc_create(dim, p, nel, geom, rhs, _ip(fr), C.byref(o),
+        self._h = lib().orc_create(dim, p, nel, geom, rhs, pde, _ip(fr), C.byref(o),
                                    0 if ilut else 1, C.byref(st))
         self.status = st.value
         if self._h is None:

@@ -18,7 +18,8 @@
  *
  * Parity status of each part (what pins it, see tests/test_oracle_*.py):
  *   basis, quadrature, geometry, assembly, lumping, transfers, P1 hierarchy,
- *   smoother algebra, V-cycle identities, CG ........ pinned
+ *   smoother algebra, V-cycle identities, CG, BiCGSTAB,
+ *   the CDR operator and right-hand side of benchmark 2 .... pinned
  *   ILUT with tau = 1e-12, m = 1 (values) ........... parity unpinned: only
  *     invariants and the exact-LU limit (tau = 0, unlimited fill) are fixed
  *     by the paper and by mathematics; the values for the paper's constants
@@ -38,6 +39,17 @@
 #define ORC_ENAN 7
 
 #define MAXLEV 24
+
+/* Operators (the model problem of Section 2, -div(D grad u) + v.grad u + R u
+ * = f with u = 0 on the boundary):
+ *  ORC_PDE_POISSON: D = I, v = 0, R = 0 (benchmarks 1 and 4);
+ *  ORC_PDE_CDR: the coefficients of benchmark 2 on the unit square,
+ *    D = [1.2 -0.7; -0.4 0.9], v = (0.4, -0.2), R = 0.3. */
+#define ORC_PDE_POISSON 0
+#define ORC_PDE_CDR 1
+static const double CDR_D[2][2] = {{1.2, -0.7}, {-0.4, 0.9}};
+static const double CDR_V[2] = {0.4, -0.2};
+static const double CDR_R = 0.3;
 
 /* ------------------------------------------------------------------------ */
 /* Compressed sparse row storage (rows sorted by column).                    */
@@ -348,6 +360,22 @@ double orc_rhs_f(int rhs, int dim, const int *k, const double *X) {
   return 40.0 * x * y * y * (s - 2.0) + 2.0 * x * (s * s - 5.0 * s + 4.0);
 }
 
+/* Benchmark 2: the right-hand side for u = sin(k1 pi x) sin(k2 pi y) (k = 1
+ * gives the paper's solution) under the CDR operator, from
+ *   u_xx = -k1^2 pi^2 u,  u_yy = -k2^2 pi^2 u,  u_xy = k1 k2 pi^2 cx cy,
+ *   -div(D grad u) = -(d11 u_xx + (d12 + d21) u_xy + d22 u_yy),
+ *   v.grad u = v1 k1 pi cx sy + v2 k2 pi sx cy,
+ * with sx = sin(k1 pi x), cx = cos(k1 pi x) and likewise in y. */
+double orc_cdr_f(const int *k, const double *X) {
+  double a = k[0] * M_PI, b = k[1] * M_PI;
+  double sx = sin(a * X[0]), cx = cos(a * X[0]), sy = sin(b * X[1]), cy = cos(b * X[1]);
+  double u = sx * sy;
+  double diff = -(CDR_D[0][0] * (-a * a * u) + (CDR_D[0][1] + CDR_D[1][0]) * (a * b * cx * cy) +
+                  CDR_D[1][1] * (-b * b * u));
+  double conv = CDR_V[0] * a * cx * sy + CDR_V[1] * b * sx * cy;
+  return diff + conv + CDR_R * u;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Index maps.  Tensor functions carry a multi-index (i_x, i_y[, i_z]); the  */
 /* paper's global-index formula is garbled, the reading taken is the 0-based */
@@ -385,7 +413,9 @@ static void unflat(int idx, int base, int dim, int *m) {
 /* ------------------------------------------------------------------------ */
 /* Element-loop Galerkin assembly (Section 2, discrete system; Section 3,    */
 /* mass and transfer matrices).  kind 0: stiffness int grad(F_i).grad(F_j);  */
-/* kind 1: mass / transfer int F_i F_j.  Row functions have degree pr, column */
+/* kind 1: mass / transfer int F_i F_j; kind 2: the CDR form of benchmark 2, */
+/* int grad(F_i).D grad(F_j) + (v.grad F_j) F_i + R F_j F_i, row i the test  */
+/* function and column j the trial function.  Row functions have degree pr, column */
 /* functions degree pc, both on the same uniform knot mesh of n_el elements; */
 /* nq Gauss points per direction and element.  The sparsity pattern is every */
 /* pair of functions whose supports share an element.  Element contributions */
@@ -518,6 +548,13 @@ static int assemble(const omesh *M, int kind, int pr, int pc, int nq, int elim, 
             double d = 0.0;
             for (int c = 0; c < dim; ++c) d += gr[a * 3 + c] * gc[b * 3 + c];
             integrand = d;
+          } else if (kind == 2) {
+            double d = 0.0;
+            for (int c = 0; c < 2; ++c)
+              for (int c2 = 0; c2 < 2; ++c2) d += gr[a * 3 + c] * CDR_D[c][c2] * gc[b * 3 + c2];
+            double cv = 0.0;
+            for (int c = 0; c < 2; ++c) cv += CDR_V[c] * gc[b * 3 + c];
+            integrand = d + cv * vr[a] + CDR_R * vc[b] * vr[a];
           } else {
             integrand = vr[a] * vc[b];
           }
@@ -534,7 +571,7 @@ static int assemble(const omesh *M, int kind, int pr, int pc, int nq, int elim, 
 }
 
 /* Load vector f_i = int f Phi_i over the interior functions of degree p. */
-static int assemble_load(const omesh *M, int p, int nq, int rhs, const int *k, double *f) {
+static int assemble_load(const omesh *M, int p, int nq, int rhs, int pde, const int *k, double *f) {
   int dim = M->dim, nel = M->nel, nb = nel + p;
   int n = ipow(nb - 2, dim);
   memset(f, 0, sizeof(double) * (size_t)n);
@@ -553,7 +590,7 @@ static int assemble_load(const omesh *M, int p, int nq, int rhs, const int *k, d
       }
       double X[3], J[3][3], det;
       geom_eval(M->geom, dim, xi, X, J, &det);
-      double fx = orc_rhs_f(rhs, dim, k, X);
+      double fx = pde == ORC_PDE_CDR ? orc_cdr_f(k, X) : orc_rhs_f(rhs, dim, k, X);
       for (int l = 0; l < nl; ++l) {
         unflat(l, p + 1, dim, am);
         for (int a = 0; a < dim; ++a) fm[a] = em[a] + am[a];
@@ -804,7 +841,7 @@ typedef struct {
 } orc_opts;
 
 typedef struct {
-  int dim, p, nel, geom, rhs;
+  int dim, p, nel, geom, rhs, pde;
   int freq[3];
   orc_opts o;
   int n, n1;
@@ -819,6 +856,8 @@ typedef struct {
   ocsr Ph[MAXLEV];  /* Ph[l]: level l (fine) x level l+1 (coarse) */
   ocsr Rh[MAXLEV];  /* transpose */
   double *chol;     /* dense lower Cholesky factor of the coarsest level */
+  double *lu;       /* or (non-symmetric operator) its dense LU factors */
+  int *piv;         /* and the row interchanges */
   /* work */
   double *r, *y, *r1, *e1;
   double *hv_b[MAXLEV], *hv_e[MAXLEV], *hv_r[MAXLEV];
@@ -861,6 +900,55 @@ static int dense_cholesky(const ocsr *A, double **out) {
   return ORC_OK;
 }
 
+/* Dense LU with partial pivoting (Gaussian elimination, largest pivot in
+ * the column), for the non-symmetric coarsest operator of benchmark 2: the
+ * unit lower factor below the diagonal, U on and above it; piv[k] is the row
+ * swapped with row k at step k. */
+static int dense_lu(const ocsr *A, double **out, int **piv_out) {
+  int n = A->nrows;
+  double *C = calloc((size_t)n * n, sizeof(double));
+  int *piv = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) C[(size_t)i * n + A->ci[k]] = A->v[k];
+  for (int k = 0; k < n; ++k) {
+    int m = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(C[(size_t)i * n + k]) > fabs(C[(size_t)m * n + k])) m = i;
+    piv[k] = m;
+    if (!(C[(size_t)m * n + k] != 0.0)) { free(C); free(piv); return ORC_EZEROPIVOT; }
+    if (m != k)
+      for (int j = 0; j < n; ++j) {
+        double t = C[(size_t)k * n + j];
+        C[(size_t)k * n + j] = C[(size_t)m * n + j];
+        C[(size_t)m * n + j] = t;
+      }
+    for (int i = k + 1; i < n; ++i) {
+      double l = C[(size_t)i * n + k] / C[(size_t)k * n + k];
+      C[(size_t)i * n + k] = l;
+      for (int j = k + 1; j < n; ++j) C[(size_t)i * n + j] -= l * C[(size_t)k * n + j];
+    }
+  }
+  *out = C;
+  *piv_out = piv;
+  return ORC_OK;
+}
+
+static void dense_lu_solve(const double *C, const int *piv, int n, const double *b, double *x) {
+  for (int i = 0; i < n; ++i) x[i] = b[i];
+  for (int k = 0; k < n; ++k)
+    if (piv[k] != k) {
+      double t = x[k];
+      x[k] = x[piv[k]];
+      x[piv[k]] = t;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < i; ++k) x[i] -= C[(size_t)i * n + k] * x[k];
+  for (int i = n - 1; i >= 0; --i) {
+    for (int k = i + 1; k < n; ++k) x[i] -= C[(size_t)i * n + k] * x[k];
+    x[i] /= C[(size_t)i * n + i];
+  }
+}
+
 static void dense_chol_solve(const double *C, int n, const double *b, double *x) {
   for (int i = 0; i < n; ++i) {
     double s = b[i];
@@ -881,7 +969,7 @@ void orc_free(orc *s) {
     csr_free(&s->A1[l]); csr_free(&s->Ph[l]); csr_free(&s->Rh[l]);
     free(s->hv_b[l]); free(s->hv_e[l]); free(s->hv_r[l]);
   }
-  free(s->f); free(s->mlp); free(s->ml1); free(s->chol); free(s->perm);
+  free(s->f); free(s->mlp); free(s->ml1); free(s->chol); free(s->lu); free(s->piv); free(s->perm);
   free(s->r); free(s->y); free(s->r1); free(s->e1);
   free(s);
 }
@@ -982,23 +1070,26 @@ static int permute_sym(const ocsr *A, const int *perm, ocsr *B) {
  *                   n_el <= coarse_min (or odd), direct solve there;
  *   L, U            ILUT(tau, m) of A_p in the natural order.
  * stage_mask bit 0 skips ILUT (assembly-only use in tests). */
-orc *orc_create(int dim, int p, int nel, int geom, int rhs, const int *freq, const orc_opts *o,
+orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *freq, const orc_opts *o,
                 int stage_mask, int *status) {
   *status = ORC_OK;
-  if ((dim != 2 && dim != 3) || p < 1 || nel < 2 || (geom == 1 && dim != 2) || nel + p - 2 < 1) {
+  if ((dim != 2 && dim != 3) || p < 1 || nel < 2 || (geom == 1 && dim != 2) || nel + p - 2 < 1 ||
+      (pde != ORC_PDE_POISSON && pde != ORC_PDE_CDR) ||
+      (pde == ORC_PDE_CDR && (dim != 2 || geom != 0 || rhs != 0))) {
     *status = ORC_EINVAL;
     return NULL;
   }
   orc *s = calloc(1, sizeof(orc));
-  s->dim = dim; s->p = p; s->nel = nel; s->geom = geom; s->rhs = rhs;
+  s->dim = dim; s->p = p; s->nel = nel; s->geom = geom; s->rhs = rhs; s->pde = pde;
   for (int a = 0; a < 3; ++a) s->freq[a] = freq ? freq[a] : 1;
   if (o) s->o = *o; else orc_default_opts(&s->o);
   omesh M = {dim, geom, nel};
   s->n = ipow(nel + p - 2, dim);
   s->n1 = ipow(nel - 1, dim);
-  int rc = assemble(&M, 0, p, p, p + 1, 1, &s->A);
+  const int akind = pde == ORC_PDE_CDR ? 2 : 0;
+  int rc = assemble(&M, akind, p, p, p + 1, 1, &s->A);
   s->f = malloc(sizeof(double) * s->n);
-  if (!rc) rc = assemble_load(&M, p, p + 1, rhs, s->freq, s->f);
+  if (!rc) rc = assemble_load(&M, p, p + 1, rhs, pde, s->freq, s->f);
   s->mlp = malloc(sizeof(double) * s->n);
   s->ml1 = malloc(sizeof(double) * (s->n1 > 0 ? s->n1 : 1));
   if (!rc) rc = lumped_mass(&M, p, p + 1, s->mlp);
@@ -1011,7 +1102,7 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, const int *freq, con
     omesh Ml = {dim, geom, ne};
     s->lnel[l] = ne;
     s->ln[l] = ipow(ne - 1, dim);
-    rc = assemble(&Ml, 0, 1, 1, 2, 1, &s->A1[l]);
+    rc = assemble(&Ml, akind, 1, 1, 2, 1, &s->A1[l]);
     if (rc) break;
     if (ne <= s->o.coarse_min || (ne % 2) != 0 || l + 1 >= MAXLEV) break;
     rc = canonical_prolongation(dim, ne / 2, &s->Ph[l]);
@@ -1020,7 +1111,9 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, const int *freq, con
     l++;
   }
   s->nlev = l + 1;
-  if (!rc && s->n1 > 0) rc = dense_cholesky(&s->A1[s->nlev - 1], &s->chol);
+  if (!rc && s->n1 > 0)
+    rc = pde == ORC_PDE_CDR ? dense_lu(&s->A1[s->nlev - 1], &s->lu, &s->piv)
+                            : dense_cholesky(&s->A1[s->nlev - 1], &s->chol);
   s->perm = make_ordering(dim, nel + p - 2, p, s->o.ordering, s->o.nd_leaf);
   if (!rc && !(stage_mask & 1)) {
     s->bad_row = -1;
@@ -1119,7 +1212,10 @@ static void gs_sweep(const orc *s, int l, const double *b, double *e) {
  * coarsest level. */
 static void hcycle(orc *s, int l, const double *b, double *e) {
   if (l == s->nlev - 1) {
-    dense_chol_solve(s->chol, s->ln[l], b, e);
+    if (s->pde == ORC_PDE_CDR)
+      dense_lu_solve(s->lu, s->piv, s->ln[l], b, e);
+    else
+      dense_chol_solve(s->chol, s->ln[l], b, e);
     return;
   }
   double *r = s->hv_r[l];
@@ -1425,6 +1521,7 @@ int orc_get_vec(const orc *s, int which, double *out) {
     case OV_MLP: memcpy(out, s->mlp, sizeof(double) * s->n); return ORC_OK;
     case OV_ML1: memcpy(out, s->ml1, sizeof(double) * s->n1); return ORC_OK;
     case OV_CHOL: {
+      if (!s->chol) return ORC_EINVAL;
       int nc = s->ln[s->nlev - 1];
       memcpy(out, s->chol, sizeof(double) * (size_t)nc * nc);
       return ORC_OK;
