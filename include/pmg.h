@@ -51,14 +51,21 @@ typedef enum {
 
 enum { PMG_GEOM_BOX = 0, PMG_GEOM_QUARTER_ANNULUS = 1 };
 enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1 };
+enum { PMG_PDE_POISSON = 0, PMG_PDE_CDR = 1 };
 enum { PMG_FP64 = 0, PMG_FP32_IN_FP64 = 1 };
 enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1 };
 enum { PMG_GS_MULTICOLOR = 0 };
 enum { PMG_ORDER_NATURAL = 0, PMG_ORDER_NESTED_DISSECTION = 1 };
 
-/* The problem (Section 2): -Lap u = f on Omega = F((0,1)^dim), u = 0 on the
- * boundary, discretised with tensor B-splines of degree `degree` on the open
- * uniform knot vector with n_elem elements per direction (h = 1/n_elem).
+/* The problem (Section 2): -div(D grad u) + v.grad u + R u = f on
+ * Omega = F((0,1)^dim), u = 0 on the boundary, discretised with tensor
+ * B-splines of degree `degree` on the open uniform knot vector with n_elem
+ * elements per direction (h = 1/n_elem).
+ *   pde PMG_PDE_POISSON: D = I, v = 0, R = 0 (benchmarks 1 and 4);
+ *   pde PMG_PDE_CDR (dim 2, unit square, rhs_kind sine): benchmark 2,
+ *     D = [1.2 -0.7; -0.4 0.9], v = (0.4, -0.2), R = 0.3, a non-symmetric
+ *     operator at every level; the sine right-hand side is then this
+ *     operator applied to u = sin(k1 pi x) sin(k2 pi y).
  *   geometry PMG_GEOM_BOX: unit square / cube (F = identity);
  *   geometry PMG_GEOM_QUARTER_ANNULUS (dim 2): radii 1 and 2, F(xi, eta) =
  *     (1 + xi) C(eta), C the rational quadratic quarter circle (benchmark 1).
@@ -73,6 +80,7 @@ typedef struct {
   int32_t geometry; /* PMG_GEOM_* */
   int32_t rhs_kind; /* PMG_RHS_* */
   int32_t freq[3];  /* sine frequencies (>= 1) */
+  int32_t pde;      /* PMG_PDE_* (0: Poisson) */
 } pmg_problem;
 
 /* Solver options.  Defaults (pmg_default_options) are the paper's constants

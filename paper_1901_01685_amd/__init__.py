@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpmg.so")
 OK, EINVAL, ENOMEM, EDEVICE, EZEROPIVOT, EDIVERGED, EMAXIT, ENAN, EBUDGET = range(9)
 GEOM_BOX, GEOM_QUARTER_ANNULUS = 0, 1
 RHS_SINE, RHS_ANNULUS = 0, 1
+PDE_POISSON, PDE_CDR = 0, 1
 FP64, FP32_IN_FP64 = 0, 1
 ORDER_NATURAL, ORDER_NESTED_DISSECTION = 0, 1
 OP_A, OP_L, OP_U, OP_R, OP_P, OP_A1, OP_PH = range(7)
@@ -35,7 +36,8 @@ class PmgError(RuntimeError):
 
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("n_elem", C.c_int32),
-                ("geometry", C.c_int32), ("rhs_kind", C.c_int32), ("freq", C.c_int32 * 3)]
+                ("geometry", C.c_int32), ("rhs_kind", C.c_int32), ("freq", C.c_int32 * 3),
+                ("pde", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -186,17 +188,18 @@ def default_options(**kw) -> Options:
     return o
 
 
-def make_problem(dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1)):
+def make_problem(dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1),
+                 pde=0):
     fr = list(freq) + [1] * (3 - len(freq))
-    return Problem(dim, degree, n_elem, geometry, rhs_kind, (C.c_int32 * 3)(*fr))
+    return Problem(dim, degree, n_elem, geometry, rhs_kind, (C.c_int32 * 3)(*fr), pde)
 
 
 class Solver:
     """One set-up problem (pmg_setup handle) with the solve-phase entry points."""
 
     def __init__(self, dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE,
-                 freq=(1, 1, 1), **opts):
-        self.problem = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq)
+                 freq=(1, 1, 1), pde=0, **opts):
+        self.problem = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq, pde)
         self.options = default_options(**opts)
         h = C.c_void_p()
         _check(lib().pmg_setup(C.byref(self.problem), C.byref(self.options), C.byref(h)))
@@ -357,14 +360,15 @@ class Server:
         except Exception:
             pass
 
-    def prepare(self, dim, degree, n_elem, geometry=GEOM_BOX):
+    def prepare(self, dim, degree, n_elem, geometry=GEOM_BOX, pde=0):
         """Sets up a class ahead of requests; returns the status (EBUDGET if rejected)."""
-        pr = make_problem(dim, degree, n_elem, geometry, RHS_SINE, (1, 1, 1))
+        pr = make_problem(dim, degree, n_elem, geometry, RHS_SINE, (1, 1, 1), pde)
         return lib().pmg_server_prepare(self._h, C.byref(pr))
 
-    def submit(self, dim, degree, n_elem, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1), b=None):
+    def submit(self, dim, degree, n_elem, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1), b=None,
+               pde=0):
         """Queues a solve; returns (status, ticket)."""
-        pr = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq)
+        pr = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq, pde)
         t = C.c_int64(-1)
         bp = None
         if b is not None:

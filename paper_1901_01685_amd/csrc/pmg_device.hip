@@ -915,6 +915,11 @@ bool valid_problem(const pmg_problem* p, std::string& msg) {
   if (p->rhs_kind != PMG_RHS_SINE && p->rhs_kind != PMG_RHS_ANNULUS) { msg = "unknown rhs_kind"; return false; }
   if (p->rhs_kind == PMG_RHS_ANNULUS && p->dim != 2) { msg = "the annulus right-hand side is 2-D"; return false; }
   if (p->dim == 3 && p->geometry != PMG_GEOM_BOX) { msg = "3-D supports the unit cube only"; return false; }
+  if (p->pde != PMG_PDE_POISSON && p->pde != PMG_PDE_CDR) { msg = "unknown pde"; return false; }
+  if (p->pde == PMG_PDE_CDR && (p->dim != 2 || p->geometry != PMG_GEOM_BOX || p->rhs_kind != PMG_RHS_SINE)) {
+    msg = "the CDR problem is benchmark 2: unit square with the sine right-hand side";
+    return false;
+  }
   for (int a = 0; a < p->dim; ++a)
     if (p->freq[a] < 1 && p->rhs_kind == PMG_RHS_SINE) { msg = "freq must be >= 1"; return false; }
   double n = std::pow((double)(p->n_elem + p->degree - 2), p->dim);
@@ -1220,6 +1225,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   sp.nel = prob->n_elem;
   sp.geom = prob->geometry;
   sp.rhs = prob->rhs_kind;
+  sp.pde = prob->pde;
   for (int a = 0; a < 3; ++a) sp.freq[a] = prob->freq[a] > 0 ? prob->freq[a] : 1;
   sp.tau = o.ilut_tau;
   sp.fill = o.ilut_fill;

@@ -18,7 +18,7 @@ struct Csr {
 };
 
 struct SetupParams {
-  int dim = 2, p = 2, nel = 16, geom = 0, rhs = 0;
+  int dim = 2, p = 2, nel = 16, geom = 0, rhs = 0, pde = 0;
   int freq[3] = {1, 1, 1};
   double tau = 1e-12, fill = 1.0;
   int limit_mode = 0;

@@ -31,9 +31,9 @@ using pmgdev::Workspace;
 
 namespace {
 
-using Key = std::tuple<int, int, int, int>;  // dim, degree, n_elem, geometry
+using Key = std::tuple<int, int, int, int, int>;  // dim, degree, n_elem, geometry, pde
 
-Key key_of(const pmg_problem& p) { return Key(p.dim, p.degree, p.n_elem, p.geometry); }
+Key key_of(const pmg_problem& p) { return Key(p.dim, p.degree, p.n_elem, p.geometry, p.pde); }
 
 // Closed-form estimate of a class's device footprint before it is set up:
 // A_p, the ILUT factors (about twice nnz(A) under the per-part fill rule),
@@ -132,7 +132,7 @@ struct pmg_server_s {
   pmg_status setup_class(ClassEntry* c, std::unique_lock<std::mutex>& lk) {
     // runs with mu held on entry and exit; releases it around the host setup
     pmg_problem pr{};
-    std::tie(pr.dim, pr.degree, pr.n_elem, pr.geometry) = c->key;
+    std::tie(pr.dim, pr.degree, pr.n_elem, pr.geometry, pr.pde) = c->key;
     pr.rhs_kind = PMG_RHS_SINE;
     pr.freq[0] = pr.freq[1] = pr.freq[2] = 1;
     pmg_options o;
@@ -439,6 +439,7 @@ pmg_status pmg_server_submit(pmg_server s, const pmg_problem* prob, const double
     sp.nel = prob->n_elem;
     sp.geom = prob->geometry;
     sp.rhs = prob->rhs_kind;
+    sp.pde = prob->pde;
     for (int a = 0; a < 3; ++a) sp.freq[a] = prob->freq[a] > 0 ? prob->freq[a] : 1;
     std::string msg;
     if (pmg::load_vector(sp, req->b, msg)) {

@@ -173,8 +173,9 @@ struct Band1D {
   }
 };
 
-// kind 0: int dphi_i dphi_j; kind 1: int phi_i phi_j.  Rows degree pr, cols
-// degree pc on the same mesh, nq Gauss points per element.
+// kind 0: int dphi_i dphi_j; kind 1: int phi_i phi_j; kind 2: int phi_i
+// dphi_j; kind 3: int dphi_i phi_j.  Rows degree pr, cols degree pc on the
+// same mesh, nq Gauss points per element.
 static Band1D matrix_1d(int kind, int pr, int pc, int nel, int nq) {
   Table1D Tr = make_table(pr, nel, nq), Tc = make_table(pc, nel, nq);
   Band1D B;
@@ -188,7 +189,10 @@ static Band1D matrix_1d(int kind, int pr, int pc, int nel, int nq) {
       double w = Tr.wt[(size_t)e * nq + q];
       for (int a = 0; a <= pr; ++a)
         for (int b = 0; b <= pc; ++b) {
-          double f = kind == 0 ? Tr.D(e, q, a) * Tc.D(e, q, b) : Tr.V(e, q, a) * Tc.V(e, q, b);
+          double f = kind == 0   ? Tr.D(e, q, a) * Tc.D(e, q, b)
+                     : kind == 1 ? Tr.V(e, q, a) * Tc.V(e, q, b)
+                     : kind == 2 ? Tr.V(e, q, a) * Tc.D(e, q, b)
+                                 : Tr.D(e, q, a) * Tc.V(e, q, b);
           int i = e + a, j = e + b;
           B.a[(size_t)i * B.width + (j - i + B.lo)] += w * f;
         }
@@ -196,14 +200,16 @@ static Band1D matrix_1d(int kind, int pr, int pc, int nel, int nq) {
   return B;
 }
 
-// int phi_i (degree p) over (0,1), and int g phi_i for g(x) = sin(k pi x).
-static std::vector<double> integrals_1d(int p, int nel, int nq, int k) {
+// int phi_i (degree p) over (0,1), and int g phi_i for g(x) = sin(k pi x)
+// (or cos(k pi x) with cosine).
+static std::vector<double> integrals_1d(int p, int nel, int nq, int k, bool cosine = false) {
   Table1D T = make_table(p, nel, nq);
   std::vector<double> s(nel + p, 0.0);
   for (int e = 0; e < nel; ++e)
     for (int q = 0; q < nq; ++q) {
       double w = T.wt[(size_t)e * nq + q];
-      double g = k > 0 ? std::sin(k * M_PI * T.u[(size_t)e * nq + q]) : 1.0;
+      const double x = k * M_PI * T.u[(size_t)e * nq + q];
+      double g = k > 0 ? (cosine ? std::cos(x) : std::sin(x)) : 1.0;
       for (int a = 0; a <= p; ++a) s[e + a] += w * g * T.V(e, q, a);
     }
   return s;
@@ -286,6 +292,61 @@ static Csr kron_assemble(int dim, const std::vector<std::vector<const Band1D*>>&
     }
   });
   return M;
+}
+
+// --------------------------------------------------------- CDR benchmark
+// Benchmark 2 (Section 2): -div(D grad u) + v.grad u + R u on the unit
+// square.  The Galerkin form int grad(phi_i).D grad(phi_j) + (v.grad phi_j)
+// phi_i + R phi_j phi_i (row i the test function) is a sum of seven
+// Kronecker products of 1-D matrices, x factor times y factor:
+//   d11 K (x) M,  d12 G' (x) G,  d21 G (x) G',  d22 M (x) K,
+//   v1 G (x) M,   v2 M (x) G,    R M (x) M,
+// K = int B_i' B_j', M = int B_i B_j, G = int B_i B_j', G' = int B_i' B_j.
+constexpr double kCdrD[2][2] = {{1.2, -0.7}, {-0.4, 0.9}};
+constexpr double kCdrV[2] = {0.4, -0.2};
+constexpr double kCdrR = 0.3;
+
+struct CdrTerms {
+  std::vector<Band1D> m;  // 14 factors, x and y of each term
+  std::vector<std::vector<const Band1D*>> terms() const {
+    std::vector<std::vector<const Band1D*>> t;
+    for (size_t k = 0; k + 1 < m.size(); k += 2) t.push_back({&m[k], &m[k + 1]});
+    return t;
+  }
+};
+
+static Band1D scaled(Band1D B, double s) {
+  for (double& v : B.a) v *= s;
+  return B;
+}
+
+static CdrTerms cdr_terms(int p, int nel, int nq) {
+  const Band1D K = matrix_1d(0, p, p, nel, nq), M = matrix_1d(1, p, p, nel, nq);
+  const Band1D G = matrix_1d(2, p, p, nel, nq), Gd = matrix_1d(3, p, p, nel, nq);
+  CdrTerms c;
+  c.m = {scaled(K, kCdrD[0][0]), M,  scaled(Gd, kCdrD[0][1]), G, scaled(G, kCdrD[1][0]), Gd,
+         scaled(M, kCdrD[1][1]), K,  scaled(G, kCdrV[0]),     M, scaled(M, kCdrV[1]),    G,
+         scaled(M, kCdrR),       M};
+  return c;
+}
+
+// Load vector of benchmark 2 for u = sin(k1 pi x) sin(k2 pi y): with
+// a = k1 pi, b = k2 pi the right-hand side is
+//   (d11 a^2 + d22 b^2 + R) sx sy - (d12 + d21) a b cx cy + v1 a cx sy + v2 b sx cy,
+// separable, so f_i is a sum of products of 1-D sine / cosine integrals.
+static void cdr_load(int p, int nel, const int* k, std::vector<double>& f) {
+  const int nq = p + 1, np1 = nel + p - 2;
+  const auto sx = integrals_1d(p, nel, nq, k[0]), cx = integrals_1d(p, nel, nq, k[0], true);
+  const auto sy = integrals_1d(p, nel, nq, k[1]), cy = integrals_1d(p, nel, nq, k[1], true);
+  const double a = k[0] * M_PI, b = k[1] * M_PI;
+  const double css = kCdrD[0][0] * a * a + kCdrD[1][1] * b * b + kCdrR;
+  const double ccc = -(kCdrD[0][1] + kCdrD[1][0]) * a * b, ccs = kCdrV[0] * a, csc = kCdrV[1] * b;
+  f.resize((size_t)np1 * np1);
+  for (int iy = 0; iy < np1; ++iy)
+    for (int ix = 0; ix < np1; ++ix) {
+      const int i = ix + 1, j = iy + 1;
+      f[(size_t)iy * np1 + ix] = css * sx[i] * sy[j] + ccc * cx[i] * cy[j] + ccs * cx[i] * sy[j] + csc * sx[i] * cy[j];
+    }
 }
 
 // ------------------------------------------------------------------ annulus
@@ -588,9 +649,50 @@ static bool dense_spd_inverse(const Csr& A, std::vector<double>& inv) {
   return true;
 }
 
+// Inverse of a non-singular matrix by Gaussian elimination with partial
+// pivoting (the coarsest degree-1 operator of the non-symmetric problem).
+static bool dense_lu_inverse(const Csr& A, std::vector<double>& inv) {
+  const int n = A.nrows;
+  std::vector<double> C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) C[(size_t)i * n + A.ci[k]] = A.v[k];
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int m = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(C[(size_t)i * n + k]) > std::fabs(C[(size_t)m * n + k])) m = i;
+    if (!(C[(size_t)m * n + k] != 0.0) || !std::isfinite(C[(size_t)m * n + k])) return false;
+    if (m != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(C[(size_t)k * n + j], C[(size_t)m * n + j]);
+        std::swap(inv[(size_t)k * n + j], inv[(size_t)m * n + j]);
+      }
+    const double d = C[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) {
+      C[(size_t)k * n + j] /= d;
+      inv[(size_t)k * n + j] /= d;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double l = C[(size_t)i * n + k];
+      if (l == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        C[(size_t)i * n + j] -= l * C[(size_t)k * n + j];
+        inv[(size_t)i * n + j] -= l * inv[(size_t)k * n + j];
+      }
+    }
+  }
+  return true;
+}
+
 int load_vector(const SetupParams& sp, std::vector<double>& f, std::string& msg) {
   const int dim = sp.dim, p = sp.p, nel = sp.nel;
   const int64_t n = ipow(nel + p - 2, dim);
+  if (sp.pde == 1) {
+    cdr_load(p, nel, sp.freq, f);
+    return 0;
+  }
   if (sp.geom == 0 && sp.rhs == 0) {
     std::vector<std::vector<double>> sf(dim);
     double ks = 0.0;
@@ -637,7 +739,12 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
       t[a] = &K;
       termsA.push_back(t);
     }
-    H.A = kron_assemble(dim, termsA, th);
+    if (sp.pde == 1) {
+      const CdrTerms c = cdr_terms(p, nel, p + 1);
+      H.A = kron_assemble(dim, c.terms(), th);
+    } else {
+      H.A = kron_assemble(dim, termsA, th);
+    }
     Band1D X = matrix_1d(1, p, 1, nel, p + 1);
     H.P = kron_assemble(dim, {std::vector<const Band1D*>(dim, &X)}, th);
     // lumped masses = int Phi_i = product of 1-D integrals; load vector
@@ -665,6 +772,7 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
       H.mlp[r] = m;
       H.f[r] = M_PI * M_PI * ks * s;
     }
+    if (sp.pde == 1) cdr_load(p, nel, sp.freq, H.f);
     for (int64_t r = 0; r < H.n1; ++r) {
       int64_t t = r;
       double m = 1.0;
@@ -695,7 +803,10 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
   for (;;) {
     H.lnel.push_back(ne);
     H.ln.push_back((int)ipow(ne - 1, dim));
-    if (sp.geom == 0) {
+    if (sp.geom == 0 && sp.pde == 1) {
+      const CdrTerms c = cdr_terms(1, ne, 2);
+      H.A1.push_back(kron_assemble(dim, c.terms(), th));
+    } else if (sp.geom == 0) {
       Band1D K1 = matrix_1d(0, 1, 1, ne, 2), M1 = matrix_1d(1, 1, 1, ne, 2);
       std::vector<std::vector<const Band1D*>> t1;
       for (int a = 0; a < dim; ++a) {
@@ -719,7 +830,11 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
           " unknowns (limit 1024): use n_elem = 2^k * m with m <= coarse_min_elems";
     return 1;
   }
-  if (H.n_coarse > 0 && !dense_spd_inverse(H.A1.back(), H.coarse_inv)) {
+  if (H.n_coarse > 0 && sp.pde == 1 && !dense_lu_inverse(H.A1.back(), H.coarse_inv)) {
+    msg = "coarsest degree-1 operator is singular";
+    return 4;
+  }
+  if (H.n_coarse > 0 && sp.pde != 1 && !dense_spd_inverse(H.A1.back(), H.coarse_inv)) {
     msg = "coarsest degree-1 operator is not positive definite";
     return 4;
   }

@@ -19,16 +19,17 @@ def _dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("case", [(2, 3, 32, 0), (2, 5, 32, 1), (2, 5, 64, 1), (3, 2, 12, 0)],
-                         ids=lambda c: "d%dp%dn%dg%d" % c)
+@pytest.mark.parametrize("case", [(2, 3, 32, 0), (2, 5, 32, 1), (2, 5, 64, 1), (3, 2, 12, 0), (2, 4, 64, 0, 1)],
+                         ids=lambda c: "d%dp%dn%dg%d" % c[:4] + ("cdr" if len(c) > 4 else ""))
 def test_mixed_reaches_fp64_tolerance(case):
     import paper_1901_01685_amd as pmg
     dev = _dev()
-    dim, p, nel, g = case
+    dim, p, nel, g = case[:4]
+    pde = case[4] if len(case) > 4 else 0
     print("mixed case", case, flush=True)
-    sm = pmg.Solver(dim, p, nel, geometry=g, rhs_kind=g, device=0, precision=pmg.FP32_IN_FP64)
-    sd = pmg.Solver(dim, p, nel, geometry=g, rhs_kind=g, device=0)
-    o = O.Oracle(dim, p, nel, geom=g, rhs=g)
+    sm = pmg.Solver(dim, p, nel, geometry=g, rhs_kind=g, pde=pde, device=0, precision=pmg.FP32_IN_FP64)
+    sd = pmg.Solver(dim, p, nel, geometry=g, rhs_kind=g, pde=pde, device=0)
+    o = O.Oracle(dim, p, nel, geom=g, rhs=g, pde=pde)
     n = sm.n
     b = torch.empty(n, dtype=torch.float64, device=dev)
     sm.rhs(b)

@@ -21,7 +21,15 @@ CASES = [
     (2, 4, 32, 1),     # quarter annulus
     (3, 2, 16, 0),     # unit cube
     (3, 3, 12, 0),
+    # benchmark 2: non-symmetric CDR operator on the unit square (pde = 1)
+    (2, 2, 16, 0, 1),
+    (2, 4, 64, 0, 1),
+    (2, 5, 128, 0, 1),  # degree-1 levels 127 and 63: tiled smoothing and the LDS cycle
 ]
+
+
+def _id(c):
+    return "d%dp%dn%dg%d" % c[:4] + ("cdr" if len(c) > 4 and c[4] else "")
 
 
 def _dev():
@@ -33,12 +41,12 @@ def _dev():
 _cache = {}
 
 
-def _pair(dim, p, nel, geom, **kw):
+def _pair(dim, p, nel, geom, pde=0, **kw):
     import paper_1901_01685_amd as pmg
-    key = (dim, p, nel, geom, tuple(sorted(kw.items())))
+    key = (dim, p, nel, geom, pde, tuple(sorted(kw.items())))
     if key not in _cache:
-        s = pmg.Solver(dim, p, nel, geometry=geom, rhs_kind=geom, device=0, **kw)
-        o = O.Oracle(dim, p, nel, geom=geom, rhs=geom)
+        s = pmg.Solver(dim, p, nel, geometry=geom, rhs_kind=geom, pde=pde, device=0, **kw)
+        o = O.Oracle(dim, p, nel, geom=geom, rhs=geom, pde=pde)
         _cache[key] = (s, o)
     return _cache[key]
 
@@ -51,7 +59,7 @@ def _rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "d%dp%dn%dg%d" % c)
+@pytest.mark.parametrize("case", CASES, ids=_id)
 def test_steps_match_oracle(case):
     dev = _dev()
     s, o = _pair(*case)
@@ -96,7 +104,7 @@ def test_steps_match_oracle(case):
     assert abs(nv - np.linalg.norm(rv_or)) <= 1e-10 * np.linalg.norm(r_or)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "d%dp%dn%dg%d" % c)
+@pytest.mark.parametrize("case", CASES, ids=_id)
 @pytest.mark.parametrize("x0kind", ["zero", "random"])
 def test_solve_history_matches_oracle(case, x0kind):
     dev = _dev()

@@ -140,3 +140,24 @@ def test_fp64_single_slot_mode():
         assert _oracle_relres(2, 4, 32, 0, (1, 2, 1), x) <= 1.01e-10
     finally:
         srv.close()
+
+
+def test_cdr_requests_are_their_own_class():
+    """Benchmark 2 requests share (dim, p, n_el, geometry) with Poisson ones but
+    not the operator: the class key includes the pde, and each result matches
+    its own oracle."""
+    import paper_1901_01685_amd as pmg
+    _need_gpu()
+    srv = pmg.Server(max_slots=2)
+    try:
+        t_p = srv.submit(2, 3, 32)[1]
+        t_c = srv.submit(2, 3, 32, pde=pmg.PDE_CDR)[1]
+        (st_p, info_p, x_p), (st_c, info_c, x_c) = srv.wait(t_p), srv.wait(t_c)
+        assert st_p == pmg.OK and st_c == pmg.OK
+        assert srv.stats()["classes_resident"] >= 2
+        o = O.Oracle(2, 3, 32, pde=O.PDE_CDR, ilut=False)
+        f = o.f()
+        assert np.linalg.norm(o.residual(f, x_c)) <= 1.01e-10 * np.linalg.norm(f)
+        assert _oracle_relres(2, 3, 32, 0, (1, 1, 1), x_p) <= 1.01e-10
+    finally:
+        srv.close()

@@ -23,6 +23,7 @@ CASES = [
     (2, 2, 256, 0, {"nu1": 2, "nu2": 1}),
     (2, 2, 1024, 0, {}),
     (3, 2, 16, 0, {}),
+    (2, 2, 256, 0, {"pde": 1}),   # non-symmetric CDR stencils (benchmark 2)
 ]
 
 

@@ -125,3 +125,37 @@ def test_status_codes_host():
     assert st == P.EDEVICE
     assert P.lib().pmg_get_info(None, None) == P.EINVAL
     assert P.lib().pmg_status_str(P.EZEROPIVOT) == b"zero pivot in ILUT"
+
+
+@pytest.mark.parametrize("case", [(2, 16), (3, 32), (5, 16), (4, 64)], ids=lambda c: "p%dn%d" % c)
+def test_host_setup_matches_oracle_cdr(case):
+    """Benchmark 2 (CDR operator): the library's Kronecker assembly against the
+    oracle's element loop, at degree p and on every degree-1 level, the load
+    vector of the CDR right-hand side, the non-symmetric coarsest inverse, and
+    the ILUT factors of the non-symmetric operator."""
+    p, nel = case
+    s = P.Solver(2, p, nel, pde=P.PDE_CDR, device=-1)
+    o = O.Oracle(2, p, nel, pde=O.PDE_CDR)
+    A = s.export(P.OP_A)
+    assert _same_pattern(A, o.A()) and _rel(A, o.A()) < 1e-13
+    assert abs(A - A.T).max() > 1e-3 * abs(A).max()      # genuinely non-symmetric
+    assert _rel(s.export_vec(P.VEC_F), o.f()) < 1e-12
+    for lev in range(o.nlev):
+        assert _rel(s.export(P.OP_A1, lev), o.A1(lev)) < 1e-13
+    nc = o.level_n[o.nlev - 1]
+    inv = np.linalg.inv(o.A1(o.nlev - 1).toarray())
+    assert _rel(s.export_vec(P.VEC_COARSE_INV).reshape(nc, nc), inv) < 1e-11
+    assert np.array_equal(s.export_perm(), o.perm())
+    for a, b in ((s.export(P.OP_L), o.L()), (s.export(P.OP_U), o.U())):
+        assert _same_pattern(a, b)
+        assert _rel(a, b) < 1e-12
+
+
+def test_cdr_configurations_checked():
+    for kw in ({"dim": 3, "degree": 2, "n_elem": 8}, {"dim": 2, "degree": 2, "n_elem": 8, "geometry": 1, "rhs_kind": 1}):
+        with pytest.raises(P.PmgError) as e:
+            P.Solver(pde=P.PDE_CDR, device=-1, **kw)
+        assert e.value.status == P.EINVAL
+    with pytest.raises(P.PmgError) as e:
+        P.Solver(2, 2, 8, pde=7, device=-1)
+    assert e.value.status == P.EINVAL
