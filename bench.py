@@ -75,7 +75,7 @@ def _traffic(kernel_class, workload):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(p, nel_full, n_full, budget_s=20.0):
+def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
     the workload: the same problem family (2-D unit square, same p) at
     h = 1/nel_s, V-cycles repeated for about budget_s seconds; reported in
@@ -84,7 +84,7 @@ def cpu_baseline(p, nel_full, n_full, budget_s=20.0):
     import oracle
     nel_s = 128
     t0 = time.perf_counter()
-    o = oracle.Oracle(2, p, nel_s)
+    o = oracle.Oracle(2, p, nel_s, pde=pde)
     t_setup = time.perf_counter() - t0
     b = o.f()
     x = np.zeros(o.n)
@@ -103,7 +103,7 @@ def cpu_baseline(p, nel_full, n_full, budget_s=20.0):
         "unit": "DOF*iter/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle V-cycles on the same 2-D unit-square p={p} problem at h=1/{nel_s} "
+        "sample": (f"oracle V-cycles on the same 2-D unit-square {'CDR ' if pde else ''}p={p} problem at h=1/{nel_s} "
                    f"(n={o.n}; the timed workload is h=1/{nel_full}, n={n_full}): {cycles} cycles in "
                    f"{el:.1f} s, setup {t_setup:.1f} s excluded; single-threaded C, FP64"),
     }
@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--degree", type=int, default=5)
     ap.add_argument("--nel", type=int, default=1024)
     ap.add_argument("--dim", type=int, default=2)
+    ap.add_argument("--pde", choices=("poisson", "cdr"), default="poisson",
+                    help="cdr: benchmark 2's convection-diffusion-reaction operator on the unit square")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--serve", action="store_true", help="continuous-batching serving benchmark")
@@ -272,7 +274,8 @@ def main():
                           "launches": 3}))
         return
     t0 = time.perf_counter()
-    s = pmg.Solver(dim=args.dim, degree=args.degree, n_elem=args.nel, device=0)
+    pde = pmg.PDE_CDR if args.pde == "cdr" else pmg.PDE_POISSON
+    s = pmg.Solver(dim=args.dim, degree=args.degree, n_elem=args.nel, pde=pde, device=0)
     t_setup = time.perf_counter() - t0
     info = s.info
     n = s.n
@@ -344,6 +347,8 @@ def main():
     achieved = nbytes / avg_s / 1e9
     workload = f"2d-unit-square-p{args.degree}-h1/{args.nel}" if args.dim == 2 else \
         f"3d-unit-cube-p{args.degree}-h1/{args.nel}"
+    if pde == pmg.PDE_CDR:
+        workload = f"2d-unit-square-cdr-p{args.degree}-h1/{args.nel}"
     roofline = {
         "bound": "hbm",
         "kernel": KERNELS[dom][0],
@@ -374,7 +379,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "dim": args.dim, "degree": args.degree, "n_elem": args.nel,
+        "config": {"workload": workload, "pde": args.pde, "dim": args.dim, "degree": args.degree, "n_elem": args.nel,
                    "unknowns": n, "precision": "fp64", "ilut": [1e-12, 1.0], "final_relres": rel,
                    "setup_s": round(t_setup, 1), "parallelism": "1 GPU"},
         "roofline": roofline,
@@ -382,7 +387,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.degree, args.nel, n, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.degree, args.nel, n, args.cpu_budget, pde=pde)
     print(json.dumps(out), flush=True)
 
 
