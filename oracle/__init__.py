@@ -45,7 +45,8 @@ def build(force: bool = True) -> str:
 class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("fill", C.c_double), ("limit_mode", C.c_int),
                 ("coarse_cycles", C.c_int), ("gs_variant", C.c_int), ("coarse_min", C.c_int),
-                ("nu1", C.c_int), ("nu2", C.c_int), ("ordering", C.c_int), ("nd_leaf", C.c_int)]
+                ("nu1", C.c_int), ("nu2", C.c_int), ("ordering", C.c_int), ("nd_leaf", C.c_int),
+                ("mass_transfer", C.c_int)]
 
 
 _lib = None
@@ -79,6 +80,8 @@ def lib():
         L.orc_residual.argtypes = [vp, dp, dp, dp]
         L.orc_smooth.argtypes = [vp, dp, dp]
         L.orc_hcycle.argtypes = [vp, dp, dp]
+        L.orc_restrict.argtypes = [vp, dp, dp]
+        L.orc_prolong.argtypes = [vp, dp, dp]
         L.orc_coarse.argtypes = [vp, dp, dp]
         L.orc_gs.argtypes = [vp, C.c_int, dp, dp]
         L.orc_gauss.argtypes = [C.c_int, dp, dp]
@@ -119,10 +122,11 @@ class Options:
     nu2: int = 1
     ordering: int = 1        # 0: natural, 1: nested dissection over grid lines
     nd_leaf: int = 8
+    mass_transfer: int = 0   # 0: lumped masses in the transfers, 1: consistent (App. B)
 
     def c(self):
         return _Opts(self.tau, self.fill, self.limit_mode, self.coarse_cycles, self.gs_variant,
-                     self.coarse_min, self.nu1, self.nu2, self.ordering, self.nd_leaf)
+                     self.coarse_min, self.nu1, self.nu2, self.ordering, self.nd_leaf, self.mass_transfer)
 
 
 # ---------------------------------------------------------------- primitives
@@ -316,6 +320,18 @@ class Oracle:
         e1 = np.zeros(self.n1)
         lib().orc_coarse(self._h, _dp(np.ascontiguousarray(r1, dtype=np.float64)), _dp(e1))
         return e1
+
+    def restrict(self, r):
+        """r1 = M_1^{-1} P_p^1 r with the lumped or consistent mass of the options."""
+        r1 = np.zeros(self.n1)
+        lib().orc_restrict(self._h, _dp(np.ascontiguousarray(r, dtype=np.float64)), _dp(r1))
+        return r1
+
+    def prolong_delta(self, e1):
+        """y = M_p^{-1} P_1^p e1 (the correction added to u by the prolongation)."""
+        y = np.zeros(self.n)
+        lib().orc_prolong(self._h, _dp(np.ascontiguousarray(e1, dtype=np.float64)), _dp(y))
+        return y
 
     def hcycle(self, b1, e1):
         e1 = np.array(e1, dtype=np.float64, copy=True)

@@ -838,6 +838,7 @@ typedef struct {
   double tau, fill;
   int limit_mode, coarse_cycles, gs_variant, coarse_min, nu1, nu2;
   int ordering, nd_leaf;
+  int mass_transfer; /* 0: lumped masses in the transfers (Section 3), 1: consistent (App. B) */
 } orc_opts;
 
 typedef struct {
@@ -853,6 +854,7 @@ typedef struct {
   int nlev;
   int lnel[MAXLEV], ln[MAXLEV];
   ocsr A1[MAXLEV];
+  ocsr Mp, M1;      /* consistent interior mass matrices (mass_transfer = 1) */
   ocsr Ph[MAXLEV];  /* Ph[l]: level l (fine) x level l+1 (coarse) */
   ocsr Rh[MAXLEV];  /* transpose */
   double *chol;     /* dense lower Cholesky factor of the coarsest level */
@@ -876,6 +878,7 @@ void orc_default_opts(orc_opts *o) {
   o->nu2 = 1;
   o->ordering = 1;  /* nested dissection over grid lines */
   o->nd_leaf = 8;
+  o->mass_transfer = 0; /* Section 3: lumped */
 }
 
 static int dense_cholesky(const ocsr *A, double **out) {
@@ -965,6 +968,7 @@ static void dense_chol_solve(const double *C, int n, const double *b, double *x)
 void orc_free(orc *s) {
   if (!s) return;
   csr_free(&s->A); csr_free(&s->L); csr_free(&s->U); csr_free(&s->R); csr_free(&s->Pr);
+  csr_free(&s->Mp); csr_free(&s->M1);
   for (int l = 0; l < MAXLEV; ++l) {
     csr_free(&s->A1[l]); csr_free(&s->Ph[l]); csr_free(&s->Rh[l]);
     free(s->hv_b[l]); free(s->hv_e[l]); free(s->hv_r[l]);
@@ -1095,6 +1099,10 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *
   if (!rc) rc = lumped_mass(&M, p, p + 1, s->mlp);
   if (!rc && s->n1 > 0) rc = lumped_mass(&M, 1, 2, s->ml1);
   if (!rc && s->n1 > 0) rc = assemble(&M, 1, p, 1, p + 1, 1, &s->Pr);
+  if (!rc && s->n1 > 0 && s->o.mass_transfer) {
+    rc = assemble(&M, 1, p, p, p + 1, 1, &s->Mp);
+    if (!rc) rc = assemble(&M, 1, 1, 1, 2, 1, &s->M1);
+  }
   if (!rc && s->n1 > 0) rc = csr_transpose(&s->Pr, &s->R);
   /* P1 hierarchy */
   int l = 0, ne = nel;
@@ -1248,13 +1256,50 @@ void orc_coarse(orc *s, const double *r1, double *e1) {
  *   u += (M_p^L)^{-1} P_1^p e1                 (lumped L2 prolongation),
  *   nu2 ILUT post-smoothing steps.
  * On entry r must hold f - A u; on exit it holds f - A u for the new u. */
+/* Consistent transfers (App. B): x = M^{-1} b for an interior mass matrix,
+ * by plain conjugate gradients from x = 0 until ||b - M x|| <= 1e-14 ||b||
+ * (M is symmetric positive definite and well conditioned). */
+static void mass_solve(const ocsr *M, const double *b, double *x) {
+  int n = M->nrows;
+  double *r = malloc(sizeof(double) * n), *pv = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
+  double bb = 0.0;
+  for (int i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; pv[i] = b[i]; bb += b[i] * b[i]; }
+  double rr = bb;
+  for (int it = 0; it < 20000 && rr > 1e-28 * bb; ++it) {
+    csr_mv(M, pv, q);
+    double pq = 0.0;
+    for (int i = 0; i < n; ++i) pq += pv[i] * q[i];
+    double alpha = rr / pq, rr2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      x[i] += alpha * pv[i];
+      r[i] -= alpha * q[i];
+      rr2 += r[i] * r[i];
+    }
+    double beta = rr2 / rr;
+    for (int i = 0; i < n; ++i) pv[i] = r[i] + beta * pv[i];
+    rr = rr2;
+  }
+  free(r); free(pv); free(q);
+}
+
 void orc_vcycle(orc *s, const double *b, double *x, double *r) {
   int n = s->n, n1 = s->n1;
   for (int k = 0; k < s->o.nu1; ++k) {
     ilut_smooth(s, r, x, s->y);
     residual(&s->A, b, x, r);
   }
-  if (n1 > 0) {
+  if (n1 > 0 && s->o.mass_transfer) {
+    /* r1 = M_1^{-1} P_p^1 r, u += M_p^{-1} P_1^p e1 with consistent masses */
+    double *t1 = malloc(sizeof(double) * n1), *t = malloc(sizeof(double) * n), *dx = malloc(sizeof(double) * n);
+    csr_mv(&s->R, r, t1);
+    mass_solve(&s->M1, t1, s->r1);
+    orc_coarse(s, s->r1, s->e1);
+    csr_mv(&s->Pr, s->e1, t);
+    mass_solve(&s->Mp, t, dx);
+    for (int i = 0; i < n; ++i) x[i] += dx[i];
+    free(t1); free(t); free(dx);
+    residual(&s->A, b, x, r);
+  } else if (n1 > 0) {
     csr_mv(&s->R, r, s->r1);
     for (int i = 0; i < n1; ++i) s->r1[i] = s->r1[i] / s->ml1[i];
     orc_coarse(s, s->r1, s->e1);
@@ -1534,6 +1579,30 @@ int orc_get_vec(const orc *s, int which, double *out) {
 void orc_residual(const orc *s, const double *b, const double *x, double *r) { residual(&s->A, b, x, r); }
 void orc_smooth(orc *s, const double *r, double *x) { ilut_smooth(s, r, x, s->y); }
 void orc_hcycle(orc *s, const double *b, double *e) { hcycle(s, 0, b, e); }
+/* Transfers as the V-cycle applies them (lumped or consistent per the options):
+ * r1 = M_1^{-1} P_p^1 r and y = M_p^{-1} P_1^p e1. */
+void orc_restrict(orc *s, const double *r, double *r1) {
+  csr_mv(&s->R, r, r1);
+  if (s->o.mass_transfer) {
+    double *t = malloc(sizeof(double) * s->n1);
+    memcpy(t, r1, sizeof(double) * s->n1);
+    mass_solve(&s->M1, t, r1);
+    free(t);
+  } else {
+    for (int i = 0; i < s->n1; ++i) r1[i] /= s->ml1[i];
+  }
+}
+void orc_prolong(orc *s, const double *e1, double *y) {
+  csr_mv(&s->Pr, e1, y);
+  if (s->o.mass_transfer) {
+    double *t = malloc(sizeof(double) * s->n);
+    memcpy(t, y, sizeof(double) * s->n);
+    mass_solve(&s->Mp, t, y);
+    free(t);
+  } else {
+    for (int i = 0; i < s->n; ++i) y[i] /= s->mlp[i];
+  }
+}
 void orc_gs(orc *s, int lev, const double *b, double *e) { gs_sweep(s, lev, b, e); }
 
 /* Assembly of one operator on its own, for the pins: kind 0 stiffness,
