@@ -52,6 +52,7 @@ typedef enum {
 enum { PMG_GEOM_BOX = 0, PMG_GEOM_QUARTER_ANNULUS = 1 };
 enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1 };
 enum { PMG_PDE_POISSON = 0, PMG_PDE_CDR = 1 };
+enum { PMG_MASS_LUMPED = 0, PMG_MASS_CONSISTENT = 1 };
 enum { PMG_FP64 = 0, PMG_FP32_IN_FP64 = 1 };
 enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1 };
 enum { PMG_GS_MULTICOLOR = 0 };
@@ -108,6 +109,13 @@ typedef struct {
                                restriction as one tiled launch, and the prolongation with
                                the sweeps after it (up to 2 sweeps each); 0: one launch
                                per colour and per transfer.  Results are identical. */
+  int32_t mass_transfer;    /* PMG_MASS_LUMPED (default, Section 3): the transfers divide by
+                               the row-sum lumped masses; PMG_MASS_CONSISTENT (Appendix B):
+                               they solve with the consistent interior mass matrices M_1 and
+                               M_p instead (conjugate gradients preconditioned by the lumped
+                               masses, to 1e-13 relative).  Consistent: FP64 only, and the
+                               steps run kernel by kernel (graphs off), as the inner solves
+                               test convergence on the host. */
 } pmg_options;
 
 typedef struct {

@@ -224,6 +224,51 @@ __global__ __launch_bounds__(256) void dot2_partials(int64_t n, const double* __
   block_sum2(s1, s2, pa, c ? pb : nullptr);
 }
 
+// Conjugate gradients for the consistent-mass transfers (Appendix B), with
+// the inverse lumped mass dinv as preconditioner.  cg_init: x = 0, r = b,
+// z = dinv .* b, p = z, partials of b.b and b.z; cg_step: x += a p,
+// r -= a q, z = dinv .* r, partials of r.r and r.z; cg_dir: p = z + c p.
+__global__ __launch_bounds__(256) void cg_init(int64_t n, const double* __restrict__ b, const double* __restrict__ dinv,
+                                               double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                                               double* __restrict__ p, double* __restrict__ pa, double* __restrict__ pb) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double bi = b[i], zi = dinv[i] * bi;
+    x[i] = 0.0;
+    r[i] = bi;
+    z[i] = zi;
+    p[i] = zi;
+    s1 += bi * bi;
+    s2 += bi * zi;
+  }
+  block_sum2(s1, s2, pa, pb);
+}
+
+__global__ __launch_bounds__(256) void cg_step(int64_t n, double a, const double* __restrict__ p,
+                                               const double* __restrict__ q, const double* __restrict__ dinv,
+                                               double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                                               double* __restrict__ pa, double* __restrict__ pb) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i], zi = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = zi;
+    s1 += ri * ri;
+    s2 += ri * zi;
+  }
+  block_sum2(s1, s2, pa, pb);
+}
+
+__global__ __launch_bounds__(256) void cg_dir(int64_t n, double c, const double* __restrict__ z, double* __restrict__ p) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = z[i] + c * p[i];
+}
+
+// x += y
+__global__ __launch_bounds__(256) void add_vec(int64_t n, const double* __restrict__ y, double* __restrict__ x) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] += y[i];
+}
+
 // S[ia] = sum of pa (and S[ib] = sum of pb if ib >= 0); with shift_rho the
 // old S[0] is first saved in S[1].  One block.
 __global__ __launch_bounds__(256) void bicg_reduce(int nb, const double* __restrict__ pa, const double* __restrict__ pb,

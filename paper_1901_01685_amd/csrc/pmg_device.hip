@@ -862,13 +862,80 @@ void coarse_impl(pmg_handle h, Workspace& ws, const double* r1, double* e1, hipS
   for (int c = 0; c < h->opt.coarse_cycles; ++c) hcycle(h, ws, 0, r1, e1, st);
 }
 
-void restrict64(pmg_handle h, const double* r, double* r1, hipStream_t st) {
+// x = M^{-1} b for a consistent interior mass matrix M (Appendix B) by
+// conjugate gradients preconditioned with the inverse lumped mass dinv, from
+// x = 0 until ||b - M x|| <= 1e-13 ||b|| or 20000 steps (the count is
+// independent of h but grows with p: about 250 at p = 3 and 1600 at p = 5,
+// the lumped masses being a weak preconditioner at high degree).  The two
+// scalars of a step are summed on the host from the block partials, in
+// block order.
+void mass_solve(pmg_handle h, Workspace& ws, const DevMat& M, const double* dinv, const double* b, double* x,
+                hipStream_t st) {
+  const int64_t n = M.nrows;
+  const unsigned nb = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+  auto sums = [&](double& a, double* c) {
+    hipMemcpyAsync(ws.cg_host, ws.cg_pa, nb * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (c) hipMemcpyAsync(ws.cg_host + kMaxCsrBlocks, ws.cg_pb, nb * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    a = 0.0;
+    for (unsigned i = 0; i < nb; ++i) a += ws.cg_host[i];
+    if (c) {
+      *c = 0.0;
+      for (unsigned i = 0; i < nb; ++i) *c += ws.cg_host[kMaxCsrBlocks + i];
+    }
+  };
+  pmg::cg_init<<<nb, 256, 0, st>>>(n, b, dinv, x, ws.cg_r, ws.cg_z, ws.cg_p, ws.cg_pa, ws.cg_pb);
+  double bb, rz;
+  sums(bb, &rz);
+  if (!(bb > 0.0)) return;
+  for (int it = 0; it < 20000; ++it) {
+    csr_launch<double>(pmg::kPlain, (int)n, nullptr, M, M.v, ws.cg_p, nullptr, nullptr, ws.cg_q, nullptr, st);
+    pmg::dot2_partials<<<nb, 256, 0, st>>>(n, ws.cg_p, ws.cg_q, nullptr, nullptr, ws.cg_pa, nullptr);
+    double pq;
+    sums(pq, nullptr);
+    if (!(pq > 0.0)) return;
+    pmg::cg_step<<<nb, 256, 0, st>>>(n, rz / pq, ws.cg_p, ws.cg_q, dinv, x, ws.cg_r, ws.cg_z, ws.cg_pa, ws.cg_pb);
+    double rr, rz2;
+    sums(rr, &rz2);
+    if (rr <= 1e-26 * bb) return;
+    pmg::cg_dir<<<nb, 256, 0, st>>>(n, rz2 / rz, ws.cg_z, ws.cg_p);
+    rz = rz2;
+  }
+}
+
+pmg_status alloc_mass(pmg_handle h, Workspace& ws) {
+  if (ws.cg_host) return PMG_OK;
+  const int64_t n = h->H.n;
+  pmgdev::DevArena& m = ws.mem;
+  pmg_status s;
+  for (double** v : {&ws.cg_r, &ws.cg_z, &ws.cg_p, &ws.cg_q, &ws.cg_t, &ws.cg_y})
+    if ((s = m.alloc(v, n))) return s;
+  if ((s = m.alloc(&ws.cg_pa, kMaxCsrBlocks))) return s;
+  if ((s = m.alloc(&ws.cg_pb, kMaxCsrBlocks))) return s;
+  PMG_HIP_OK(hipHostMalloc((void**)&ws.cg_host, 2 * kMaxCsrBlocks * sizeof(double), hipHostMallocDefault));
+  return PMG_OK;
+}
+
+// r1 = M_1^{-1} P_p^1 r: lumped (Section 3) or consistent (Appendix B) mass
+void restrict64(pmg_handle h, Workspace& ws, const double* r, double* r1, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_RESTRICT, st);
+  if (h->opt.mass_transfer == PMG_MASS_CONSISTENT) {
+    csr_launch<double>(pmg::kPlain, h->R.nrows, nullptr, h->R, h->R.v, r, nullptr, nullptr, ws.cg_t, nullptr, st);
+    mass_solve(h, ws, h->M1, h->ml1_inv, ws.cg_t, r1, st);
+    return;
+  }
   transfer<double>(h->R, h->Rs, h->prob.dim, r, h->ml1_inv, r1, false, st);
 }
 
-void prolong64(pmg_handle h, const double* e1, double* x, hipStream_t st) {
+// x += M_p^{-1} P_1^p e1: lumped or consistent mass
+void prolong64(pmg_handle h, Workspace& ws, const double* e1, double* x, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_PROLONG, st);
+  if (h->opt.mass_transfer == PMG_MASS_CONSISTENT) {
+    csr_launch<double>(pmg::kPlain, h->P.nrows, nullptr, h->P, h->P.v, e1, nullptr, nullptr, ws.cg_t, nullptr, st);
+    mass_solve(h, ws, h->Mp, h->mlp_inv, ws.cg_t, ws.cg_y, st);
+    pmg::add_vec<<<std::min<unsigned>(nblocks(h->P.nrows, 256), kMaxCsrBlocks), 256, 0, st>>>(h->P.nrows, ws.cg_y, x);
+    return;
+  }
   transfer<double>(h->P, h->Ps, h->prob.dim, e1, h->mlp_inv, x, true, st);
 }
 
@@ -970,6 +1037,7 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
     if ((s = m.alloc(&ws.hr[l], H.ln[l]))) return s;
   if ((s = m.alloc(&ws.tickets, 4))) return s;
   fill<unsigned>(ws.tickets, 4, 0u, st);
+  if (h->opt.mass_transfer == PMG_MASS_CONSISTENT && H.n1 > 0 && (s = alloc_mass(h, ws))) return s;
   PMG_HIP_OK(hipGetLastError());
   if (mixed) {
     if ((s = m.alloc(&ws.r32, n))) return s;
@@ -1008,9 +1076,9 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
     residual64(h, ws, b, x, r, false, st);
   }
   if (h->H.n1 > 0) {
-    restrict64(h, r, ws.r1, st);
+    restrict64(h, ws, r, ws.r1, st);
     coarse_impl(h, ws, ws.r1, ws.e1, st);
-    prolong64(h, ws.e1, x, st);
+    prolong64(h, ws, ws.e1, x, st);
     if (nu2 > 0 || final_resid) residual64(h, ws, b, x, r, nu2 == 0 && norm, st);
   }
   for (int k = 0; k < nu2; ++k) {
@@ -1199,6 +1267,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->nd_leaf = 8;
   o->graphs = 1;
   o->tiled_gs = 1;
+  o->mass_transfer = PMG_MASS_LUMPED;
   return PMG_OK;
 }
 
@@ -1214,12 +1283,17 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
       !(o.ilut_tau >= 0) || o.gs_variant != PMG_GS_MULTICOLOR ||
       (o.precision != PMG_FP64 && o.precision != PMG_FP32_IN_FP64) ||
       (o.ilut_limit_mode != PMG_LIMIT_PER_PART && o.ilut_limit_mode != PMG_LIMIT_PER_ROW) || o.device < -1 ||
-      (o.ordering != PMG_ORDER_NATURAL && o.ordering != PMG_ORDER_NESTED_DISSECTION) || o.nd_leaf < 1)
+      (o.ordering != PMG_ORDER_NATURAL && o.ordering != PMG_ORDER_NESTED_DISSECTION) || o.nd_leaf < 1 ||
+      (o.mass_transfer != PMG_MASS_LUMPED && o.mass_transfer != PMG_MASS_CONSISTENT) ||
+      (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64))
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
   h->opt = o;
+  // the consistent-mass inner solves test convergence on the host: no graphs
+  if (o.mass_transfer == PMG_MASS_CONSISTENT) h->opt.graphs = 0;
   pmg::SetupParams sp;
+  sp.consistent_mass = o.mass_transfer == PMG_MASS_CONSISTENT;
   sp.dim = prob->dim;
   sp.p = prob->degree;
   sp.nel = prob->n_elem;
@@ -1333,6 +1407,10 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     if (n1 > 0) {
       if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
       if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
+      if (sp.consistent_mass) {
+        if ((s = upload_mat(m, H.Mp, h->Mp, false))) return s;
+        if ((s = upload_mat(m, H.M1, h->M1, false))) return s;
+      }
       const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem - 1;
       if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
       if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
@@ -1588,7 +1666,7 @@ pmg_status pmg_restrict(pmg_handle h, const double* r, double* r1, void* stream)
   NEED_DEVICE(h);
   if (!r || !r1) return fail(PMG_EINVAL, "NULL vector");
   if (h->H.n1 == 0) return PMG_OK;
-  restrict64(h, r, r1, (hipStream_t)stream);
+  restrict64(h, h->ws, r, r1, (hipStream_t)stream);
   PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
@@ -1606,7 +1684,7 @@ pmg_status pmg_prolong(pmg_handle h, const double* e1, double* x, void* stream) 
   NEED_DEVICE(h);
   if (!e1 || !x) return fail(PMG_EINVAL, "NULL vector");
   if (h->H.n1 == 0) return PMG_OK;
-  prolong64(h, e1, x, (hipStream_t)stream);
+  prolong64(h, h->ws, e1, x, (hipStream_t)stream);
   PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }

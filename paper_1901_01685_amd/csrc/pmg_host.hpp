@@ -19,6 +19,7 @@ struct Csr {
 
 struct SetupParams {
   int dim = 2, p = 2, nel = 16, geom = 0, rhs = 0, pde = 0;
+  bool consistent_mass = false;  // also assemble the consistent mass matrices Mp, M1
   int freq[3] = {1, 1, 1};
   double tau = 1e-12, fill = 1.0;
   int limit_mode = 0;
@@ -34,6 +35,7 @@ struct HostOps {
   std::vector<int32_t> perm;   // position i of the factors holds unknown perm[i]
   Csr R;                       // P_p^1 (n1 x n)
   Csr P;                       // P_1^p (n x n1)
+  Csr Mp, M1;                  // consistent interior mass matrices (only when requested)
   std::vector<double> f, mlp, ml1;
   int nlev = 0;
   std::vector<int> lnel, ln;   // elements / unknowns per degree-1 level

@@ -115,6 +115,11 @@ struct Workspace {
   // scalars (see pmg::bicg_*), block partials and a pinned host copy
   double *bc_rh = nullptr, *bc_p = nullptr, *bc_v = nullptr, *bc_y = nullptr, *bc_z = nullptr, *bc_t = nullptr,
          *bc_w = nullptr, *bc_S = nullptr, *bc_pa = nullptr, *bc_pb = nullptr, *bc_host = nullptr;
+  // conjugate gradients of the consistent-mass transfers: residual, preconditioned
+  // residual, direction, M p, the transferred right-hand side and solution,
+  // block partials and a pinned host copy of them
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_t = nullptr, *cg_y = nullptr,
+         *cg_pa = nullptr, *cg_pb = nullptr, *cg_host = nullptr;
   // cached graph of one outer step (outer_step), captured on `cap` and valid
   // for the handle and vectors it was captured with
   hipStream_t cap = nullptr;
@@ -127,6 +132,7 @@ struct Workspace {
     mem.release();
     if (host_scalar) hipHostFree(host_scalar);
     if (bc_host) hipHostFree(bc_host);
+    if (cg_host) hipHostFree(cg_host);
   }
 };
 
@@ -141,6 +147,7 @@ struct pmg_handle_s {
   int colors = 4;
   pmgdev::DevArena ops;  // operators (read-only during solves)
   pmgdev::DevMat A, L, U, R, P;
+  pmgdev::DevMat Mp, M1;  // consistent masses (mass_transfer = consistent)
   pmgdev::DevStencil As;  // A in stencil layout (As.v == nullptr: CSR is used)
   int a_stencil = 0;      // offsets of that layout, 0 if CSR is used
   pmgdev::DevXStencil Rs, Ps;  // P_p^1 and P_1^p in stencil layout

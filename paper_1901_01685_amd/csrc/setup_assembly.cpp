@@ -793,6 +793,17 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
     element_vectors_2d(1, sp.rhs, sp.freq, 1, nel, 2, nullptr, &H.ml1);
   }
   H.R = transpose(H.P);
+  if (sp.consistent_mass) {
+    // Appendix B: consistent interior mass matrices of degree p and 1
+    if (sp.geom == 0) {
+      Band1D Mq = matrix_1d(1, p, p, nel, p + 1), M1q = matrix_1d(1, 1, 1, nel, 2);
+      H.Mp = kron_assemble(dim, {std::vector<const Band1D*>(dim, &Mq)}, th);
+      H.M1 = kron_assemble(dim, {std::vector<const Band1D*>(dim, &M1q)}, th);
+    } else {
+      H.Mp = element_assemble_2d(1, 1, p, p, nel, p + 1, th);
+      H.M1 = element_assemble_2d(1, 1, 1, 1, nel, 2, th);
+    }
+  }
   // ---- degree-1 hierarchy by rediscretisation
   int ne = nel;
   H.A1.clear();

@@ -159,3 +159,14 @@ def test_cdr_configurations_checked():
     with pytest.raises(P.PmgError) as e:
         P.Solver(2, 2, 8, pde=7, device=-1)
     assert e.value.status == P.EINVAL
+
+
+def test_mass_transfer_options_checked():
+    with pytest.raises(P.PmgError) as e:
+        P.Solver(2, 2, 8, mass_transfer=2, device=-1)
+    assert e.value.status == P.EINVAL
+    with pytest.raises(P.PmgError) as e:       # consistent masses run in FP64 only
+        P.Solver(2, 2, 8, mass_transfer=P.MASS_CONSISTENT, precision=P.FP32_IN_FP64, device=-1)
+    assert e.value.status == P.EINVAL
+    s = P.Solver(2, 3, 16, geometry=1, rhs_kind=1, mass_transfer=P.MASS_CONSISTENT, device=-1)
+    assert s.options.mass_transfer == P.MASS_CONSISTENT
