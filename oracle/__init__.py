@@ -46,7 +46,7 @@ class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("fill", C.c_double), ("limit_mode", C.c_int),
                 ("coarse_cycles", C.c_int), ("gs_variant", C.c_int), ("coarse_min", C.c_int),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("ordering", C.c_int), ("nd_leaf", C.c_int),
-                ("mass_transfer", C.c_int)]
+                ("mass_transfer", C.c_int), ("projection", C.c_int)]
 
 
 _lib = None
@@ -123,10 +123,12 @@ class Options:
     ordering: int = 1        # 0: natural, 1: nested dissection over grid lines
     nd_leaf: int = 8
     mass_transfer: int = 0   # 0: lumped masses in the transfers, 1: consistent (App. B)
+    projection: int = 0      # 0: direct p -> 1, 1: indirect p -> p-1 -> ... -> 1 (App. A)
 
     def c(self):
         return _Opts(self.tau, self.fill, self.limit_mode, self.coarse_cycles, self.gs_variant,
-                     self.coarse_min, self.nu1, self.nu2, self.ordering, self.nd_leaf, self.mass_transfer)
+                     self.coarse_min, self.nu1, self.nu2, self.ordering, self.nd_leaf, self.mass_transfer,
+                     self.projection)
 
 
 # ---------------------------------------------------------------- primitives

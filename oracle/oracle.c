@@ -839,6 +839,7 @@ typedef struct {
   int limit_mode, coarse_cycles, gs_variant, coarse_min, nu1, nu2;
   int ordering, nd_leaf;
   int mass_transfer; /* 0: lumped masses in the transfers (Section 3), 1: consistent (App. B) */
+  int projection;    /* 0: direct p -> 1 (Section 3), 1: indirect p -> p-1 -> ... -> 1 (App. A) */
 } orc_opts;
 
 typedef struct {
@@ -855,6 +856,8 @@ typedef struct {
   int lnel[MAXLEV], ln[MAXLEV];
   ocsr A1[MAXLEV];
   ocsr Mp, M1;      /* consistent interior mass matrices (mass_transfer = 1) */
+  int cdeg;         /* degree of the coarse space of the transfers (1 unless indirect) */
+  void *sub;        /* indirect projection: the degree p-1 level (an orc), else NULL */
   ocsr Ph[MAXLEV];  /* Ph[l]: level l (fine) x level l+1 (coarse) */
   ocsr Rh[MAXLEV];  /* transpose */
   double *chol;     /* dense lower Cholesky factor of the coarsest level */
@@ -879,6 +882,7 @@ void orc_default_opts(orc_opts *o) {
   o->ordering = 1;  /* nested dissection over grid lines */
   o->nd_leaf = 8;
   o->mass_transfer = 0; /* Section 3: lumped */
+  o->projection = 0;    /* Section 3: direct projection to p = 1 */
 }
 
 static int dense_cholesky(const ocsr *A, double **out) {
@@ -967,6 +971,7 @@ static void dense_chol_solve(const double *C, int n, const double *b, double *x)
 
 void orc_free(orc *s) {
   if (!s) return;
+  if (s->sub) orc_free((orc *)s->sub);
   csr_free(&s->A); csr_free(&s->L); csr_free(&s->U); csr_free(&s->R); csr_free(&s->Pr);
   csr_free(&s->Mp); csr_free(&s->M1);
   for (int l = 0; l < MAXLEV; ++l) {
@@ -1089,7 +1094,12 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *
   if (o) s->o = *o; else orc_default_opts(&s->o);
   omesh M = {dim, geom, nel};
   s->n = ipow(nel + p - 2, dim);
-  s->n1 = ipow(nel - 1, dim);
+  /* Indirect projection (App. A): the transfers go to degree p-1 on the same
+   * mesh and the coarse correction is one V-cycle of that level, down to
+   * degree 2, whose coarse space is the degree-1 space of the direct method. */
+  const int cdeg = (s->o.projection == 1 && p > 2) ? p - 1 : 1;
+  s->cdeg = cdeg;
+  s->n1 = ipow(nel + cdeg - 2, dim);
   const int akind = pde == ORC_PDE_CDR ? 2 : 0;
   int rc = assemble(&M, akind, p, p, p + 1, 1, &s->A);
   s->f = malloc(sizeof(double) * s->n);
@@ -1097,16 +1107,25 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *
   s->mlp = malloc(sizeof(double) * s->n);
   s->ml1 = malloc(sizeof(double) * (s->n1 > 0 ? s->n1 : 1));
   if (!rc) rc = lumped_mass(&M, p, p + 1, s->mlp);
-  if (!rc && s->n1 > 0) rc = lumped_mass(&M, 1, 2, s->ml1);
-  if (!rc && s->n1 > 0) rc = assemble(&M, 1, p, 1, p + 1, 1, &s->Pr);
+  if (!rc && s->n1 > 0) rc = lumped_mass(&M, cdeg, cdeg + 1, s->ml1);
+  if (!rc && s->n1 > 0) rc = assemble(&M, 1, p, cdeg, p + 1, 1, &s->Pr);
   if (!rc && s->n1 > 0 && s->o.mass_transfer) {
     rc = assemble(&M, 1, p, p, p + 1, 1, &s->Mp);
-    if (!rc) rc = assemble(&M, 1, 1, 1, 2, 1, &s->M1);
+    if (!rc) rc = assemble(&M, 1, cdeg, cdeg, cdeg + 1, 1, &s->M1);
   }
   if (!rc && s->n1 > 0) rc = csr_transpose(&s->Pr, &s->R);
+  if (cdeg > 1) {
+    /* the degree p-1 level, itself indirect down to degree 2 */
+    int st2 = ORC_OK;
+    if (!rc) {
+      s->sub = orc_create(dim, p - 1, nel, geom, rhs, pde, s->freq, &s->o, stage_mask, &st2);
+      if (!s->sub) rc = ORC_ENOMEM;
+      else if (st2) rc = st2;
+    }
+  }
   /* P1 hierarchy */
   int l = 0, ne = nel;
-  while (!rc) {
+  while (!rc && cdeg == 1) {
     omesh Ml = {dim, geom, ne};
     s->lnel[l] = ne;
     s->ln[l] = ipow(ne - 1, dim);
@@ -1118,8 +1137,8 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *
     ne /= 2;
     l++;
   }
-  s->nlev = l + 1;
-  if (!rc && s->n1 > 0)
+  s->nlev = cdeg == 1 ? l + 1 : 0;
+  if (!rc && s->n1 > 0 && cdeg == 1)
     rc = pde == ORC_PDE_CDR ? dense_lu(&s->A1[s->nlev - 1], &s->lu, &s->piv)
                             : dense_cholesky(&s->A1[s->nlev - 1], &s->chol);
   s->perm = make_ordering(dim, nel + p - 2, p, s->o.ordering, s->o.nd_leaf);
@@ -1243,19 +1262,23 @@ static void hcycle(orc *s, int l, const double *b, double *e) {
 
 /* Coarse correction at p = 1: e1 = 0, then coarse_cycles h-multigrid
  * V-cycles on A_{h,1} e1 = r1. */
+void orc_vcycle(orc *s, const double *b, double *x, double *r);
+
+/* Coarse correction e1 ~ A_c^{-1} r1: coarse_cycles h-multigrid V-cycles at
+ * p = 1, or (indirect projection) one V-cycle of the degree p-1 level from
+ * e1 = 0. */
 void orc_coarse(orc *s, const double *r1, double *e1) {
   memset(e1, 0, sizeof(double) * s->n1);
+  if (s->sub) {
+    double *r = malloc(sizeof(double) * s->n1);
+    memcpy(r, r1, sizeof(double) * s->n1);  /* residual of e1 = 0 */
+    orc_vcycle((orc *)s->sub, r1, e1, r);
+    free(r);
+    return;
+  }
   for (int c = 0; c < s->o.coarse_cycles; ++c) hcycle(s, 0, r1, e1);
 }
 
-/* One p-multigrid V-cycle with direct projection to p = 1 (Section 3,
- * two-grid correction steps 1-5 and Figure 1, upper part):
- *   nu1 ILUT pre-smoothing steps, r = f - A u,
- *   r1 = (M_1^L)^{-1} P_p^1 r                 (lumped L2 restriction),
- *   e1 ~ A_{h,1}^{-1} r1                       (coarse_cycles h-MG V-cycles),
- *   u += (M_p^L)^{-1} P_1^p e1                 (lumped L2 prolongation),
- *   nu2 ILUT post-smoothing steps.
- * On entry r must hold f - A u; on exit it holds f - A u for the new u. */
 /* Consistent transfers (App. B): x = M^{-1} b for an interior mass matrix,
  * by plain conjugate gradients from x = 0 until ||b - M x|| <= 1e-14 ||b||
  * (M is symmetric positive definite and well conditioned). */
@@ -1282,6 +1305,16 @@ static void mass_solve(const ocsr *M, const double *b, double *x) {
   free(r); free(pv); free(q);
 }
 
+/* One p-multigrid V-cycle with direct projection to p = 1 (Section 3,
+ * two-grid correction steps 1-5 and Figure 1, upper part):
+ *   nu1 ILUT pre-smoothing steps, r = f - A u,
+ *   r1 = (M_1^L)^{-1} P_p^1 r                 (lumped L2 restriction),
+ *   e1 ~ A_{h,1}^{-1} r1                       (coarse_cycles h-MG V-cycles),
+ *   u += (M_p^L)^{-1} P_1^p e1                 (lumped L2 prolongation),
+ *   nu2 ILUT post-smoothing steps.
+ * With indirect projection (App. A) the coarse space is degree p-1 and e1
+ * comes from one V-cycle of that level.
+ * On entry r must hold f - A u; on exit it holds f - A u for the new u. */
 void orc_vcycle(orc *s, const double *b, double *x, double *r) {
   int n = s->n, n1 = s->n1;
   for (int k = 0; k < s->o.nu1; ++k) {

@@ -82,12 +82,14 @@ def test_box_stiffness_mass_kronecker_3d(p, nel):
     assert np.abs(Mm - refm).max() < 1e-14 * np.abs(refm).max()
 
 
-@pytest.mark.parametrize("p,nel", [(2, 6), (4, 5)])
-def test_box_transfer_is_kronecker(p, nel):
-    _, _, X = _matrices_1d(p, 1, nel)
+@pytest.mark.parametrize("p,q,nel", [(2, 1, 6), (4, 1, 5), (3, 2, 6), (5, 4, 5)])
+def test_box_transfer_is_kronecker(p, q, nel):
+    """Transfer P_q^p = int phi_{i,p} phi_{j,q}: to degree 1 (direct
+    projection) and to degree p-1 (indirect projection, Appendix A)."""
+    _, _, X = _matrices_1d(p, q, nel)
     Xi = _interior(X)
     ref = np.kron(Xi, Xi)
-    P = O.assemble_only(2, O.GEOM_BOX, nel, 1, p, 1, p + 1, 1).toarray()
+    P = O.assemble_only(2, O.GEOM_BOX, nel, 1, p, q, p + 1, 1).toarray()
     assert np.abs(P - ref).max() < 1e-14 * np.abs(ref).max()
 
 
