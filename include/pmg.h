@@ -53,6 +53,7 @@ enum { PMG_GEOM_BOX = 0, PMG_GEOM_QUARTER_ANNULUS = 1 };
 enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1 };
 enum { PMG_PDE_POISSON = 0, PMG_PDE_CDR = 1 };
 enum { PMG_MASS_LUMPED = 0, PMG_MASS_CONSISTENT = 1 };
+enum { PMG_PROJ_DIRECT = 0, PMG_PROJ_INDIRECT = 1 };
 enum { PMG_FP64 = 0, PMG_FP32_IN_FP64 = 1 };
 enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1 };
 enum { PMG_GS_MULTICOLOR = 0 };
@@ -116,6 +117,13 @@ typedef struct {
                                masses, to 1e-13 relative).  Consistent: FP64 only, and the
                                steps run kernel by kernel (graphs off), as the inner solves
                                test convergence on the host. */
+  int32_t projection;       /* PMG_PROJ_DIRECT (default, Section 3): transfers between degree p
+                               and the degree-1 space; PMG_PROJ_INDIRECT (Appendix A): degree p
+                               transfers to degree p-1 on the same mesh and its coarse
+                               correction is one V-cycle (ILUT smoothing) of an internal
+                               degree-(p-1) handle, recursively down to degree 2, whose coarse
+                               space is degree 1 with the h-multigrid.  Setup builds one
+                               operator, ILUT factorisation and transfer per degree. */
 } pmg_options;
 
 typedef struct {

@@ -22,6 +22,7 @@ GEOM_BOX, GEOM_QUARTER_ANNULUS = 0, 1
 RHS_SINE, RHS_ANNULUS = 0, 1
 PDE_POISSON, PDE_CDR = 0, 1
 MASS_LUMPED, MASS_CONSISTENT = 0, 1
+PROJ_DIRECT, PROJ_INDIRECT = 0, 1
 FP64, FP32_IN_FP64 = 0, 1
 ORDER_NATURAL, ORDER_NESTED_DISSECTION = 0, 1
 OP_A, OP_L, OP_U, OP_R, OP_P, OP_A1, OP_PH = range(7)
@@ -47,7 +48,8 @@ class Options(C.Structure):
                 ("coarse_min_elems", C.c_int32), ("gs_variant", C.c_int32), ("precision", C.c_int32),
                 ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
-                ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32)]
+                ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32),
+                ("projection", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -48,6 +48,7 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 }  // namespace pmgdev
 
 pmg_handle_s::~pmg_handle_s() {
+  delete sub;
   if (on_device) {
     hipSetDevice(device);
     hipDeviceSynchronize();
@@ -393,6 +394,7 @@ pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, D
 // levels halve (nx_l = 2 nx_{l+1} + 1).
 pmg_status upload_grid_levels(pmgdev::DevArena& mem, const pmg::HostOps& H, int dim, std::vector<pmg::GridLevel>& G) {
   G.clear();
+  if (H.nlev < 1) return PMG_OK;  // no degree-1 hierarchy (indirect projection)
   const int nl = H.nlev - 1;  // levels with smoothing (the last is solved directly)
   for (int l = 0; l + 1 < H.nlev; ++l)
     if (H.lnel[l] != 2 * H.lnel[l + 1]) return PMG_OK;
@@ -856,9 +858,19 @@ void hcycle(pmg_handle h, Workspace& ws, int l, const double* b, double* e, hipS
   gs_sweeps(h, l, b, e, h->opt.nu2, st);
 }
 
+// Coarse correction e1 ~ A_c^{-1} r1 from e1 = 0: coarse_cycles h-multigrid
+// V-cycles at p = 1, or (indirect projection) one V-cycle of the degree p-1
+// level, whose own workspace holds its vectors.
 void coarse_impl(pmg_handle h, Workspace& ws, const double* r1, double* e1, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_COARSE, st);
   fill<double>(e1, h->H.n1, 0.0, st);
+  if (h->sub) {
+    pmg_handle c = h->sub;
+    const int64_t nc = c->H.n;
+    pmg::cast_kernel<double, double><<<nblocks(nc, 256), 256, 0, st>>>(nc, r1, c->ws.r);  // residual at e1 = 0
+    pmgdev::vcycle64(c, c->ws, r1, e1, c->ws.r, false, st, false);
+    return;
+  }
   for (int c = 0; c < h->opt.coarse_cycles; ++c) hcycle(h, ws, 0, r1, e1, st);
 }
 
@@ -1268,6 +1280,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->graphs = 1;
   o->tiled_gs = 1;
   o->mass_transfer = PMG_MASS_LUMPED;
+  o->projection = PMG_PROJ_DIRECT;
   return PMG_OK;
 }
 
@@ -1285,7 +1298,8 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
       (o.ilut_limit_mode != PMG_LIMIT_PER_PART && o.ilut_limit_mode != PMG_LIMIT_PER_ROW) || o.device < -1 ||
       (o.ordering != PMG_ORDER_NATURAL && o.ordering != PMG_ORDER_NESTED_DISSECTION) || o.nd_leaf < 1 ||
       (o.mass_transfer != PMG_MASS_LUMPED && o.mass_transfer != PMG_MASS_CONSISTENT) ||
-      (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64))
+      (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64) ||
+      (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT))
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
@@ -1294,6 +1308,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   if (o.mass_transfer == PMG_MASS_CONSISTENT) h->opt.graphs = 0;
   pmg::SetupParams sp;
   sp.consistent_mass = o.mass_transfer == PMG_MASS_CONSISTENT;
+  sp.cdeg = (o.projection == PMG_PROJ_INDIRECT && prob->degree > 2) ? prob->degree - 1 : 1;
   sp.dim = prob->dim;
   sp.p = prob->degree;
   sp.nel = prob->n_elem;
@@ -1361,7 +1376,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   I.bytes_trisolve_l = 12 * I.nnz_l + 4 * (n + 1) + 16 * n;
   I.bytes_trisolve_u = 12 * I.nnz_u + 4 * (n + 1) + 32 * n;
   {
-    const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem - 1;
+    const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
     int lo, W;
     const int64_t sr = n1 > 0 ? xstencil_shape(H.R, prob->dim, nx1, nxp, lo, W) : 0;
     const int64_t sp = n1 > 0 ? xstencil_shape(H.P, prob->dim, nxp, nx1, lo, W) : 0;
@@ -1411,7 +1426,7 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
         if ((s = upload_mat(m, H.Mp, h->Mp, false))) return s;
         if ((s = upload_mat(m, H.M1, h->M1, false))) return s;
       }
-      const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem - 1;
+      const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
       if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
       if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
     }
@@ -1489,6 +1504,16 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
     PMG_HIP_OK(hipDeviceSynchronize());
     I.t_upload = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     I.device_bytes = (int64_t)(h->ops.bytes + h->ws.mem.bytes);
+  }
+  if (sp.cdeg > 1) {
+    // indirect projection: the degree p-1 level, set up with the same
+    // options (and so itself indirect down to degree 2)
+    pmg_problem sub = *prob;
+    sub.degree = prob->degree - 1;
+    pmg_handle sh = nullptr;
+    const pmg_status s2 = pmg_setup(&sub, &o, &sh);
+    if (s2 != PMG_OK) return s2;  // the inner call has set the message
+    h->sub = sh;
   }
   *out = h.release();
   return PMG_OK;

@@ -20,6 +20,7 @@ struct Csr {
 struct SetupParams {
   int dim = 2, p = 2, nel = 16, geom = 0, rhs = 0, pde = 0;
   bool consistent_mass = false;  // also assemble the consistent mass matrices Mp, M1
+  int cdeg = 1;  // degree of the coarse space of the p-transfers (p - 1: indirect projection)
   int freq[3] = {1, 1, 1};
   double tau = 1e-12, fill = 1.0;
   int limit_mode = 0;

@@ -141,6 +141,7 @@ struct Workspace {
 struct pmg_handle_s {
   pmg_problem prob{};
   pmg_options opt{};
+  pmg_handle_s* sub = nullptr;  // indirect projection: the degree p-1 level (owned)
   pmg::HostOps H;
   int device = -1;
   bool on_device = false;

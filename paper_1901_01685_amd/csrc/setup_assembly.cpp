@@ -728,7 +728,10 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
   H.p = p;
   H.nel = nel;
   H.n = (int)ipow(nel + p - 2, dim);
-  H.n1 = (int)ipow(nel - 1, dim);
+  // coarse space of the transfers: degree 1 (direct projection, Section 3)
+  // or degree p - 1 on the same mesh (indirect projection, Appendix A)
+  const int cdeg = std::max(1, sp.cdeg);
+  H.n1 = (int)ipow(nel + cdeg - 2, dim);
   const int th = std::max(1, sp.threads);
   if (sp.geom == 0) {
     // ---- unit box: Kronecker products of 1-D Galerkin matrices
@@ -745,11 +748,11 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
     } else {
       H.A = kron_assemble(dim, termsA, th);
     }
-    Band1D X = matrix_1d(1, p, 1, nel, p + 1);
+    Band1D X = matrix_1d(1, p, cdeg, nel, p + 1);
     H.P = kron_assemble(dim, {std::vector<const Band1D*>(dim, &X)}, th);
     // lumped masses = int Phi_i = product of 1-D integrals; load vector
     // f = pi^2 (sum k^2) prod_a int sin(k_a pi x) phi
-    auto ip = integrals_1d(p, nel, p + 1, 0), i1 = integrals_1d(1, nel, 2, 0);
+    auto ip = integrals_1d(p, nel, p + 1, 0), i1 = integrals_1d(cdeg, nel, cdeg + 1, 0);
     H.mlp.resize(H.n);
     H.ml1.resize(H.n1);
     H.f.resize(H.n);
@@ -759,7 +762,7 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
       sf[a] = integrals_1d(p, nel, p + 1, sp.freq[a]);
       ks += (double)sp.freq[a] * sp.freq[a];
     }
-    int np1 = nel + p - 2, n11 = nel - 1;
+    int np1 = nel + p - 2, n11 = nel + cdeg - 2;
     for (int64_t r = 0; r < H.n; ++r) {
       int64_t t = r;
       double m = 1.0, s = 1.0;
@@ -788,20 +791,20 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
       return 1;
     }
     H.A = element_assemble_2d(1, 0, p, p, nel, p + 1, th);
-    H.P = element_assemble_2d(1, 1, p, 1, nel, p + 1, th);
+    H.P = element_assemble_2d(1, 1, p, cdeg, nel, p + 1, th);
     element_vectors_2d(1, sp.rhs, sp.freq, p, nel, p + 1, &H.f, &H.mlp);
-    element_vectors_2d(1, sp.rhs, sp.freq, 1, nel, 2, nullptr, &H.ml1);
+    element_vectors_2d(1, sp.rhs, sp.freq, cdeg, nel, cdeg + 1, nullptr, &H.ml1);
   }
   H.R = transpose(H.P);
   if (sp.consistent_mass) {
     // Appendix B: consistent interior mass matrices of degree p and 1
     if (sp.geom == 0) {
-      Band1D Mq = matrix_1d(1, p, p, nel, p + 1), M1q = matrix_1d(1, 1, 1, nel, 2);
+      Band1D Mq = matrix_1d(1, p, p, nel, p + 1), M1q = matrix_1d(1, cdeg, cdeg, nel, cdeg + 1);
       H.Mp = kron_assemble(dim, {std::vector<const Band1D*>(dim, &Mq)}, th);
       H.M1 = kron_assemble(dim, {std::vector<const Band1D*>(dim, &M1q)}, th);
     } else {
       H.Mp = element_assemble_2d(1, 1, p, p, nel, p + 1, th);
-      H.M1 = element_assemble_2d(1, 1, 1, 1, nel, 2, th);
+      H.M1 = element_assemble_2d(1, 1, cdeg, cdeg, nel, cdeg + 1, th);
     }
   }
   // ---- degree-1 hierarchy by rediscretisation
@@ -811,6 +814,15 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
   H.Rh.clear();
   H.lnel.clear();
   H.ln.clear();
+  if (cdeg > 1) {
+    // indirect projection: the coarse correction is a V-cycle of the degree
+    // p - 1 level, set up by the caller; no degree-1 hierarchy here
+    H.nlev = 0;
+    H.n_coarse = 0;
+    H.coarse_inv.clear();
+    H.t_assembly = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return 0;
+  }
   for (;;) {
     H.lnel.push_back(ne);
     H.ln.push_back((int)ipow(ne - 1, dim));

@@ -170,3 +170,21 @@ def test_mass_transfer_options_checked():
     assert e.value.status == P.EINVAL
     s = P.Solver(2, 3, 16, geometry=1, rhs_kind=1, mass_transfer=P.MASS_CONSISTENT, device=-1)
     assert s.options.mass_transfer == P.MASS_CONSISTENT
+
+
+@pytest.mark.parametrize("case", [(2, 3, 16, 0), (2, 4, 16, 1), (3, 3, 6, 0)], ids=lambda c: "d%dp%dn%dg%d" % c)
+def test_host_setup_matches_oracle_indirect(case):
+    """Indirect projection (Appendix A): the degree-p level transfers to
+    degree p-1 (transfer matrix and lumped masses against the oracle's), has
+    no degree-1 hierarchy of its own, and the options are checked."""
+    dim, p, nel, g = case
+    s = P.Solver(dim, p, nel, geometry=g, rhs_kind=g, projection=P.PROJ_INDIRECT, device=-1)
+    o = O.Oracle(dim, p, nel, geom=g, rhs=g, opts=O.Options(projection=1), ilut=False)
+    assert s.n1 == o.n1 == (nel + p - 3) ** dim
+    assert s.info.nlev == 0
+    assert _same_pattern(s.export(P.OP_P), o.P()) and _rel(s.export(P.OP_P), o.P()) < 1e-13
+    assert _same_pattern(s.export(P.OP_R), o.R()) and _rel(s.export(P.OP_R), o.R()) < 1e-13
+    assert _rel(s.export_vec(P.VEC_ML1), o.ml1()) < 1e-13
+    with pytest.raises(P.PmgError) as e:
+        P.Solver(2, 3, 8, projection=5, device=-1)
+    assert e.value.status == P.EINVAL
