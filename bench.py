@@ -238,6 +238,10 @@ def main():
     ap.add_argument("--dim", type=int, default=2)
     ap.add_argument("--pde", choices=("poisson", "cdr"), default="poisson",
                     help="cdr: benchmark 2's convection-diffusion-reaction operator on the unit square")
+    ap.add_argument("--projection", choices=("direct", "indirect"), default="direct",
+                    help="indirect: p -> p-1 -> ... -> 1 (Appendix A variant)")
+    ap.add_argument("--mass", choices=("lumped", "consistent"), default="lumped",
+                    help="consistent: consistent mass matrices in the transfers (Appendix B variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--serve", action="store_true", help="continuous-batching serving benchmark")
@@ -275,7 +279,9 @@ def main():
         return
     t0 = time.perf_counter()
     pde = pmg.PDE_CDR if args.pde == "cdr" else pmg.PDE_POISSON
-    s = pmg.Solver(dim=args.dim, degree=args.degree, n_elem=args.nel, pde=pde, device=0)
+    s = pmg.Solver(dim=args.dim, degree=args.degree, n_elem=args.nel, pde=pde, device=0,
+                   projection=pmg.PROJ_INDIRECT if args.projection == "indirect" else pmg.PROJ_DIRECT,
+                   mass_transfer=pmg.MASS_CONSISTENT if args.mass == "consistent" else pmg.MASS_LUMPED)
     t_setup = time.perf_counter() - t0
     info = s.info
     n = s.n
@@ -349,6 +355,8 @@ def main():
         f"3d-unit-cube-p{args.degree}-h1/{args.nel}"
     if pde == pmg.PDE_CDR:
         workload = f"2d-unit-square-cdr-p{args.degree}-h1/{args.nel}"
+    if args.projection != "direct" or args.mass != "lumped":
+        workload += f"-{args.projection}-{args.mass}"
     roofline = {
         "bound": "hbm",
         "kernel": KERNELS[dom][0],
@@ -379,7 +387,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "pde": args.pde, "dim": args.dim, "degree": args.degree, "n_elem": args.nel,
+        "config": {"workload": workload, "pde": args.pde, "projection": args.projection, "mass": args.mass,
+                   "dim": args.dim, "degree": args.degree, "n_elem": args.nel,
                    "unknowns": n, "precision": "fp64", "ilut": [1e-12, 1.0], "final_relres": rel,
                    "setup_s": round(t_setup, 1), "parallelism": "1 GPU"},
         "roofline": roofline,
