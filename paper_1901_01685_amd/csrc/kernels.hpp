@@ -979,12 +979,15 @@ __device__ __forceinline__ TriMeta ld_meta(const TriMeta* p) {
 
 constexpr int kStage = 16;  // in-chunk slots loaded per round trip
 
+// Lanes past the end of a partial chunk hold only padding: they read the
+// shared padding entries (cached) instead of their own slots, so those slots
+// cost no memory traffic.
 template <typename T>
 __device__ __forceinline__ void load_in(int (&jj)[kStage], T (&vv)[kStage], int u0, int w, int base, int lane,
-                                        const TriDev<T>& F) {
+                                        const TriDev<T>& F, bool act) {
 #pragma unroll
   for (int u = 0; u < kStage; ++u) {
-    const int i = u0 + u < w ? base + (u0 + u) * kWave + lane : F.in_pad + lane;
+    const int i = act && u0 + u < w ? base + (u0 + u) * kWave + lane : F.in_pad + lane;
     jj[u] = F.in_j[i];
     vv[u] = F.in_val[i];
   }
@@ -996,7 +999,7 @@ __device__ __forceinline__ void load_in(int (&jj)[kStage], T (&vv)[kStage], int 
 // which holds no entry of a strictly triangular part.
 template <typename T>
 __device__ __forceinline__ void stage_tile(T* tile, int (&jj)[kStage], T (&vv)[kStage], int base, int w,
-                                           int lane, const TriDev<T>& F) {
+                                           int lane, const TriDev<T>& F, bool act) {
 #pragma unroll
   for (int j = 0; j < kWave; ++j) tile[j * kWave + lane] = 0;
   for (int u0 = 0;;) {
@@ -1004,7 +1007,7 @@ __device__ __forceinline__ void stage_tile(T* tile, int (&jj)[kStage], T (&vv)[k
     for (int u = 0; u < kStage; ++u) tile[(jj[u] >= 0 ? jj[u] : lane) * kWave + lane] = jj[u] >= 0 ? vv[u] : (T)0;
     u0 += kStage;
     if (u0 >= w) break;
-    load_in(jj, vv, u0, w, base, lane, F);
+    load_in(jj, vv, u0, w, base, lane, F, act);
   }
 }
 
@@ -1014,11 +1017,11 @@ __device__ __forceinline__ int first_batch(int w) { return w - (w + kTriBatch - 
 
 template <typename T>
 __device__ __forceinline__ void load_batch(int (&c)[kTriBatch], T (&a)[kTriBatch], int u0, int w, int base,
-                                           int lane, const TriDev<T>& F) {
+                                           int lane, const TriDev<T>& F, bool act) {
 #pragma unroll
   for (int u = 0; u < kTriBatch; ++u) {
     const int v = u0 + u;
-    const int i = v >= 0 && v < w ? base + v * kWave + lane : F.off_pad + lane;
+    const int i = act && v >= 0 && v < w ? base + v * kWave + lane : F.off_pad + lane;
     c[u] = F.off_col[i];
     a[u] = F.off_val[i];
   }
@@ -1040,7 +1043,7 @@ __device__ __forceinline__ T gather_off(T t, int (&cc)[kTriBatch], T (&aa)[kTriB
     for (int u = 0; u < kTriBatch; ++u) yy[u] = ld_dev(cc[u] >= 0 ? y + cc[u] : zero);
     int cn[kTriBatch];
     T an[kTriBatch];
-    load_batch(cn, an, u0 + kTriBatch, m.off_w, m.off_ptr, lane, F);
+    load_batch(cn, an, u0 + kTriBatch, m.off_w, m.off_ptr, lane, F, lane < m.nrow);
     for (;;) {
       bool nan = false;  // cheap first test: the marker is a NaN
 #pragma unroll
@@ -1116,13 +1119,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     const int pr = perm[act ? row : row - lane];  // lanes past the end read the chunk's first row
     int cc[kTriBatch];
     T aa[kTriBatch];
-    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F);
+    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F, act);
     int jj[kStage];
     T vv[kStage];
-    load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F);
+    load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F, act);
     T t = r[pr];
     t = act ? t : (T)0;
-    stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F);
+    stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F, act);
     t = gather_off(t, cc, aa, m, lane, F, y);
     t = serial_forward(t, tile, lane);
     if (act) st_dev(y + row, publishable(t));
@@ -1150,12 +1153,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     const int pr = perm[ra];
     int cc[kTriBatch];
     T aa[kTriBatch];
-    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F);
+    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F, act);
     int jj[kStage];
     T vv[kStage];
-    load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F);
+    load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F, act);
     const T xv = x[pr];  // each entry of x is updated by one row only
-    stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F);
+    stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F, act);
     T t = act ? t0 : (T)0;
     const T dg = act ? d0 : (T)1;
     t = gather_off(t, cc, aa, m, lane, F, (const T*)e);
