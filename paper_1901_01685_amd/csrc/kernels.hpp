@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void grid_prolong_add(int nc, const double* __
 // launch-per-phase kernels.
 // ---------------------------------------------------------------------------
 
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 512;
 constexpr int kTileMaxSweeps = 2;  // sweeps per launch (the halo grows with them)
 
 struct TileBox {
