@@ -978,19 +978,55 @@ __device__ __forceinline__ TriMeta ld_meta(const TriMeta* p) {
 }
 
 constexpr int kStage = 16;  // in-chunk slots loaded per round trip
+static_assert(kStage % kColGroup == 0 && kTriBatch % kColGroup == 0, "slot loads come in whole groups");
+static_assert(kTriPad >= 64 * kColGroup, "one padding group per lane");
 
-// Lanes past the end of a partial chunk hold only padding: they read the
-// shared padding entries (cached) instead of their own slots, so those slots
-// cost no memory traffic.
+// 16-byte groups of a lane's slots (see pmg::TriDev): kColGroup column
+// indices, or 16 / sizeof(T) values.
+typedef int ColGroup __attribute__((ext_vector_type(kColGroup)));
+template <typename T>
+struct ValGroup;
+template <>
+struct ValGroup<double> {
+  static constexpr int G = 2;
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct ValGroup<float> {
+  static constexpr int G = 4;
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// Slots u0 .. u0 + N - 1 of one lane (u0 a multiple of kColGroup) from the
+// grouped arrays at `base`; slots outside [0, w) and lanes past the end of a
+// partial chunk (act false) read the padding group at `pad` instead, which
+// stays cached, so padding lanes cost no memory traffic.
+template <typename T, int N>
+__device__ __forceinline__ void load_slots(int (&c)[N], T (&a)[N], int u0, int w, int base, int pad, int lane,
+                                           const int* cols, const T* vals, bool act) {
+  constexpr int G = ValGroup<T>::G;
+#pragma unroll
+  for (int g = 0; g < N / kColGroup; ++g) {
+    const int v = u0 + g * kColGroup;
+    const int i = act && v >= 0 && v < w ? base + v * kWave + lane * kColGroup : pad + lane * kColGroup;
+    const ColGroup q = *reinterpret_cast<const ColGroup*>(cols + i);
+#pragma unroll
+    for (int k = 0; k < kColGroup; ++k) c[g * kColGroup + k] = q[k];
+  }
+#pragma unroll
+  for (int g = 0; g < N / G; ++g) {
+    const int v = u0 + g * G;
+    const int i = act && v >= 0 && v < w ? base + v * kWave + lane * G : pad + lane * G;
+    const typename ValGroup<T>::type q = *reinterpret_cast<const typename ValGroup<T>::type*>(vals + i);
+#pragma unroll
+    for (int k = 0; k < G; ++k) a[g * G + k] = q[k];
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void load_in(int (&jj)[kStage], T (&vv)[kStage], int u0, int w, int base, int lane,
                                         const TriDev<T>& F, bool act) {
-#pragma unroll
-  for (int u = 0; u < kStage; ++u) {
-    const int i = act && u0 + u < w ? base + (u0 + u) * kWave + lane : F.in_pad + lane;
-    jj[u] = F.in_j[i];
-    vv[u] = F.in_val[i];
-  }
+  load_slots<T, kStage>(jj, vv, u0, w, base, F.in_pad, lane, F.in_j, F.in_val, act);
 }
 
 // Stage the in-chunk entries of this lane's row in column `lane` of the tile
@@ -1012,19 +1048,14 @@ __device__ __forceinline__ void stage_tile(T* tile, int (&jj)[kStage], T (&vv)[k
 }
 
 // Off-chunk batches end at the last slot, so the last batch holds every
-// row's latest entries; the first may start before slot 0 (those read padding).
+// row's latest entries; the first may start before slot 0 (those read
+// padding).  With w a multiple of kColGroup every batch starts on a group.
 __device__ __forceinline__ int first_batch(int w) { return w - (w + kTriBatch - 1) / kTriBatch * kTriBatch; }
 
 template <typename T>
 __device__ __forceinline__ void load_batch(int (&c)[kTriBatch], T (&a)[kTriBatch], int u0, int w, int base,
                                            int lane, const TriDev<T>& F, bool act) {
-#pragma unroll
-  for (int u = 0; u < kTriBatch; ++u) {
-    const int v = u0 + u;
-    const int i = act && v >= 0 && v < w ? base + v * kWave + lane : F.off_pad + lane;
-    c[u] = F.off_col[i];
-    a[u] = F.off_val[i];
-  }
+  load_slots<T, kTriBatch>(c, a, u0, w, base, F.off_pad, lane, F.off_col, F.off_val, act);
 }
 
 // t -= sum over the off-chunk slots of this lane of val * y[col], slot by

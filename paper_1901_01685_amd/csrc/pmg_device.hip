@@ -201,8 +201,9 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
       wo = std::max(wo, no);
       wi = std::max(wi, ni);
     }
-    S.off_w[q] = wo;
-    S.in_w[q] = wi;
+    // whole column groups (see pmg::TriDev)
+    S.off_w[q] = (wo + pmg::kColGroup - 1) / pmg::kColGroup * pmg::kColGroup;
+    S.in_w[q] = (wi + pmg::kColGroup - 1) / pmg::kColGroup * pmg::kColGroup;
   }
   int64_t no_tot = 0, ni_tot = 0;
   for (int q = 0; q < nq; ++q) {
@@ -211,15 +212,15 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
     no_tot += (int64_t)S.off_w[q] * 64;
     ni_tot += (int64_t)S.in_w[q] * 64;
   }
-  if (no_tot + 64 >= INT32_MAX || ni_tot + 64 >= INT32_MAX)
+  if (no_tot + pmg::kTriPad >= INT32_MAX || ni_tot + pmg::kTriPad >= INT32_MAX)
     return fail(PMG_EINVAL, "triangular factor has more than 2^31 stored slots");
-  // 64 trailing padding entries each (see pmg::TriDev)
+  // trailing padding entries (see pmg::TriDev)
   S.off_pad = (int)no_tot;
   S.in_pad = (int)ni_tot;
-  S.off_col.assign(no_tot + 64, -1);
-  S.off_val.assign(no_tot + 64, 0.0);
-  S.in_j.assign(ni_tot + 64, -1);
-  S.in_val.assign(ni_tot + 64, 0.0);
+  S.off_col.assign(no_tot + pmg::kTriPad, -1);
+  S.off_val.assign(no_tot + pmg::kTriPad, 0.0);
+  S.in_j.assign(ni_tot + pmg::kTriPad, -1);
+  S.in_val.assign(ni_tot + pmg::kTriPad, 0.0);
   // per chunk, in a topological order (forward: ascending q, backward:
   // descending q): the chunks it reads, its level and the sliced entries
   std::vector<int> level(nq, 0), mark(nq, 0), touched;
@@ -498,6 +499,21 @@ pmg_status upload_xstencil(pmgdev::DevArena& mem, const pmg::Csr& M, int dim, in
   return PMG_OK;
 }
 
+// Host slot-major order (slot u of lane l at ptr + 64 u + l) to the device's
+// 16-byte groups of G slots per lane (ptr + 64 u + G l + u % G).  Chunks start
+// at multiples of 64 * kColGroup entries, so the groups never straddle two
+// chunks; the padding tail (pad_at..) keeps its value.
+template <typename TO, typename TI>
+std::vector<TO> group_slots(const std::vector<TI>& src, int64_t pad_at, int G) {
+  std::vector<TO> dst(src.size());
+  for (int64_t i = 0; i < pad_at; ++i) {
+    const int64_t u = i / 64, l = i % 64;
+    dst[(u / G) * 64 * G + l * G + u % G] = (TO)src[i];
+  }
+  for (size_t i = (size_t)pad_at; i < src.size(); ++i) dst[i] = (TO)src[i];
+  return dst;
+}
+
 pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with32) {
   pmg_status s;
   const int nq = (int)S.order.size();
@@ -510,15 +526,22 @@ pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with3
   int *oc, *ij;
   double *ov, *iv, *dg = nullptr;
   if ((s = mem.upload(&md, meta.data(), meta.size()))) return s;
-  if ((s = mem.upload(&oc, S.off_col.data(), S.off_col.size()))) return s;
-  if ((s = mem.upload(&ov, S.off_val.data(), S.off_val.size()))) return s;
-  if ((s = mem.upload(&ij, S.in_j.data(), S.in_j.size()))) return s;
-  if ((s = mem.upload(&iv, S.in_val.data(), S.in_val.size()))) return s;
+  {
+    const std::vector<int> gc = group_slots<int>(S.off_col, S.off_pad, pmg::kColGroup);
+    const std::vector<double> gv = group_slots<double>(S.off_val, S.off_pad, 2);
+    const std::vector<int> gj = group_slots<int>(S.in_j, S.in_pad, pmg::kColGroup);
+    const std::vector<double> gw = group_slots<double>(S.in_val, S.in_pad, 2);
+    if ((s = mem.upload(&oc, gc.data(), gc.size()))) return s;
+    if ((s = mem.upload(&ov, gv.data(), gv.size()))) return s;
+    if ((s = mem.upload(&ij, gj.data(), gj.size()))) return s;
+    if ((s = mem.upload(&iv, gw.data(), gw.size()))) return s;
+  }
   if (upper && (s = mem.upload(&dg, S.diag.data(), S.diag.size()))) return s;
   S.dev64 = pmg::TriDev<double>{S.off_pad, S.in_pad, md, oc, ov, ij, iv, dg};
   if (with32) {
-    std::vector<float> a(S.off_val.begin(), S.off_val.end()), b(S.in_val.begin(), S.in_val.end()),
-        c(S.diag.begin(), S.diag.end());
+    const std::vector<float> a = group_slots<float>(S.off_val, S.off_pad, 4),
+                             b = group_slots<float>(S.in_val, S.in_pad, 4);
+    const std::vector<float> c(S.diag.begin(), S.diag.end());
     float *ov32, *iv32, *dg32 = nullptr;
     if ((s = mem.upload(&ov32, a.data(), a.size()))) return s;
     if ((s = mem.upload(&iv32, b.data(), b.size()))) return s;

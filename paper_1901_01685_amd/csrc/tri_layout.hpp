@@ -6,6 +6,10 @@ namespace pmg {
 
 // Off-chunk slots are gathered in batches of this many per lane.
 constexpr int kTriBatch = 32;
+// Slot widths are rounded up to this; column indices load in groups of it.
+constexpr int kColGroup = 4;
+// Padding entries at the end of each sliced array (one 16-byte group per lane).
+constexpr int kTriPad = 64 * kColGroup;
 
 // Marker of a solution entry that is not final yet.  Before a triangular
 // solve the output vector is filled with it; a wave that needs an entry
@@ -21,21 +25,28 @@ constexpr unsigned kPending32 = 0x7F80DEADu;
 // the chunk's natural index (chunks numbered by first row).  Chunks are taken
 // in a topological order of the chunk dependency graph, by level, so a wave
 // only ever waits for chunks taken before its own.
-//   Off-chunk entries: slot u of lane l at off_ptr[q] + 64 u + l for
-//   u < off_w[q], per row sorted by the level of the chunk holding the
-//   source row (ties: lower factor ascending columns, upper descending), so
-//   entries that are final early come first.  Each row's entries fill its
-//   last slots (right-aligned) and padding, column -1 and value 0, the first
-//   ones, so the entries every row waits for longest share the last slots.
-//   In-chunk entries: slot u of lane l at in_ptr[q] + 64 u + l for
-//   u < in_w[q], the position j of the source row inside the chunk (-1 for
-//   padding) and the value.  For the upper factor the value is divided by
-//   the diagonal of its column, U_ij / U_jj, so the in-chunk recurrence runs
-//   on undivided partial sums and each row is divided by its own diagonal
-//   once at the end.
-// Loads of one slot by the 64 lanes are contiguous (coalesced).  off_col /
-// off_val and in_j / in_val end with 64 padding entries (one per lane) at
-// off_pad and in_pad, which lanes without an entry load instead, so every
+//   Off-chunk entries: slot u of lane l, u < off_w[q], per row sorted by the
+//   level of the chunk holding the source row (ties: lower factor ascending
+//   columns, upper descending), so entries that are final early come first.
+//   Each row's entries fill its last slots (right-aligned) and padding,
+//   column -1 and value 0, the first ones, so the entries every row waits
+//   for longest share the last slots.
+//   In-chunk entries: slot u of lane l, u < in_w[q], the position j of the
+//   source row inside the chunk (-1 for padding) and the value.  For the
+//   upper factor the value is divided by the diagonal of its column,
+//   U_ij / U_jj, so the in-chunk recurrence runs on undivided partial sums
+//   and each row is divided by its own diagonal once at the end.
+// Slot widths are multiples of kColGroup, so every chunk starts at a
+// multiple of 64 * kColGroup entries.  On the host (and in exports) slot u of
+// lane l sits at ptr[q] + 64 u + l.  On the device each lane's slots come in
+// 16-byte groups, one vector load each: columns in groups of kColGroup = 4 at
+// ptr[q] + 64 u + 4 l + u % 4 (u a multiple of 4 for the group's first), values
+// in groups of G = 16 / sizeof(T) at ptr[q] + 64 u + G l + u % G.  A wave's
+// load of one group is 1 KiB contiguous, and a batch of kTriBatch slots takes
+// kTriBatch / 4 + kTriBatch / G loads besides its gathers, which keeps a
+// batch's loads within the 63 a wave can have outstanding.  The arrays end
+// with kTriPad padding entries (column -1, value 0) at off_pad and in_pad,
+// one group per lane, which lanes without an entry load instead, so every
 // load is unconditional and its value needs no select.
 //
 // The per-chunk scalars are packed in ticket order, one 32-byte record per
