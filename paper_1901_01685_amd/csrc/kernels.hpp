@@ -1000,27 +1000,42 @@ struct ValGroup<float> {
 // Slots u0 .. u0 + N - 1 of one lane (u0 a multiple of kColGroup) from the
 // grouped arrays at `base`; slots outside [0, w) and lanes past the end of a
 // partial chunk (act false) read the padding group at `pad` instead, which
-// stays cached, so padding lanes cost no memory traffic.
-template <typename T, int N>
-__device__ __forceinline__ void load_slots(int (&c)[N], T (&a)[N], int u0, int w, int base, int pad, int lane,
-                                           const int* cols, const T* vals, bool act) {
-  constexpr int G = ValGroup<T>::G;
+// stays cached, so padding lanes cost no memory traffic.  The factor is read
+// once per solve, so its loads are non-temporal and leave the caches to the
+// solution vector.
+template <int N>
+__device__ __forceinline__ void load_cols(int (&c)[N], int u0, int w, int base, int pad, int lane, const int* cols,
+                                          bool act) {
 #pragma unroll
   for (int g = 0; g < N / kColGroup; ++g) {
     const int v = u0 + g * kColGroup;
     const int i = act && v >= 0 && v < w ? base + v * kWave + lane * kColGroup : pad + lane * kColGroup;
-    const ColGroup q = *reinterpret_cast<const ColGroup*>(cols + i);
+    const ColGroup q = __builtin_nontemporal_load(reinterpret_cast<const ColGroup*>(cols + i));
 #pragma unroll
     for (int k = 0; k < kColGroup; ++k) c[g * kColGroup + k] = q[k];
   }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_vals(T (&a)[N], int u0, int w, int base, int pad, int lane, const T* vals,
+                                          bool act) {
+  constexpr int G = ValGroup<T>::G;
 #pragma unroll
   for (int g = 0; g < N / G; ++g) {
     const int v = u0 + g * G;
     const int i = act && v >= 0 && v < w ? base + v * kWave + lane * G : pad + lane * G;
-    const typename ValGroup<T>::type q = *reinterpret_cast<const typename ValGroup<T>::type*>(vals + i);
+    const typename ValGroup<T>::type q =
+        __builtin_nontemporal_load(reinterpret_cast<const typename ValGroup<T>::type*>(vals + i));
 #pragma unroll
     for (int k = 0; k < G; ++k) a[g * G + k] = q[k];
   }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_slots(int (&c)[N], T (&a)[N], int u0, int w, int base, int pad, int lane,
+                                           const int* cols, const T* vals, bool act) {
+  load_cols<N>(c, u0, w, base, pad, lane, cols, act);
+  load_vals<T, N>(a, u0, w, base, pad, lane, vals, act);
 }
 
 template <typename T>
@@ -1053,49 +1068,85 @@ __device__ __forceinline__ void stage_tile(T* tile, int (&jj)[kStage], T (&vv)[k
 __device__ __forceinline__ int first_batch(int w) { return w - (w + kTriBatch - 1) / kTriBatch * kTriBatch; }
 
 template <typename T>
-__device__ __forceinline__ void load_batch(int (&c)[kTriBatch], T (&a)[kTriBatch], int u0, int w, int base,
-                                           int lane, const TriDev<T>& F, bool act) {
-  load_slots<T, kTriBatch>(c, a, u0, w, base, F.off_pad, lane, F.off_col, F.off_val, act);
+__device__ __forceinline__ void load_batch_cols(int (&c)[kTriBatch], int u0, const TriMeta& m, int lane,
+                                                const TriDev<T>& F, bool act) {
+  load_cols<kTriBatch>(c, u0, m.off_w, m.off_ptr, F.off_pad, lane, F.off_col, act);
 }
 
-// t -= sum over the off-chunk slots of this lane of val * y[col], slot by
-// slot.  Entries still holding the marker are reloaded until they are final
-// (only those lanes issue loads).  The first batch (from first_batch) was
-// loaded into cc/aa by the caller.  A row's entries fill its last slots, so
-// the entries that become final last all sit in the last batch and, once
-// they arrive, no further batch has to be loaded.
+// The solution vector as a buffer resource of n entries: a gather of a
+// padding column (stored as n) falls outside it and reads 0 without a memory
+// access, and each gather needs only a 32-bit offset.
 template <typename T>
-__device__ __forceinline__ T gather_off(T t, int (&cc)[kTriBatch], T (&aa)[kTriBatch], const TriMeta& m, int lane,
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const T* y, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(y), (short)0, n * (int)sizeof(T), 0x00020000);
+}
+__device__ __forceinline__ double ld_buf(__amdgpu_buffer_rsrc_t r, int col, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, col * 8, 0, 0));
+}
+__device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, int col, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, col * 4, 0, 0));
+}
+
+// One off-chunk batch, slots u0 .. u0 + kTriBatch - 1: gathers y for the
+// columns in cc, loads the batch's values and the next batch's columns (into
+// cn), then subtracts the batch in slot order.  The values load with the
+// gathers rather than a batch ahead: the batch waits for the next columns'
+// memory round trip anyway, and the registers they would hold keep the
+// gather's state out of the accumulation registers.  The first gathers are
+// plain loads: within one solve an entry only ever changes from the marker to
+// its final value, so a cached copy is either final or the marker.  The batch
+// is summed first; only if the sum is a NaN (some entry still the marker, or
+// a NaN in the data) are the marker entries reloaded with device-scope loads
+// until they are final (only those lanes load), and the batch summed again
+// from the same start, so the result does not depend on which path was taken.
+template <typename T>
+__device__ __forceinline__ T gather_batch(T t, const int (&cc)[kTriBatch], int (&cn)[kTriBatch], int u0,
+                                          const TriMeta& m, int lane, const TriDev<T>& F, const T* y,
+                                          __amdgpu_buffer_rsrc_t yr) {
+  const bool act = lane < m.nrow;
+  T yy[kTriBatch];
+#pragma unroll
+  for (int u = 0; u < kTriBatch; ++u) yy[u] = ld_buf(yr, cc[u], T());
+  T aa[kTriBatch];
+  load_vals<T, kTriBatch>(aa, u0, m.off_w, m.off_ptr, F.off_pad, lane, F.off_val, act);
+  load_batch_cols(cn, u0 + kTriBatch, m, lane, F, act);
+  T s = t;
+#pragma unroll
+  for (int u = 0; u < kTriBatch; ++u) s -= aa[u] * yy[u];  // padding: 0 * 0
+  if (__ballot(s != s) == 0) return s;
+  for (;;) {
+    bool pend = false;
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u) pend |= pending(yy[u]);
+    if (__ballot(pend) == 0) break;
+    __builtin_amdgcn_s_sleep(2);
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u)
+      if (pending(yy[u])) yy[u] = ld_dev(y + cc[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kTriBatch; ++u) t -= aa[u] * yy[u];
+  return t;
+}
+
+// t -= sum over the off-chunk slots of this lane of val * y[col], batch by
+// batch in slot order.  The first batch's columns (from first_batch) were
+// loaded into cc by the caller; the two column sets take turns as current and
+// next batch, so none is copied.  A row's entries fill its last slots, so the
+// entries that become final last all sit in the last batch and, once they
+// arrive, no further batch has to be loaded.
+template <typename T>
+__device__ __forceinline__ T gather_off(T t, int (&cc)[kTriBatch], const TriMeta& m, int lane,
                                         const TriDev<T>& F, const T* y) {
-  const T* zero = F.off_val + F.off_pad;  // padding reads a 0 here
-  for (int u0 = first_batch(m.off_w); u0 < m.off_w; u0 += kTriBatch) {
-    T yy[kTriBatch];
-#pragma unroll
-    for (int u = 0; u < kTriBatch; ++u) yy[u] = ld_dev(cc[u] >= 0 ? y + cc[u] : zero);
-    int cn[kTriBatch];
-    T an[kTriBatch];
-    load_batch(cn, an, u0 + kTriBatch, m.off_w, m.off_ptr, lane, F, lane < m.nrow);
-    for (;;) {
-      bool nan = false;  // cheap first test: the marker is a NaN
-#pragma unroll
-      for (int u = 0; u < kTriBatch; ++u) nan |= yy[u] != yy[u];
-      if (__ballot(nan) == 0) break;
-      bool pend = false;
-#pragma unroll
-      for (int u = 0; u < kTriBatch; ++u) pend |= pending(yy[u]);
-      if (__ballot(pend) == 0) break;
-      __builtin_amdgcn_s_sleep(2);
-#pragma unroll
-      for (int u = 0; u < kTriBatch; ++u)
-        if (pending(yy[u])) yy[u] = ld_dev(y + cc[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < kTriBatch; ++u) t -= aa[u] * yy[u];  // padding: 0 * 0
-#pragma unroll
-    for (int u = 0; u < kTriBatch; ++u) {
-      cc[u] = cn[u];
-      aa[u] = an[u];
-    }
+  const __amdgpu_buffer_rsrc_t yr = vec_rsrc(y, F.n);
+  int cn[kTriBatch];
+  for (int u0 = first_batch(m.off_w);;) {
+    t = gather_batch(t, cc, cn, u0, m, lane, F, y, yr);
+    u0 += kTriBatch;
+    if (u0 >= m.off_w) break;
+    t = gather_batch(t, cn, cc, u0, m, lane, F, y, yr);
+    u0 += kTriBatch;
+    if (u0 >= m.off_w) break;
   }
   return t;
 }
@@ -1149,15 +1200,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     // every independent load of the chunk first
     const int pr = perm[act ? row : row - lane];  // lanes past the end read the chunk's first row
     int cc[kTriBatch];
-    T aa[kTriBatch];
-    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F, act);
+    load_batch_cols(cc, first_batch(m.off_w), m, lane, F, act);
     int jj[kStage];
     T vv[kStage];
     load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F, act);
     T t = r[pr];
     t = act ? t : (T)0;
     stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F, act);
-    t = gather_off(t, cc, aa, m, lane, F, y);
+    t = gather_off(t, cc, m, lane, F, y);
     t = serial_forward(t, tile, lane);
     if (act) st_dev(y + row, publishable(t));
   }
@@ -1183,8 +1233,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     const T d0 = F.diag[ra];
     const int pr = perm[ra];
     int cc[kTriBatch];
-    T aa[kTriBatch];
-    load_batch(cc, aa, first_batch(m.off_w), m.off_w, m.off_ptr, lane, F, act);
+    load_batch_cols(cc, first_batch(m.off_w), m, lane, F, act);
     int jj[kStage];
     T vv[kStage];
     load_in(jj, vv, 0, m.in_w, m.in_ptr, lane, F, act);
@@ -1192,7 +1241,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F, act);
     T t = act ? t0 : (T)0;
     const T dg = act ? d0 : (T)1;
-    t = gather_off(t, cc, aa, m, lane, F, (const T*)e);
+    t = gather_off(t, cc, m, lane, F, (const T*)e);
     t = serial_backward(t, tile, lane);
     const T ev = t / dg;
     if (act) {

@@ -161,6 +161,8 @@ std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int 
 pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
   const int n = T.nrows;
   S.seg_len = seg_len;
+  if ((int64_t)n * 8 >= INT32_MAX) return fail(PMG_EINVAL, "triangular factor has more than 2^28 rows");
+  S.nrows = n;
   S.nseg = n / seg_len;
   // chunk geometry in natural order (segment-major, ascending rows)
   const std::vector<std::vector<int>> bounds = choose_chunks(T, seg_len, S.nseg, upper);
@@ -514,6 +516,15 @@ std::vector<TO> group_slots(const std::vector<TI>& src, int64_t pad_at, int G) {
   return dst;
 }
 
+// Off-chunk columns for the device: padding (-1) becomes n, the first index
+// past the buffer the gathers read through.
+std::vector<int> device_cols(const std::vector<int>& src, int64_t pad_at, int n) {
+  std::vector<int> dst = group_slots<int>(src, pad_at, pmg::kColGroup);
+  for (int& c : dst)
+    if (c < 0) c = n;
+  return dst;
+}
+
 pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with32) {
   pmg_status s;
   const int nq = (int)S.order.size();
@@ -527,7 +538,7 @@ pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with3
   double *ov, *iv, *dg = nullptr;
   if ((s = mem.upload(&md, meta.data(), meta.size()))) return s;
   {
-    const std::vector<int> gc = group_slots<int>(S.off_col, S.off_pad, pmg::kColGroup);
+    const std::vector<int> gc = device_cols(S.off_col, S.off_pad, S.nrows);
     const std::vector<double> gv = group_slots<double>(S.off_val, S.off_pad, 2);
     const std::vector<int> gj = group_slots<int>(S.in_j, S.in_pad, pmg::kColGroup);
     const std::vector<double> gw = group_slots<double>(S.in_val, S.in_pad, 2);
@@ -537,7 +548,7 @@ pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with3
     if ((s = mem.upload(&iv, gw.data(), gw.size()))) return s;
   }
   if (upper && (s = mem.upload(&dg, S.diag.data(), S.diag.size()))) return s;
-  S.dev64 = pmg::TriDev<double>{S.off_pad, S.in_pad, md, oc, ov, ij, iv, dg};
+  S.dev64 = pmg::TriDev<double>{S.off_pad, S.in_pad, S.nrows, md, oc, ov, ij, iv, dg};
   if (with32) {
     const std::vector<float> a = group_slots<float>(S.off_val, S.off_pad, 4),
                              b = group_slots<float>(S.in_val, S.in_pad, 4);
@@ -546,7 +557,7 @@ pmg_status upload_tri(pmgdev::DevArena& mem, TriSched& S, bool upper, bool with3
     if ((s = mem.upload(&ov32, a.data(), a.size()))) return s;
     if ((s = mem.upload(&iv32, b.data(), b.size()))) return s;
     if (upper && (s = mem.upload(&dg32, c.data(), c.size()))) return s;
-    S.dev32 = pmg::TriDev<float>{S.off_pad, S.in_pad, md, oc, ov32, ij, iv32, dg32};
+    S.dev32 = pmg::TriDev<float>{S.off_pad, S.in_pad, S.nrows, md, oc, ov32, ij, iv32, dg32};
   }
   return PMG_OK;
 }

@@ -44,7 +44,9 @@ constexpr unsigned kPending32 = 0x7F80DEADu;
 // in groups of G = 16 / sizeof(T) at ptr[q] + 64 u + G l + u % G.  A wave's
 // load of one group is 1 KiB contiguous, and a batch of kTriBatch slots takes
 // kTriBatch / 4 + kTriBatch / G loads besides its gathers, which keeps a
-// batch's loads within the 63 a wave can have outstanding.  The arrays end
+// batch's loads within the 63 a wave can have outstanding.  Padding columns
+// are stored as n on the device: gathers address the solution vector through
+// a buffer resource of n entries, whose range check returns 0 for them.  The arrays end
 // with kTriPad padding entries (column -1, value 0) at off_pad and in_pad,
 // one group per lane, which lanes without an entry load instead, so every
 // load is unconditional and its value needs no select.
@@ -61,6 +63,8 @@ struct alignas(32) TriMeta {
 template <typename T>
 struct TriDev {
   int off_pad, in_pad;
+  int n;                // rows of the factor; the device's off_col holds n for padding
+                        // (the host arrays and exports hold -1)
   const TriMeta* meta;  // by ticket
   const int* off_col;
   const T* off_val;
