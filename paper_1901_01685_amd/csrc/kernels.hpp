@@ -940,25 +940,32 @@ __device__ __forceinline__ T publishable(T v) {
   return pending(v) ? (T)__builtin_nan("") : v;
 }
 
-// Draws the next ticket for the whole wave: every lane takes part in the
-// atomic (lane 0 adds 1, the others 0) and lane 0's old value is the ticket.
-// No branch depends on the lane here: inside a loop, a lane-dependent branch
-// around the atomic followed by a cross-lane read lets the compiler send lane
-// 0 and the other lanes round different loops.
-__device__ __forceinline__ int wave_ticket(unsigned* ticket) {
-  const unsigned v = atomicAdd(ticket, (threadIdx.x & 63) == 0 ? 1u : 0u);
-  return __builtin_amdgcn_readfirstlane((int)v);
+// Draws the wave's next ticket from the counter of its grid slot: every lane
+// takes part in the atomic (lane 0 adds 1, the others 0) and lane 0's old
+// value k gives ticket k * nslot + slot.  No branch depends on the lane here:
+// inside a loop, a lane-dependent branch around the atomic followed by a
+// cross-lane read lets the compiler send lane 0 and the other lanes round
+// different loops.
+//
+// Why no wave waits forever: tickets follow a topological order of the chunk
+// graph, so the smallest unfinished ticket only waits for finished chunks.
+// It is held by a running wave: if it were not drawn yet, every wave of its
+// slot would hold a smaller ticket of that slot, unfinished, against its
+// being the smallest.  Every slot has waves (nslot <= grid size).
+__device__ __forceinline__ int wave_ticket(unsigned* state, int slot, int nslot) {
+  const unsigned v = atomicAdd(state + slot * kTicketStride, (threadIdx.x & 63) == 0 ? 1u : 0u);
+  return __builtin_amdgcn_readfirstlane((int)v) * nslot + slot;
 }
 
 // Called by every wave of the grid once it has drawn a ticket past the last
-// chunk.  The last wave to get here clears the ticket for the next launch
+// chunk.  The last wave to get here clears the counters for the next launch
 // (all other waves have exited), so a solve needs no separate reset launch.
-// state[0] = ticket, state[1] = exited waves.
-__device__ __forceinline__ void finish_grid(unsigned* state, int lane) {
-  const unsigned prev = atomicAdd(state + 1, lane == 0 ? 1u : 0u);
+__device__ __forceinline__ void finish_grid(unsigned* state, int nslot, int lane) {
+  unsigned* exited = state + kTicketSlots * kTicketStride;
+  const unsigned prev = atomicAdd(exited, lane == 0 ? 1u : 0u);
   if ((unsigned)__builtin_amdgcn_readfirstlane((int)prev) == gridDim.x - 1 && lane == 0) {
-    st_dev(state, 0u);
-    st_dev(state + 1, 0u);
+    for (int c = 0; c < nslot; ++c) st_dev(state + c * kTicketStride, 0u);
+    st_dev(exited, 0u);
   }
 }
 
@@ -1188,11 +1195,12 @@ __device__ __forceinline__ T serial_backward(T t, const T* tile, int lane) {
 // y must hold kPending in every entry at launch.
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_lower(
-    int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y, unsigned* state) {
+    int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y, unsigned* state, int nslot) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
+  const int slot = (int)(blockIdx.x % (unsigned)nslot);
   for (;;) {
-    const int tk = wave_ticket(state);
+    const int tk = wave_ticket(state, slot, nslot);
     if (tk >= nq) break;
     const TriMeta m = ld_meta(F.meta + tk);
     const int row = m.row0 + lane;
@@ -1211,7 +1219,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     t = serial_forward(t, tile, lane);
     if (act) st_dev(y + row, publishable(t));
   }
-  finish_grid(state, lane);
+  finish_grid(state, nslot, lane);
 }
 
 // e = U^{-1} y (diagonal in F.diag) and x += P^T e.  e must hold kPending in
@@ -1219,11 +1227,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_upper(
     int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ y, T* e, T* __restrict__ x,
-    unsigned* state) {
+    unsigned* state, int nslot) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
+  const int slot = (int)(blockIdx.x % (unsigned)nslot);
   for (;;) {
-    const int tk = wave_ticket(state);
+    const int tk = wave_ticket(state, slot, nslot);
     if (tk >= nq) break;
     const TriMeta m = ld_meta(F.meta + tk);
     const int row = m.row0 + lane;
@@ -1249,7 +1258,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
       x[pr] = xv + ev;
     }
   }
-  finish_grid(state, lane);
+  finish_grid(state, nslot, lane);
 }
 
 }  // namespace pmg

@@ -574,6 +574,9 @@ int tri_grid(const TriSched& S) {
   return sizeof(T) == 8 ? S.grid64 : S.grid32;
 }
 
+// Ticket slots of a launch of g waves: every slot needs at least one wave.
+inline int tri_slots(int g) { return std::max(1, std::min(pmg::kTicketSlots, g)); }
+
 // Persistent grid of the triangular solves: as many waves as fit on the
 // device at once (more would only start after others exit), at most one per
 // chunk.
@@ -738,15 +741,17 @@ template <typename T>
 void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_LOWER, st);
   fill_pending(y, h->H.n, st);
-  pmg::trisolve_lower<T><<<tri_grid<T>(h->tl), 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, ws.tickets);
+  const int g = tri_grid<T>(h->tl);
+  pmg::trisolve_lower<T><<<g, 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, ws.tickets, tri_slots(g));
 }
 
 template <typename T>
 void upper_impl(pmg_handle h, Workspace& ws, const T* y, T* e, T* x, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_UPPER, st);
   fill_pending(e, h->H.n, st);
-  pmg::trisolve_upper<T><<<tri_grid<T>(h->tu), 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x,
-                                                             ws.tickets + 2);
+  const int g = tri_grid<T>(h->tu);
+  pmg::trisolve_upper<T><<<g, 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x,
+                                           ws.tickets + pmg::kTicketWords, tri_slots(g));
 }
 
 // x += U^{-1} L^{-1} P r (then permuted back) with work vectors y, e.
@@ -1049,7 +1054,7 @@ size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors) {
   const pmg::HostOps& H = h->H;
   size_t b = 8 * (3 * (size_t)H.n + 2 * (size_t)std::max(H.n1, 1)) + 8 * (size_t)h->partial_cap + 32;
   for (int l = 0; l < H.nlev; ++l) b += 8 * (size_t)H.ln[l] * (l == 0 ? 1 : 3);
-  b += 16;
+  b += 2 * pmg::kTicketWords * sizeof(unsigned);
   if (mixed) b += 4 * (5 * (size_t)H.n + (size_t)std::max(H.n1, 1));
   if (request_vectors) b += 16 * (size_t)H.n;
   return b;
@@ -1081,8 +1086,8 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
   }
   for (int l = 0; l < H.nlev; ++l)
     if ((s = m.alloc(&ws.hr[l], H.ln[l]))) return s;
-  if ((s = m.alloc(&ws.tickets, 4))) return s;
-  fill<unsigned>(ws.tickets, 4, 0u, st);
+  if ((s = m.alloc(&ws.tickets, 2 * pmg::kTicketWords))) return s;
+  fill<unsigned>(ws.tickets, 2 * pmg::kTicketWords, 0u, st);
   if (h->opt.mass_transfer == PMG_MASS_CONSISTENT && H.n1 > 0 && (s = alloc_mass(h, ws))) return s;
   PMG_HIP_OK(hipGetLastError());
   if (mixed) {

@@ -107,7 +107,7 @@ struct Workspace {
   double *b = nullptr, *x = nullptr;  // request vectors (server slots only)
   double* host_scalar = nullptr;      // pinned
   std::vector<double*> hb, he, hr;
-  unsigned* tickets = nullptr;  // lower: [0] ticket, [1] exited waves; upper: [2], [3]
+  unsigned* tickets = nullptr;  // lower: pmg::kTicketWords counters (see wave_ticket), then upper
   float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *e32 = nullptr, *t32 = nullptr, *q32 = nullptr;
   bool mixed = false;
   // BiCGSTAB (pmg_bicgstab): shadow residual, direction, A y, preconditioned

@@ -10,6 +10,14 @@ constexpr int kTriBatch = 32;
 constexpr int kColGroup = 4;
 // Padding entries at the end of each sliced array (one 16-byte group per lane).
 constexpr int kTriPad = 64 * kColGroup;
+// Ticket counters of one solve: up to kTicketSlots counters kTicketStride
+// words (128 bytes) apart, then the count of exited waves; kTicketWords words
+// per solve.  The waves of grid slot c (block index mod the slot count) draw
+// tickets c, c + slots, c + 2 slots, ... from counter c, so no single address
+// takes every wave's atomic.
+constexpr int kTicketSlots = 8;
+constexpr int kTicketStride = 32;
+constexpr int kTicketWords = (kTicketSlots + 1) * kTicketStride;
 
 // Marker of a solution entry that is not final yet.  Before a triangular
 // solve the output vector is filled with it; a wave that needs an entry

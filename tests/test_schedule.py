@@ -154,3 +154,56 @@ def test_skewed_chunks_shorten_the_chain():
             lev[q] = (lev[cq].max() if len(cq) else 0) + 1
         skewed = s.info.chunk_levels_u if f else s.info.chunk_levels_l
         assert skewed <= 0.85 * lev.max(), (skewed, lev.max())
+
+
+def _drain_with_slots(order, deps_of, waves, nslot, rng):
+    """Waves of slot c = wave mod nslot draw tickets c, c + nslot, ... from
+    counter c and finish their chunk once every chunk it reads is finished,
+    in a random interleaving.  Returns the chunks in finishing order, or None
+    if no wave can move while chunks remain (a deadlock)."""
+    nq = len(order)
+    count = [0] * nslot
+    held = [None] * waves          # ticket held by each wave
+    alive = list(range(waves))
+    done = np.zeros(nq, dtype=bool)
+    finished = []
+    while alive:
+        movable = []
+        for w in alive:
+            t = held[w]
+            if t is None or all(done[d] for d in deps_of[order[t]]):
+                movable.append(w)
+        if not movable:
+            return None
+        w = movable[rng.integers(len(movable))]
+        if held[w] is None:
+            c = w % nslot
+            t = count[c] * nslot + c
+            count[c] += 1
+            if t >= nq:
+                alive.remove(w)
+            else:
+                held[w] = t
+        else:
+            q = order[held[w]]
+            done[q] = True
+            finished.append(q)
+            held[w] = None
+    return finished
+
+
+@pytest.mark.parametrize("factor", [0, 1])
+def test_slot_tickets_never_deadlock(factor):
+    """Per-slot ticket counters (trisolve kernels): with any number of waves
+    and slots (slots <= waves), every interleaving drains all chunks."""
+    s = pmg.Solver(2, 3, 40, device=-1)
+    S = s.export_schedule(factor)
+    order = [int(q) for q in S["order"]]
+    deps_of = {q: [int(d) for d in S["deps"][S["wptr"][q]:S["wptr"][q + 1]]] for q in range(len(order))}
+    rng = np.random.default_rng(11)
+    for waves in (1, 2, 3, 8, 13):
+        nslot = min(8, waves)
+        for _ in range(3):
+            fin = _drain_with_slots(order, deps_of, waves, nslot, rng)
+            assert fin is not None, "deadlock with %d waves, %d slots" % (waves, nslot)
+            assert sorted(fin) == list(range(len(order)))
