@@ -41,7 +41,9 @@ typedef enum {
   PMG_OK = 0,
   PMG_EINVAL = 1,     /* invalid argument or unsupported configuration */
   PMG_ENOMEM = 2,     /* host or device allocation failed */
-  PMG_EDEVICE = 3,    /* HIP runtime error, or no device for a device call */
+  PMG_EDEVICE = 3,    /* HIP runtime error, no device for a device call, or a
+                         triangular solve that stopped at its poll bound (see
+                         pmg_options.poll_limit) */
   PMG_EZEROPIVOT = 4, /* ILUT met a zero or non-finite pivot */
   PMG_EDIVERGED = 5,  /* relative residual above the divergence ratio */
   PMG_EMAXIT = 6,     /* max_iter V-cycles without reaching tol */
@@ -55,7 +57,7 @@ enum { PMG_PDE_POISSON = 0, PMG_PDE_CDR = 1 };
 enum { PMG_MASS_LUMPED = 0, PMG_MASS_CONSISTENT = 1 };
 enum { PMG_PROJ_DIRECT = 0, PMG_PROJ_INDIRECT = 1 };
 enum { PMG_FP64 = 0, PMG_FP32_IN_FP64 = 1 };
-enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1 };
+enum { PMG_LIMIT_PER_PART = 0, PMG_LIMIT_PER_ROW = 1, PMG_LIMIT_HALF_PER_PART = 2 };
 enum { PMG_GS_MULTICOLOR = 0 };
 enum { PMG_ORDER_NATURAL = 0, PMG_ORDER_NESTED_DISSECTION = 1 };
 
@@ -124,6 +126,16 @@ typedef struct {
                                degree-(p-1) handle, recursively down to degree 2, whose coarse
                                space is degree 1 with the h-multigrid.  Setup builds one
                                operator, ILUT factorisation and transfer per degree. */
+  int32_t poll_limit;       /* bound on the polls of one wave of a triangular solve waiting
+                               for one batch of entries (0: the default, 1 << 22, seconds of
+                               waiting).  A wave that reaches it marks the solve as faulted
+                               and stops waiting, and so does every other wave of the solve:
+                               the kernels always end.  The next call that synchronises
+                               (pmg_residual or pmg_vcycle with a norm, pmg_solve,
+                               pmg_bicgstab, a server step) returns PMG_EDEVICE, and the
+                               results since the previous such call are invalid.  A
+                               correct schedule never reaches the default bound; small
+                               values force the fault path (test hook). */
 } pmg_options;
 
 typedef struct {
@@ -317,6 +329,7 @@ typedef struct {
   int32_t max_iter;        /* outer steps per request, default 100 */
   int32_t device;          /* HIP device ordinal */
   int32_t setup_threads;   /* host threads per class setup; 0 = default */
+  double diverge_ratio;    /* PMG_EDIVERGED above this relative residual, default 1e10 */
 } pmg_server_options;
 
 typedef struct {
@@ -350,6 +363,11 @@ pmg_status pmg_server_submit(pmg_server s, const pmg_problem *prob, const double
  * n) if non-NULL and its record into *info if non-NULL, then forgets the
  * ticket.  Returns the solve status; EINVAL for an unknown ticket. */
 pmg_status pmg_server_wait(pmg_server s, int64_t ticket, double *x_host, pmg_request_info *info);
+/* Non-blocking form of pmg_server_wait: *done = 0 and PMG_OK while the
+ * request is queued or running; once it is done, *done = 1 and the call acts
+ * as pmg_server_wait (copies, forgets the ticket, returns the solve status).
+ * EINVAL for an unknown ticket or a NULL done. */
+pmg_status pmg_server_poll(pmg_server s, int64_t ticket, int32_t *done, double *x_host, pmg_request_info *info);
 /* Changes slots and precision; waits until no request is queued or active. */
 pmg_status pmg_server_configure(pmg_server s, int32_t max_slots, int32_t precision);
 pmg_status pmg_server_get_stats(pmg_server s, pmg_server_stats *st);

@@ -686,8 +686,10 @@ static int canonical_prolongation(int dim, int nc, ocsr *P) {
 /*   rule 2: keep the M largest entries in the strict lower part and the M    */
 /*   largest in the strict upper part, M = floor(m nnz(A) / n) (mode 0, "per  */
 /*   part"), or the M largest off-diagonal entries in total (mode 1, "per     */
-/*   row"); magnitudes are ranked in single precision and ties go to the     */
-/*   smaller column; exact zeros are never stored.                            */
+/*   row"), or the floor(M/2) largest in each part (mode 2, "half per part": */
+/*   at most M off-diagonal entries per row, split evenly between L and U);   */
+/*   magnitudes are ranked in single precision and ties go to the smaller     */
+/*   column; exact zeros are never stored.                                    */
 /* L is returned as the strict lower part (unit diagonal implied), U as the  */
 /* upper part with the diagonal first in each row.  A zero or non-finite     */
 /* pivot is an error (no substitution).  fill <= 0 means "no limit".         */
@@ -779,7 +781,8 @@ int orc_ilut_raw(int n, const int64_t *rp, const int *ci, const double *v, doubl
       nc++;
     }
     int64_t keepL = 0, keepU = 0;
-    if (mode == 0) {
+    if (mode == 0 || mode == 2) {
+      int64_t Mpart = mode == 2 ? M / 2 : M;
       /* split into lower / upper, sort each by magnitude */
       int a = 0;
       for (int t = 0; t < nc; ++t)
@@ -788,8 +791,8 @@ int orc_ilut_raw(int n, const int64_t *rp, const int *ci, const double *v, doubl
       nup = nc - a;
       qsort(cand, (size_t)nlo, sizeof(ent), ent_cmp_mag);
       qsort(cand + nlo, (size_t)nup, sizeof(ent), ent_cmp_mag);
-      keepL = nlo < M ? nlo : M;
-      keepU = nup < M ? nup : M;
+      keepL = nlo < Mpart ? nlo : Mpart;
+      keepU = nup < Mpart ? nup : Mpart;
       /* move the kept upper entries right after the kept lower ones */
       memmove(cand + keepL, cand + nlo, sizeof(ent) * (size_t)keepU);
     } else {

@@ -25,6 +25,7 @@ MASS_LUMPED, MASS_CONSISTENT = 0, 1
 PROJ_DIRECT, PROJ_INDIRECT = 0, 1
 FP64, FP32_IN_FP64 = 0, 1
 ORDER_NATURAL, ORDER_NESTED_DISSECTION = 0, 1
+LIMIT_PER_PART, LIMIT_PER_ROW, LIMIT_HALF_PER_PART = 0, 1, 2
 OP_A, OP_L, OP_U, OP_R, OP_P, OP_A1, OP_PH = range(7)
 VEC_F, VEC_MLP, VEC_ML1, VEC_COARSE_INV = range(4)
 PROF_CLASSES = ("residual", "lower", "upper", "restrict", "coarse", "prolong")
@@ -49,7 +50,7 @@ class Options(C.Structure):
                 ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
                 ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32),
-                ("projection", C.c_int32)]
+                ("projection", C.c_int32), ("poll_limit", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -76,7 +77,7 @@ class Info(C.Structure):
 class ServerOptions(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("max_class_bytes", C.c_int64), ("max_slots", C.c_int32),
                 ("precision", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("device", C.c_int32),
-                ("setup_threads", C.c_int32)]
+                ("setup_threads", C.c_int32), ("diverge_ratio", C.c_double)]
 
 
 class RequestInfo(C.Structure):
@@ -126,6 +127,7 @@ SIGNATURES = {
     "pmg_server_prepare": (C.c_int, [_VP, C.POINTER(Problem)]),
     "pmg_server_submit": (C.c_int, [_VP, C.POINTER(Problem), _DP, _I64P]),
     "pmg_server_wait": (C.c_int, [_VP, C.c_int64, _DP, C.POINTER(RequestInfo)]),
+    "pmg_server_poll": (C.c_int, [_VP, C.c_int64, _I32P, _DP, C.POINTER(RequestInfo)]),
     "pmg_server_configure": (C.c_int, [_VP, C.c_int32, C.c_int32]),
     "pmg_server_get_stats": (C.c_int, [_VP, C.POINTER(ServerStats)]),
     "pmg_server_clock": (C.c_double, [_VP]),
@@ -390,6 +392,22 @@ class Server:
         x = np.zeros(n) if want_x else None
         info = RequestInfo()
         st = lib().pmg_server_wait(self._h, ticket, x.ctypes.data_as(_DP) if want_x else None, C.byref(info))
+        return st, info.as_dict(), x
+
+    def poll(self, ticket, want_x=True):
+        """Non-blocking wait: None while the request runs, else as wait()."""
+        n = self._n.get(ticket)
+        if n is None:
+            raise KeyError(ticket)
+        x = np.zeros(n) if want_x else None
+        info = RequestInfo()
+        done = C.c_int32(0)
+        st = lib().pmg_server_poll(self._h, ticket, C.byref(done), x.ctypes.data_as(_DP) if want_x else None,
+                                   C.byref(info))
+        if not done.value:
+            _check(st)
+            return None
+        self._n.pop(ticket)
         return st, info.as_dict(), x
 
     def configure(self, max_slots, precision):

@@ -940,31 +940,42 @@ __device__ __forceinline__ T publishable(T v) {
   return pending(v) ? (T)__builtin_nan("") : v;
 }
 
-// Draws the wave's next ticket from the counter of its grid slot: every lane
-// takes part in the atomic (lane 0 adds 1, the others 0) and lane 0's old
-// value k gives ticket k * nslot + slot.  No branch depends on the lane here:
-// inside a loop, a lane-dependent branch around the atomic followed by a
-// cross-lane read lets the compiler send lane 0 and the other lanes round
-// different loops.
+// Counters and fault word of one triangular solve.  state: the ticket
+// counter and the exited-wave count (kTicketWords words); fault: set to 1
+// by a wave that polled a batch poll_limit times, and left for the host to
+// read and clear.
+struct TriCtl {
+  unsigned* state;
+  unsigned* fault;
+  int poll_limit;
+};
+
+// Draws the wave's next ticket: every lane takes part in the atomic (lane 0
+// adds 1, the others 0) and lane 0's old value is the ticket.  No branch
+// depends on the lane here: inside a loop, a lane-dependent branch around the
+// atomic followed by a cross-lane read lets the compiler send lane 0 and the
+// other lanes round different loops.
 //
-// Why no wave waits forever: tickets follow a topological order of the chunk
-// graph, so the smallest unfinished ticket only waits for finished chunks.
-// It is held by a running wave: if it were not drawn yet, every wave of its
-// slot would hold a smaller ticket of that slot, unfinished, against its
-// being the smallest.  Every slot has waves (nslot <= grid size).
-__device__ __forceinline__ int wave_ticket(unsigned* state, int slot, int nslot) {
-  const unsigned v = atomicAdd(state + slot * kTicketStride, (threadIdx.x & 63) == 0 ? 1u : 0u);
-  return __builtin_amdgcn_readfirstlane((int)v) * nslot + slot;
+// Why no wave waits forever, whatever the number of resident waves: tickets
+// follow a topological order of the chunk graph, so the smallest unfinished
+// ticket only waits for finished chunks, and it is held by a wave that is
+// running (a wave draws a ticket only once it runs, and tickets are drawn in
+// increasing order from the one counter).  That wave finishes its chunk, and
+// by induction every chunk is finished.  The poll bound (TriCtl) turns a
+// schedule that breaks this order into a reported fault instead of a hang.
+__device__ __forceinline__ int wave_ticket(unsigned* state) {
+  const unsigned v = atomicAdd(state, (threadIdx.x & 63) == 0 ? 1u : 0u);
+  return __builtin_amdgcn_readfirstlane((int)v);
 }
 
 // Called by every wave of the grid once it has drawn a ticket past the last
 // chunk.  The last wave to get here clears the counters for the next launch
 // (all other waves have exited), so a solve needs no separate reset launch.
-__device__ __forceinline__ void finish_grid(unsigned* state, int nslot, int lane) {
-  unsigned* exited = state + kTicketSlots * kTicketStride;
+__device__ __forceinline__ void finish_grid(unsigned* state, int lane) {
+  unsigned* exited = state + kTicketStride;
   const unsigned prev = atomicAdd(exited, lane == 0 ? 1u : 0u);
   if ((unsigned)__builtin_amdgcn_readfirstlane((int)prev) == gridDim.x - 1 && lane == 0) {
-    for (int c = 0; c < nslot; ++c) st_dev(state + c * kTicketStride, 0u);
+    st_dev(state, 0u);
     st_dev(exited, 0u);
   }
 }
@@ -1109,7 +1120,7 @@ __device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, int col, float
 template <typename T>
 __device__ __forceinline__ T gather_batch(T t, const int (&cc)[kTriBatch], int (&cn)[kTriBatch], int u0,
                                           const TriMeta& m, int lane, const TriDev<T>& F, const T* y,
-                                          __amdgpu_buffer_rsrc_t yr) {
+                                          __amdgpu_buffer_rsrc_t yr, const TriCtl& ctl) {
   const bool act = lane < m.nrow;
   T yy[kTriBatch];
 #pragma unroll
@@ -1121,15 +1132,25 @@ __device__ __forceinline__ T gather_batch(T t, const int (&cc)[kTriBatch], int (
 #pragma unroll
   for (int u = 0; u < kTriBatch; ++u) s -= aa[u] * yy[u];  // padding: 0 * 0
   if (__ballot(s != s) == 0) return s;
-  for (;;) {
+  // The fault word is reloaded with the pending entries, so checking it adds
+  // no round trip; after poll_limit polls, or once another wave has set it,
+  // the wave stops waiting and its sums turn NaN (the marker is a NaN), which
+  // it stores as a quiet NaN, so no later wave waits on it either.
+  unsigned fault = 0;
+  for (int polls = 0;; ++polls) {
     bool pend = false;
 #pragma unroll
     for (int u = 0; u < kTriBatch; ++u) pend |= pending(yy[u]);
     if (__ballot(pend) == 0) break;
+    if (polls >= ctl.poll_limit || __builtin_amdgcn_readfirstlane((int)fault) != 0) {
+      st_dev(ctl.fault, 1u);
+      break;
+    }
     __builtin_amdgcn_s_sleep(2);
 #pragma unroll
     for (int u = 0; u < kTriBatch; ++u)
       if (pending(yy[u])) yy[u] = ld_dev(y + cc[u]);
+    fault = ld_dev(ctl.fault);
   }
 #pragma unroll
   for (int u = 0; u < kTriBatch; ++u) t -= aa[u] * yy[u];
@@ -1144,14 +1165,14 @@ __device__ __forceinline__ T gather_batch(T t, const int (&cc)[kTriBatch], int (
 // arrive, no further batch has to be loaded.
 template <typename T>
 __device__ __forceinline__ T gather_off(T t, int (&cc)[kTriBatch], const TriMeta& m, int lane,
-                                        const TriDev<T>& F, const T* y) {
+                                        const TriDev<T>& F, const T* y, const TriCtl& ctl) {
   const __amdgpu_buffer_rsrc_t yr = vec_rsrc(y, F.n);
   int cn[kTriBatch];
   for (int u0 = first_batch(m.off_w);;) {
-    t = gather_batch(t, cc, cn, u0, m, lane, F, y, yr);
+    t = gather_batch(t, cc, cn, u0, m, lane, F, y, yr, ctl);
     u0 += kTriBatch;
     if (u0 >= m.off_w) break;
-    t = gather_batch(t, cn, cc, u0, m, lane, F, y, yr);
+    t = gather_batch(t, cn, cc, u0, m, lane, F, y, yr, ctl);
     u0 += kTriBatch;
     if (u0 >= m.off_w) break;
   }
@@ -1195,12 +1216,11 @@ __device__ __forceinline__ T serial_backward(T t, const T* tile, int lane) {
 // y must hold kPending in every entry at launch.
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_lower(
-    int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y, unsigned* state, int nslot) {
+    int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ r, T* y, TriCtl ctl) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
-  const int slot = (int)(blockIdx.x % (unsigned)nslot);
   for (;;) {
-    const int tk = wave_ticket(state, slot, nslot);
+    const int tk = wave_ticket(ctl.state);
     if (tk >= nq) break;
     const TriMeta m = ld_meta(F.meta + tk);
     const int row = m.row0 + lane;
@@ -1215,11 +1235,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     T t = r[pr];
     t = act ? t : (T)0;
     stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F, act);
-    t = gather_off(t, cc, m, lane, F, y);
+    t = gather_off(t, cc, m, lane, F, y, ctl);
     t = serial_forward(t, tile, lane);
     if (act) st_dev(y + row, publishable(t));
   }
-  finish_grid(state, nslot, lane);
+  finish_grid(ctl.state, lane);
 }
 
 // e = U^{-1} y (diagonal in F.diag) and x += P^T e.  e must hold kPending in
@@ -1227,12 +1247,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void trisolve_upper(
     int nq, TriDev<T> F, const int* __restrict__ perm, const T* __restrict__ y, T* e, T* __restrict__ x,
-    unsigned* state, int nslot) {
+    TriCtl ctl) {
   __shared__ T tile[kWave * kWave];
   const int lane = threadIdx.x & 63;
-  const int slot = (int)(blockIdx.x % (unsigned)nslot);
   for (;;) {
-    const int tk = wave_ticket(state, slot, nslot);
+    const int tk = wave_ticket(ctl.state);
     if (tk >= nq) break;
     const TriMeta m = ld_meta(F.meta + tk);
     const int row = m.row0 + lane;
@@ -1250,7 +1269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     stage_tile(tile, jj, vv, m.in_ptr, m.in_w, lane, F, act);
     T t = act ? t0 : (T)0;
     const T dg = act ? d0 : (T)1;
-    t = gather_off(t, cc, m, lane, F, (const T*)e);
+    t = gather_off(t, cc, m, lane, F, (const T*)e, ctl);
     t = serial_backward(t, tile, lane);
     const T ev = t / dg;
     if (act) {
@@ -1258,7 +1277,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
       x[pr] = xv + ev;
     }
   }
-  finish_grid(state, nslot, lane);
+  finish_grid(ctl.state, lane);
 }
 
 }  // namespace pmg

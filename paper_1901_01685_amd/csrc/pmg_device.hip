@@ -574,8 +574,11 @@ int tri_grid(const TriSched& S) {
   return sizeof(T) == 8 ? S.grid64 : S.grid32;
 }
 
-// Ticket slots of a launch of g waves: every slot needs at least one wave.
-inline int tri_slots(int g) { return std::max(1, std::min(pmg::kTicketSlots, g)); }
+// Counters and fault word of a triangular solve of ws (factor 0 lower, 1 upper).
+pmg::TriCtl tri_ctl(pmg_handle h, Workspace& ws, int factor) {
+  return pmg::TriCtl{ws.tickets + factor * pmg::kTicketWords, ws.tickets + 2 * pmg::kTicketWords,
+                     h->opt.poll_limit > 0 ? h->opt.poll_limit : pmg::kPollLimit};
+}
 
 // Persistent grid of the triangular solves: as many waves as fit on the
 // device at once (more would only start after others exit), at most one per
@@ -723,10 +726,13 @@ void fill(T* p, int64_t n, T val, hipStream_t st) {
   if (n > 0) pmg::fill_kernel<T><<<nblocks(n, 256), 256, 0, st>>>(n, p, val);
 }
 
-double read_norm(Workspace& ws, hipStream_t st) {
+// Waits for the norm enqueued last on st and writes it to *out; EDEVICE if a
+// triangular solve of ws reported a fault since the last check.
+pmg_status read_norm(Workspace& ws, hipStream_t st, double* out) {
   pmgdev::enqueue_norm_readback(ws, st);
-  hipStreamSynchronize(st);
-  return std::sqrt(ws.host_scalar[0]);
+  PMG_HIP_OK(hipStreamSynchronize(st));
+  *out = std::sqrt(ws.host_scalar[0]);
+  return pmgdev::take_fault(ws, st);
 }
 
 // Marks every entry of a solve's output as not final (pmg::kPending).
@@ -742,7 +748,7 @@ void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_LOWER, st);
   fill_pending(y, h->H.n, st);
   const int g = tri_grid<T>(h->tl);
-  pmg::trisolve_lower<T><<<g, 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, ws.tickets, tri_slots(g));
+  pmg::trisolve_lower<T><<<g, 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, tri_ctl(h, ws, 0));
 }
 
 template <typename T>
@@ -750,8 +756,7 @@ void upper_impl(pmg_handle h, Workspace& ws, const T* y, T* e, T* x, hipStream_t
   ProfScope ps(h, PMG_PROF_UPPER, st);
   fill_pending(e, h->H.n, st);
   const int g = tri_grid<T>(h->tu);
-  pmg::trisolve_upper<T><<<g, 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x,
-                                           ws.tickets + pmg::kTicketWords, tri_slots(g));
+  pmg::trisolve_upper<T><<<g, 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x, tri_ctl(h, ws, 1));
 }
 
 // x += U^{-1} L^{-1} P r (then permuted back) with work vectors y, e.
@@ -1054,7 +1059,7 @@ size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors) {
   const pmg::HostOps& H = h->H;
   size_t b = 8 * (3 * (size_t)H.n + 2 * (size_t)std::max(H.n1, 1)) + 8 * (size_t)h->partial_cap + 32;
   for (int l = 0; l < H.nlev; ++l) b += 8 * (size_t)H.ln[l] * (l == 0 ? 1 : 3);
-  b += 2 * pmg::kTicketWords * sizeof(unsigned);
+  b += pmg::kTicketAlloc * sizeof(unsigned);
   if (mixed) b += 4 * (5 * (size_t)H.n + (size_t)std::max(H.n1, 1));
   if (request_vectors) b += 16 * (size_t)H.n;
   return b;
@@ -1086,8 +1091,8 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
   }
   for (int l = 0; l < H.nlev; ++l)
     if ((s = m.alloc(&ws.hr[l], H.ln[l]))) return s;
-  if ((s = m.alloc(&ws.tickets, 2 * pmg::kTicketWords))) return s;
-  fill<unsigned>(ws.tickets, 2 * pmg::kTicketWords, 0u, st);
+  if ((s = m.alloc(&ws.tickets, pmg::kTicketAlloc))) return s;
+  fill<unsigned>(ws.tickets, pmg::kTicketAlloc, 0u, st);
   if (h->opt.mass_transfer == PMG_MASS_CONSISTENT && H.n1 > 0 && (s = alloc_mass(h, ws))) return s;
   PMG_HIP_OK(hipGetLastError());
   if (mixed) {
@@ -1103,6 +1108,7 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
     if ((s = m.alloc(&ws.x, n))) return s;
   }
   PMG_HIP_OK(hipHostMalloc((void**)&ws.host_scalar, 4 * sizeof(double), hipHostMallocDefault));
+  std::memset(ws.host_scalar, 0, 4 * sizeof(double));
   if (!st) PMG_HIP_OK(hipDeviceSynchronize());
   return PMG_OK;
 }
@@ -1116,6 +1122,23 @@ void residual64(pmg_handle h, Workspace& ws, const double* b, const double* x, d
 
 void enqueue_norm_readback(Workspace& ws, hipStream_t st) {
   hipMemcpyAsync(ws.host_scalar, ws.scalar, sizeof(double), hipMemcpyDeviceToHost, st);
+  enqueue_fault_readback(ws, st);
+}
+
+void enqueue_fault_readback(Workspace& ws, hipStream_t st) {
+  hipMemcpyAsync(ws.host_scalar + 1, ws.tickets + 2 * pmg::kTicketWords, sizeof(unsigned), hipMemcpyDeviceToHost,
+                 st);
+}
+
+pmg_status take_fault(Workspace& ws, hipStream_t st) {
+  unsigned f;
+  std::memcpy(&f, ws.host_scalar + 1, sizeof f);
+  if (!f) return PMG_OK;
+  std::memset(ws.host_scalar + 1, 0, sizeof(double));
+  fill<unsigned>(ws.tickets + 2 * pmg::kTicketWords, 1, 0u, st);
+  return fail(PMG_EDEVICE,
+              "a triangular solve stopped waiting for an entry after its poll bound (options.poll_limit); "
+              "the results since the last check are invalid");
 }
 
 // One FP64 V-cycle; r holds b - A x on entry and exit.
@@ -1334,11 +1357,12 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   if (o.nu1 < 0 || o.nu2 < 0 || o.coarse_cycles < 1 || o.coarse_min_elems < 1 || o.max_iter < 0 ||
       !(o.ilut_tau >= 0) || o.gs_variant != PMG_GS_MULTICOLOR ||
       (o.precision != PMG_FP64 && o.precision != PMG_FP32_IN_FP64) ||
-      (o.ilut_limit_mode != PMG_LIMIT_PER_PART && o.ilut_limit_mode != PMG_LIMIT_PER_ROW) || o.device < -1 ||
+      (o.ilut_limit_mode != PMG_LIMIT_PER_PART && o.ilut_limit_mode != PMG_LIMIT_PER_ROW &&
+       o.ilut_limit_mode != PMG_LIMIT_HALF_PER_PART) || o.device < -1 ||
       (o.ordering != PMG_ORDER_NATURAL && o.ordering != PMG_ORDER_NESTED_DISSECTION) || o.nd_leaf < 1 ||
       (o.mass_transfer != PMG_MASS_LUMPED && o.mass_transfer != PMG_MASS_CONSISTENT) ||
       (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64) ||
-      (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT))
+      (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT) || o.poll_limit < 0)
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
@@ -1671,7 +1695,7 @@ pmg_status pmg_residual(pmg_handle h, const double* b, const double* x, double* 
   hipStream_t st = (hipStream_t)stream;
   pmgdev::residual64(h, h->ws, b, x, r, rnorm != nullptr, st);
   PMG_HIP_OK(hipGetLastError());
-  if (rnorm) *rnorm = read_norm(h->ws, st);
+  if (rnorm) return read_norm(h->ws, st, rnorm);
   return PMG_OK;
 }
 
@@ -1759,7 +1783,7 @@ pmg_status pmg_vcycle(pmg_handle h, const double* b, double* x, double* r, doubl
   hipStream_t st = (hipStream_t)stream;
   pmgdev::outer_step(h, h->ws, false, b, x, r, rnorm != nullptr, st);
   PMG_HIP_OK(hipGetLastError());
-  if (rnorm) *rnorm = read_norm(h->ws, st);
+  if (rnorm) return read_norm(h->ws, st, rnorm);
   return PMG_OK;
 }
 
@@ -1773,7 +1797,9 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
   pmg_result R{};
   pmgdev::residual64(h, ws, b, x, ws.r, true, st);
   PMG_HIP_OK(hipGetLastError());
-  const double r0 = read_norm(ws, st);
+  double r0 = 0.0;
+  pmg_status s0 = read_norm(ws, st, &r0);
+  if (s0) return s0;
   R.r0 = r0;
   R.relres = 1.0;
   if (hist) hist[0] = 1.0;
@@ -1788,7 +1814,9 @@ pmg_status pmg_solve(pmg_handle h, const double* b, double* x, double tol, pmg_r
     for (int it = 1; it <= h->opt.max_iter; ++it) {
       pmgdev::outer_step(h, ws, mixed, b, x, ws.r, true, st);
       PMG_HIP_OK(hipGetLastError());
-      const double rel = read_norm(ws, st) / r0;
+      double nrm = 0.0;
+      if ((s0 = read_norm(ws, st, &nrm))) return s0;
+      const double rel = nrm / r0;
       R.iterations = it;
       R.relres = rel;
       if (hist) hist[it] = rel;
@@ -1827,7 +1855,8 @@ pmg_status pmg_bicgstab(pmg_handle h, const double* b, double* x, double tol, pm
   fill<double>(ws.bc_v, n, 0.0, st);
   pmg::bicg_init<<<1, 1, 0, st>>>(ws.scalar, ws.bc_S);
   PMG_HIP_OK(hipGetLastError());
-  const double r0 = read_norm(ws, st);
+  double r0 = 0.0;
+  if ((s = read_norm(ws, st, &r0))) return s;
   R.r0 = r0;
   R.relres = 1.0;
   if (hist) hist[0] = 1.0;
@@ -1842,7 +1871,9 @@ pmg_status pmg_bicgstab(pmg_handle h, const double* b, double* x, double tol, pm
     for (int it = 1; it <= h->opt.max_iter; ++it) {
       pmgdev::run_cached(h, ws, key, [&](hipStream_t q) { pmgdev::bicg_iteration(h, ws, x, q); }, st);
       PMG_HIP_OK(hipMemcpyAsync(ws.bc_host, ws.bc_S, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+      pmgdev::enqueue_fault_readback(ws, st);
       PMG_HIP_OK(hipStreamSynchronize(st));
+      if ((s = pmgdev::take_fault(ws, st))) return s;
       const double rel = std::sqrt(ws.bc_host[7]) / r0;
       R.iterations = it;
       R.relres = rel;

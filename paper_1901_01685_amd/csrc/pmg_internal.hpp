@@ -107,7 +107,7 @@ struct Workspace {
   double *b = nullptr, *x = nullptr;  // request vectors (server slots only)
   double* host_scalar = nullptr;      // pinned
   std::vector<double*> hb, he, hr;
-  unsigned* tickets = nullptr;  // lower: pmg::kTicketWords counters (see wave_ticket), then upper
+  unsigned* tickets = nullptr;  // pmg::kTicketAlloc words: lower and upper solve counters, fault word
   float *r32 = nullptr, *c32 = nullptr, *y32 = nullptr, *e32 = nullptr, *t32 = nullptr, *q32 = nullptr;
   bool mixed = false;
   // BiCGSTAB (pmg_bicgstab): shadow residual, direction, A y, preconditioned
@@ -205,8 +205,14 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
 // One defect-correction step: r (FP64 residual, in ws.r) -> FP32 V-cycle ->
 // x += c -> r = b - A x and its norm (device scalar).
 void mixed_step(pmg_handle h, Workspace& ws, const double* b, double* x, hipStream_t st);
-// Enqueues the copy of the last norm^2 into ws.host_scalar.
+// Enqueues the copy of the last norm^2 into ws.host_scalar[0] and of the
+// triangular solves' fault word into ws.host_scalar[1] (enqueue_fault_readback).
 void enqueue_norm_readback(Workspace& ws, hipStream_t st);
+void enqueue_fault_readback(Workspace& ws, hipStream_t st);
+// After the stream has passed the readback: EDEVICE (with a message) if a
+// triangular solve of ws stopped at its poll bound, and then the word is
+// cleared on st; PMG_OK otherwise.
+pmg_status take_fault(Workspace& ws, hipStream_t st);
 // One outer step of the solve on st: the FP64 V-cycle (vcycle64 with b, x,
 // r, norm) or, with mixed, the defect-correction step (mixed_step; r is
 // ws.r and the norm is always taken).  With the handle's graphs option the

@@ -326,6 +326,7 @@ struct pmg_server_s {
         Slot& s = slots[i];
         if (!s.req || hipEventQuery(s.ev) != hipSuccess) continue;
         progressed = true;
+        if (pmgdev::take_fault(*s.ws, s.stream) != PMG_OK) { finish(s, PMG_EDEVICE, 1.0); continue; }
         const double nrm = std::sqrt(s.ws->host_scalar[0]);
         if (s.phase == 1) {
           s.r0 = nrm;
@@ -336,7 +337,7 @@ struct pmg_server_s {
         }
         s.it++;
         const double rel = nrm / s.r0;
-        if (!std::isfinite(rel) || rel > 1e10) { finish(s, PMG_EDIVERGED, rel); continue; }
+        if (!std::isfinite(rel) || rel > opt.diverge_ratio) { finish(s, PMG_EDIVERGED, rel); continue; }
         if (rel <= opt.tol) { finish(s, PMG_OK, rel); continue; }
         if (s.it >= opt.max_iter) { finish(s, PMG_EMAXIT, rel); continue; }
         launch_step(s);
@@ -359,6 +360,7 @@ pmg_status pmg_server_default_options(pmg_server_options* o) {
   o->max_iter = 100;
   o->device = 0;
   o->setup_threads = 0;
+  o->diverge_ratio = 1e10;
   return PMG_OK;
 }
 
@@ -368,7 +370,7 @@ pmg_status pmg_server_create(const pmg_server_options* o, pmg_server* out) {
   pmg_server_options op;
   if (o) op = *o; else pmg_server_default_options(&op);
   if (op.budget_bytes <= 0 || op.max_slots < 1 || op.max_slots > 256 || !(op.tol > 0) || op.max_iter < 1 ||
-      (op.precision != PMG_FP64 && op.precision != PMG_FP32_IN_FP64))
+      !(op.diverge_ratio > 0) || (op.precision != PMG_FP64 && op.precision != PMG_FP32_IN_FP64))
     return fail(PMG_EINVAL, "invalid server options");
   if (op.max_class_bytes <= 0) op.max_class_bytes = op.budget_bytes / 4;
   int ndev = 0;
@@ -467,6 +469,21 @@ pmg_status pmg_server_wait(pmg_server s, int64_t ticket, double* x_host, pmg_req
   if (it == s->requests.end()) return fail(PMG_EINVAL, "unknown ticket");
   auto req = it->second;
   s->cv_done.wait(lk, [&] { return req->done; });
+  if (x_host) std::memcpy(x_host, req->x.data(), sizeof(double) * req->x.size());
+  if (info) *info = req->info;
+  s->requests.erase(it);
+  return (pmg_status)req->info.status;
+}
+
+pmg_status pmg_server_poll(pmg_server s, int64_t ticket, int32_t* done, double* x_host, pmg_request_info* info) {
+  if (!s || !done) return fail(PMG_EINVAL, "NULL argument");
+  *done = 0;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return fail(PMG_EINVAL, "unknown ticket");
+  auto req = it->second;
+  if (!req->done) return PMG_OK;
+  *done = 1;
   if (x_host) std::memcpy(x_host, req->x.data(), sizeof(double) * req->x.size());
   if (info) *info = req->info;
   s->requests.erase(it);

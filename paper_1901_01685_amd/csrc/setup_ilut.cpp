@@ -9,9 +9,10 @@
 //           diagonal);
 //   rule 2  only the M largest entries are kept, M = floor(m nnz(A) / n),
 //           either per part (M in the strict lower part and M in the strict
-//           upper part; default) or per row (M off-diagonal entries in
-//           total); magnitudes are ranked in single precision and ties go
-//           to the smaller column; exact zeros are never stored.
+//           upper part), per row (M off-diagonal entries in total) or half
+//           per part (floor(M/2) in each part); magnitudes are ranked in
+//           single precision and ties go to the smaller column; exact zeros
+//           are never stored.
 // A zero or non-finite pivot fails the factorisation (no substitution).
 //
 // Rows depend on earlier rows only through the pivots they meet, and each
@@ -175,14 +176,15 @@ int ilut_factor(const Csr& A, double tau, double fill, int mode, int threads, Cs
           if (x == 0.0 || std::fabs(x) < taui) continue;
           (j < i ? lo : up).push_back({j, x});
         }
-        if (mode == 0) {
-          if ((int64_t)lo.size() > M) {
-            std::nth_element(lo.begin(), lo.begin() + M, lo.end(), mag_before);
-            lo.resize(M);
+        if (mode != 1) {
+          const int64_t Mp = mode == 2 ? M / 2 : M;
+          if ((int64_t)lo.size() > Mp) {
+            std::nth_element(lo.begin(), lo.begin() + Mp, lo.end(), mag_before);
+            lo.resize(Mp);
           }
-          if ((int64_t)up.size() > M) {
-            std::nth_element(up.begin(), up.begin() + M, up.end(), mag_before);
-            up.resize(M);
+          if ((int64_t)up.size() > Mp) {
+            std::nth_element(up.begin(), up.begin() + Mp, up.end(), mag_before);
+            up.resize(Mp);
           }
         } else {
           std::vector<Entry> all(lo);

@@ -10,14 +10,22 @@ constexpr int kTriBatch = 32;
 constexpr int kColGroup = 4;
 // Padding entries at the end of each sliced array (one 16-byte group per lane).
 constexpr int kTriPad = 64 * kColGroup;
-// Ticket counters of one solve: up to kTicketSlots counters kTicketStride
-// words (128 bytes) apart, then the count of exited waves; kTicketWords words
-// per solve.  The waves of grid slot c (block index mod the slot count) draw
-// tickets c, c + slots, c + 2 slots, ... from counter c, so no single address
-// takes every wave's atomic.
-constexpr int kTicketSlots = 8;
+// Ticket counters of one solve: the ticket counter, then kTicketStride words
+// (128 bytes) further the count of exited waves; kTicketWords words per
+// solve.  Every wave of the grid draws its tickets from the one counter, so
+// tickets are handed out in the order waves ask for them, whichever waves
+// are resident.
 constexpr int kTicketStride = 32;
-constexpr int kTicketWords = (kTicketSlots + 1) * kTicketStride;
+constexpr int kTicketWords = 2 * kTicketStride;
+// Words of a workspace's solve state: the lower solve's counters, the upper
+// solve's, then the fault word (TriCtl) shared by both.
+constexpr int kTicketAlloc = 2 * kTicketWords + kTicketStride;
+// Default bound on the polls of one wave waiting for one batch of entries
+// (each poll sleeps ~128 cycles and reloads the pending entries, so the bound
+// is seconds, far above any wait of a correct schedule).  A wave that reaches
+// it sets the solve's fault word and stops waiting; every other wave stops
+// waiting once it sees the word, so the grid always drains.
+constexpr int kPollLimit = 1 << 22;
 
 // Marker of a solution entry that is not final yet.  Before a triangular
 // solve the output vector is filled with it; a wave that needs an entry

@@ -218,3 +218,60 @@ def test_status_codes():
     assert st == O.ENAN
     x, st, it, _ = o.solve(np.zeros(o.n), tol=1e-8)
     assert st == 0 and it == 0 and not x.any()
+
+
+def _gs_sweep_matrix(A, dim):
+    """Error propagation of one multicolour Gauss-Seidel sweep (reading R10:
+    colour of an interior degree-1 node = parity of each 0-based index,
+    colours swept in increasing order; colour c sets e_i += (b - A e)_i / a_ii
+    for its nodes, which are uncoupled): S = S_{2^d-1} ... S_1 S_0 with
+    S_c = I - diag(mask_c / a_ii) A."""
+    A = A.toarray()
+    n = A.shape[0]
+    n1 = round(n ** (1.0 / dim))
+    idx = np.arange(n)
+    colour = sum(((idx // n1 ** a) % n1 % 2) << a for a in range(dim))
+    S = np.eye(n)
+    d = np.diag(A)
+    for c in range(2 ** dim):
+        mask = (colour == c).astype(float)
+        S = (np.eye(n) - (mask / d)[:, None] * A) @ S
+    return S
+
+
+@pytest.mark.parametrize("dim,nel", [(2, 16), (2, 32), (3, 12)])
+def test_hcycle_error_propagator_is_the_figure1_composition(dim, nel):
+    """One h-multigrid V-cycle (Figure 1, lower part; Section 3's coarse solve:
+    one Gauss-Seidel sweep before and after the coarse correction, canonical
+    prolongation P, restriction P^T, direct solve on the coarsest mesh) maps
+    the error e of A_l e = b to E_l e with
+        E_l = S_l (I - P_l B_{l+1} P_l^T A_l) S_l,
+        B_{l+1} = (I - E_{l+1}) A_{l+1}^{-1}   (one cycle from zero),
+        B at the coarsest level = A^{-1}.
+    E_0 is built densely from the exported level operators and compared with
+    the oracle's cycle applied to unit errors (b = 0), column by column; then
+    the coarse correction (two cycles from zero) is checked against
+    (I - E_0^2) A_0^{-1}.  A dropped or misplaced smoothing, a wrong colour
+    order, a scaled restriction or a missing recursion level fails this."""
+    o = O.Oracle(dim, 2, nel, ilut=False)
+    nlev = o.nlev
+    assert nlev == {(2, 16): 2, (2, 32): 3, (3, 12): 2}[(dim, nel)]
+    A = [o.A1(l) for l in range(nlev)]
+    B = np.linalg.inv(A[-1].toarray())
+    for l in range(nlev - 2, -1, -1):
+        Al = A[l].toarray()
+        P = o.Ph(l).toarray()
+        assert P.shape == (Al.shape[0], A[l + 1].shape[0])
+        S = _gs_sweep_matrix(A[l], dim)
+        E = S @ (np.eye(len(Al)) - P @ B @ P.T @ Al) @ S
+        B = (np.eye(len(Al)) - E) @ np.linalg.inv(Al)
+    n = A[0].shape[0]
+    zero = np.zeros(n)
+    Eo = np.column_stack([o.hcycle(zero, np.eye(n)[:, j]) for j in range(n)])
+    assert np.abs(Eo - E).max() <= 1e-12 * max(1.0, np.abs(E).max()), np.abs(Eo - E).max()
+    # coarse correction at p = 1: coarse_cycles = 2 cycles from e1 = 0
+    rng = np.random.default_rng(3)
+    r1 = rng.standard_normal(n)
+    ref = (np.eye(n) - E @ E) @ np.linalg.solve(A[0].toarray(), r1)
+    got = o.coarse(r1)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()

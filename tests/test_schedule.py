@@ -156,32 +156,34 @@ def test_skewed_chunks_shorten_the_chain():
         assert skewed <= 0.85 * lev.max(), (skewed, lev.max())
 
 
-def _drain_with_slots(order, deps_of, waves, nslot, rng):
-    """Waves of slot c = wave mod nslot draw tickets c, c + nslot, ... from
-    counter c and finish their chunk once every chunk it reads is finished,
-    in a random interleaving.  Returns the chunks in finishing order, or None
-    if no wave can move while chunks remain (a deadlock)."""
+def _drain(order, deps_of, waves, resident, rng):
+    """Replays the ticket protocol of the triangular-solve kernels: the grid
+    has `waves` waves, of which at most `resident` run at once (the others
+    start only as running waves exit, as when other kernels hold the rest of
+    the device).  A running wave draws the next ticket from the one counter,
+    exits once the tickets run out, and finishes its chunk once every chunk
+    it reads is finished; the step taken next is random.  Returns the chunks
+    in finishing order, or None if no running wave can move while chunks
+    remain (a deadlock)."""
     nq = len(order)
-    count = [0] * nslot
-    held = [None] * waves          # ticket held by each wave
-    alive = list(range(waves))
+    count = 0
+    held = {}                      # running wave -> ticket or None
+    waiting = list(range(waves))   # waves not started yet
     done = np.zeros(nq, dtype=bool)
     finished = []
-    while alive:
-        movable = []
-        for w in alive:
-            t = held[w]
-            if t is None or all(done[d] for d in deps_of[order[t]]):
-                movable.append(w)
+    while held or waiting:
+        while waiting and len(held) < resident:
+            held[waiting.pop(0)] = None
+        movable = [w for w, t in held.items()
+                   if t is None or all(done[d] for d in deps_of[order[t]])]
         if not movable:
             return None
         w = movable[rng.integers(len(movable))]
         if held[w] is None:
-            c = w % nslot
-            t = count[c] * nslot + c
-            count[c] += 1
+            t = count
+            count += 1
             if t >= nq:
-                alive.remove(w)
+                del held[w]
             else:
                 held[w] = t
         else:
@@ -193,17 +195,33 @@ def _drain_with_slots(order, deps_of, waves, nslot, rng):
 
 
 @pytest.mark.parametrize("factor", [0, 1])
-def test_slot_tickets_never_deadlock(factor):
-    """Per-slot ticket counters (trisolve kernels): with any number of waves
-    and slots (slots <= waves), every interleaving drains all chunks."""
+def test_tickets_never_deadlock_under_partial_residency(factor):
+    """One ticket counter (trisolve kernels): with any grid size and any
+    number of waves resident at once, down to one, every interleaving drains
+    all chunks, so the solves cannot wait on a wave that never runs."""
     s = pmg.Solver(2, 3, 40, device=-1)
     S = s.export_schedule(factor)
     order = [int(q) for q in S["order"]]
     deps_of = {q: [int(d) for d in S["deps"][S["wptr"][q]:S["wptr"][q + 1]]] for q in range(len(order))}
     rng = np.random.default_rng(11)
-    for waves in (1, 2, 3, 8, 13):
-        nslot = min(8, waves)
+    for waves, resident in ((1, 1), (8, 1), (8, 3), (13, 2), (13, 13), (64, 5)):
         for _ in range(3):
-            fin = _drain_with_slots(order, deps_of, waves, nslot, rng)
-            assert fin is not None, "deadlock with %d waves, %d slots" % (waves, nslot)
+            fin = _drain(order, deps_of, waves, resident, rng)
+            assert fin is not None, "deadlock with %d waves, %d resident" % (waves, resident)
             assert sorted(fin) == list(range(len(order)))
+
+
+def test_ticket_order_is_what_makes_it_safe():
+    """The model detects a deadlock when the order breaks the dependencies:
+    with the tickets of a chunk and a chunk it reads swapped, one resident
+    wave waits forever (the kernels' poll bound turns this into a fault)."""
+    s = pmg.Solver(2, 3, 40, device=-1)
+    S = s.export_schedule(0)
+    order = [int(q) for q in S["order"]]
+    deps_of = {q: [int(d) for d in S["deps"][S["wptr"][q]:S["wptr"][q + 1]]] for q in range(len(order))}
+    pos = {q: t for t, q in enumerate(order)}
+    q = next(q for q in order if deps_of[q])
+    d = deps_of[q][0]
+    bad = list(order)
+    bad[pos[q]], bad[pos[d]] = d, q
+    assert _drain(bad, deps_of, 4, 1, np.random.default_rng(0)) is None
