@@ -52,7 +52,7 @@ typedef enum {
 } pmg_status;
 
 enum { PMG_GEOM_BOX = 0, PMG_GEOM_QUARTER_ANNULUS = 1 };
-enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1 };
+enum { PMG_RHS_SINE = 0, PMG_RHS_ANNULUS = 1, PMG_RHS_CALLBACK = 2 };
 enum { PMG_PDE_POISSON = 0, PMG_PDE_CDR = 1 };
 enum { PMG_MASS_LUMPED = 0, PMG_MASS_CONSISTENT = 1 };
 enum { PMG_PROJ_DIRECT = 0, PMG_PROJ_INDIRECT = 1 };
@@ -76,7 +76,20 @@ enum { PMG_ORDER_NATURAL = 0, PMG_ORDER_NESTED_DISSECTION = 1 };
  *   rhs_kind PMG_RHS_SINE: f = pi^2 (sum_a k_a^2) prod_a sin(k_a pi x_a),
  *     k = freq[0..dim-1] (manufactured u = prod sin(k_a pi x_a));
  *   rhs_kind PMG_RHS_ANNULUS: f = -Lap u for benchmark 1's
- *     u = -(x^2+y^2-1)(x^2+y^2-4) x y^2. */
+ *     u = -(x^2+y^2-1)(x^2+y^2-4) x y^2;
+ *   rhs_kind PMG_RHS_CALLBACK: f is the caller's function `f` (any pde and
+ *     geometry); the load vector f_i = int f Phi_i is integrated element by
+ *     element with (p+1)^dim Gauss points per element through the geometry
+ *     map, f evaluated at the physical points.
+ * Knot vectors (Section 2, "B-spline basis functions": the knot vector Xi of
+ * each direction): knots[a] may point to the caller's knot vector of
+ * direction a, length n_elem + 2 degree + 1 (host memory, read during the
+ * call only), or be NULL for the open uniform one.  The solve phase is built
+ * for the paper's meshes, so a given vector must be that one: degree + 1
+ * zeros, the interior knots i / n_elem (to 1e-12), degree + 1 ones; any
+ * other vector (graded, periodic, repeated interior knots) is EINVAL with a
+ * message saying which knot differs. */
+typedef double (*pmg_fn)(const double *x, void *ctx); /* f at the physical point x[0..dim-1] */
 typedef struct {
   int32_t dim;      /* 2 or 3 */
   int32_t degree;   /* p >= 1 (polynomial degree, C^{p-1} splines) */
@@ -85,6 +98,10 @@ typedef struct {
   int32_t rhs_kind; /* PMG_RHS_* */
   int32_t freq[3];  /* sine frequencies (>= 1) */
   int32_t pde;      /* PMG_PDE_* (0: Poisson) */
+  const double *knots[3]; /* per direction: NULL or the open uniform knot vector (see above) */
+  pmg_fn f;         /* rhs_kind PMG_RHS_CALLBACK: called on the calling thread during
+                       pmg_setup / pmg_server_submit only, one point at a time */
+  void *f_ctx;      /* passed to f unchanged */
 } pmg_problem;
 
 /* Solver options.  Defaults (pmg_default_options) are the paper's constants
@@ -179,12 +196,27 @@ pmg_status pmg_default_options(pmg_options *o);
 /* Setup (timed separately, not the hot path): host assembly of A_p, f_p,
  * the lumped masses M_p^L and M_1^L, the transfer matrix P_1^p (Section 3,
  * "Prolongation and restriction"), the rediscretised degree-1 hierarchy
- * ("Coarse grid operator"), ILUT(tau, m) of A_p in the natural order
- * ("Smoother"), the triangular-solve schedule, then upload to device
+ * ("Coarse grid operator"), ILUT(tau, m) of P A_p P^T with P the ordering of
+ * o->ordering, nested dissection by default ("Smoother"), the
+ * triangular-solve schedule, then upload to device
  * `o->device`.  With o->device == -1 nothing touches a GPU and only
  * pmg_get_info / pmg_export work.  o may be NULL (defaults).
  * Errors: EINVAL (bad problem/options), ENOMEM, EZEROPIVOT, EDEVICE. */
 pmg_status pmg_setup(const pmg_problem *prob, const pmg_options *o, pmg_handle *out);
+
+/* Operator injection (test hook): as pmg_setup, but the degree-p operator
+ * A_{h,p} is the caller's n x n matrix instead of the assembled one, given in
+ * host CSR (rp: n + 1 int64 row pointers from 0; ci: int32 columns, strictly
+ * increasing within each row; v: values), copied during the call.  The ILUT
+ * factors of the smoother are computed from it (Section 3, "Smoother"); the
+ * transfers, the degree-1 hierarchy and the load vector still come from
+ * prob.  n must equal the problem's number of unknowns.  Any sparsity is
+ * accepted (entries outside the B-spline coupling pattern make the residual
+ * use CSR).  Drives the solver into the branches of its status codes, e.g.
+ * PMG_EZEROPIVOT for an operator with an empty row, PMG_EDIVERGED for -A.
+ * Errors: as pmg_setup, and EINVAL for a wrong size or malformed CSR. */
+pmg_status pmg_setup_from_csr(const pmg_problem *prob, int64_t n, const int64_t *rp, const int32_t *ci,
+                              const double *v, const pmg_options *o, pmg_handle *out);
 
 /* Releases every resource of h (device memory included).  NULL is a no-op. */
 pmg_status pmg_destroy(pmg_handle h);

@@ -46,7 +46,7 @@ class _Opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("fill", C.c_double), ("limit_mode", C.c_int),
                 ("coarse_cycles", C.c_int), ("gs_variant", C.c_int), ("coarse_min", C.c_int),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("ordering", C.c_int), ("nd_leaf", C.c_int),
-                ("mass_transfer", C.c_int), ("projection", C.c_int)]
+                ("mass_transfer", C.c_int), ("projection", C.c_int), ("diverge", C.c_double)]
 
 
 _lib = None
@@ -84,6 +84,7 @@ def lib():
         L.orc_prolong.argtypes = [vp, dp, dp]
         L.orc_coarse.argtypes = [vp, dp, dp]
         L.orc_gs.argtypes = [vp, C.c_int, dp, dp]
+        L.orc_set_operator.argtypes = [vp, C.c_int, i64p, ip, dp]
         L.orc_gauss.argtypes = [C.c_int, dp, dp]
         L.orc_knots.argtypes = [C.c_int, C.c_int, dp]
         L.orc_basis.argtypes = [dp, C.c_int, C.c_int, C.c_double, dp, dp]
@@ -124,11 +125,12 @@ class Options:
     nd_leaf: int = 8
     mass_transfer: int = 0   # 0: lumped masses in the transfers, 1: consistent (App. B)
     projection: int = 0      # 0: direct p -> 1, 1: indirect p -> p-1 -> ... -> 1 (App. A)
+    diverge: float = 1e10    # Section 5: diverged once the relative residual exceeds this
 
     def c(self):
         return _Opts(self.tau, self.fill, self.limit_mode, self.coarse_cycles, self.gs_variant,
                      self.coarse_min, self.nu1, self.nu2, self.ordering, self.nd_leaf, self.mass_transfer,
-                     self.projection)
+                     self.projection, self.diverge)
 
 
 # ---------------------------------------------------------------- primitives
@@ -305,6 +307,20 @@ class Oracle:
     def chol(self):
         nc = self.level_n[self.nlev - 1]
         return self._vec(V_CHOL, nc * nc).reshape(nc, nc)
+
+    def set_operator(self, A):
+        """Replaces A_p by A (n x n) and refactors the smoother from it (test
+        hook for the failure branches); returns (status, bad_row)."""
+        A = sp.csr_matrix(A)
+        A.sort_indices()
+        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+        v = np.ascontiguousarray(A.data, dtype=np.float64)
+        st = lib().orc_set_operator(self._h, self.n, _i64p(rp), _ip(ci), _dp(v))
+        info = np.zeros(32, dtype=np.int64)
+        lib().orc_info(self._h, _i64p(info))
+        self.status = st
+        return st, int(info[8])
 
     # solve phase
     def residual(self, b, x):

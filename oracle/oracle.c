@@ -843,6 +843,8 @@ typedef struct {
   int ordering, nd_leaf;
   int mass_transfer; /* 0: lumped masses in the transfers (Section 3), 1: consistent (App. B) */
   int projection;    /* 0: direct p -> 1 (Section 3), 1: indirect p -> p-1 -> ... -> 1 (App. A) */
+  double diverge;    /* a solve has diverged once its relative residual exceeds this at the
+                        end of a V-cycle (Section 5: 1e10) */
 } orc_opts;
 
 typedef struct {
@@ -886,6 +888,7 @@ void orc_default_opts(orc_opts *o) {
   o->nd_leaf = 8;
   o->mass_transfer = 0; /* Section 3: lumped */
   o->projection = 0;    /* Section 3: direct projection to p = 1 */
+  o->diverge = 1e10;    /* Section 5: diverged above 1e10 */
 }
 
 static int dense_cholesky(const ocsr *A, double **out) {
@@ -1080,7 +1083,8 @@ static int permute_sym(const ocsr *A, const int *perm, ocsr *B) {
  *   A_{2^k h, 1}    rediscretised degree-1 operators (Section 3, "Coarse
  *                   grid operator"), 2^d Gauss points, mesh halved until
  *                   n_el <= coarse_min (or odd), direct solve there;
- *   L, U            ILUT(tau, m) of A_p in the natural order.
+ *   L, U            ILUT(tau, m) of P A_p P^T, P the ordering of the
+ *                   options (nested dissection over grid lines by default).
  * stage_mask bit 0 skips ILUT (assembly-only use in tests). */
 orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *freq, const orc_opts *o,
                 int stage_mask, int *status) {
@@ -1167,6 +1171,35 @@ orc *orc_create(int dim, int p, int nel, int geom, int rhs, int pde, const int *
     s->status = rc;
   }
   return s;
+}
+
+/* Replaces A_p by the caller's n x n matrix (CSR, columns sorted within each
+ * row) and recomputes the smoother's ILUT factors from it in the same
+ * ordering; transfers, masses, the degree-1 hierarchy and f are kept.  Used
+ * by the tests to drive the solver into its failure branches (divergence,
+ * zero pivots).  Returns the ILUT status (bad_row is recorded). */
+int orc_set_operator(orc *s, int n, const int64_t *rp, const int *ci, const double *v) {
+  if (n != s->n) return ORC_EINVAL;
+  csr_free(&s->A);
+  csr_free(&s->L);
+  csr_free(&s->U);
+  int64_t nnz = rp[n];
+  s->A.nrows = s->A.ncols = n;
+  s->A.nnz = nnz;
+  s->A.rp = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  s->A.ci = malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+  s->A.v = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  memcpy(s->A.rp, rp, sizeof(int64_t) * ((size_t)n + 1));
+  memcpy(s->A.ci, ci, sizeof(int) * (size_t)nnz);
+  memcpy(s->A.v, v, sizeof(double) * (size_t)nnz);
+  s->bad_row = -1;
+  ocsr Ap = {0};
+  permute_sym(&s->A, s->perm, &Ap);
+  int rc = orc_ilut_raw(s->n, Ap.rp, Ap.ci, Ap.v, s->o.tau, s->o.fill, s->o.limit_mode, &s->L, &s->U,
+                        &s->bad_row);
+  csr_free(&Ap);
+  s->status = rc;
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1354,7 +1387,8 @@ void orc_vcycle(orc *s, const double *b, double *x, double *r) {
 
 /* Stand-alone solver (Section 5, experimental set-up): V-cycles until the
  * 2-norm of the residual has dropped by tol relative to the initial one;
- * diverged once it exceeds 1e10 times the initial one.  hist[k] receives
+ * diverged once, at the end of a V-cycle, it exceeds o.diverge (1e10) times
+ * the initial one (or is not finite).  hist[k] receives
  * ||r_k|| / ||r_0|| for k = 0..iters (length maxit + 1). */
 int orc_solve(orc *s, const double *b, double *x, double tol, int maxit, double *hist, int *iters) {
   double *r = s->r;
@@ -1369,7 +1403,7 @@ int orc_solve(orc *s, const double *b, double *x, double tol, int maxit, double 
     double rel = norm2(r, s->n) / r0;
     *iters = it;
     if (hist) hist[it] = rel;
-    if (!isfinite(rel) || rel > 1e10) return ORC_EDIVERGED;
+    if (!isfinite(rel) || rel > s->o.diverge) return ORC_EDIVERGED;
     if (rel <= tol) return ORC_OK;
   }
   return ORC_EMAXIT;
@@ -1456,7 +1490,7 @@ int orc_bicgstab(orc *s, const double *b, double *x, double tol, int maxit, int 
     double rel = norm2(r, n) / r0;
     *iters = it;
     if (hist) hist[it] = rel;
-    if (!isfinite(rel) || rel > 1e10) {
+    if (!isfinite(rel) || rel > s->o.diverge) {
       rc = ORC_EDIVERGED;
       break;
     }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpmg.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EZEROPIVOT, EDIVERGED, EMAXIT, ENAN, EBUDGET = range(9)
 GEOM_BOX, GEOM_QUARTER_ANNULUS = 0, 1
-RHS_SINE, RHS_ANNULUS = 0, 1
+RHS_SINE, RHS_ANNULUS, RHS_CALLBACK = 0, 1, 2
 PDE_POISSON, PDE_CDR = 0, 1
 MASS_LUMPED, MASS_CONSISTENT = 0, 1
 PROJ_DIRECT, PROJ_INDIRECT = 0, 1
@@ -37,10 +37,14 @@ class PmgError(RuntimeError):
         self.status = status
 
 
+# f(x, ctx) at a physical point x[0..dim-1] (pmg_fn)
+FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)
+
+
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("n_elem", C.c_int32),
                 ("geometry", C.c_int32), ("rhs_kind", C.c_int32), ("freq", C.c_int32 * 3),
-                ("pde", C.c_int32)]
+                ("pde", C.c_int32), ("knots", C.POINTER(C.c_double) * 3), ("f", FN), ("f_ctx", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -103,6 +107,8 @@ _VP, _DP, _I64P, _I32P = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
 SIGNATURES = {
     "pmg_default_options": (C.c_int, [C.POINTER(Options)]),
     "pmg_setup": (C.c_int, [C.POINTER(Problem), C.POINTER(Options), C.POINTER(_VP)]),
+    "pmg_setup_from_csr": (C.c_int, [C.POINTER(Problem), C.c_int64, _I64P, _I32P, _DP, C.POINTER(Options),
+                                     C.POINTER(_VP)]),
     "pmg_destroy": (C.c_int, [_VP]),
     "pmg_rhs": (C.c_int, [_VP, _VP, _VP]),
     "pmg_residual": (C.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
@@ -194,20 +200,52 @@ def default_options(**kw) -> Options:
 
 
 def make_problem(dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1),
-                 pde=0):
+                 pde=0, knots=None, f=None):
+    """pmg_problem.  knots: None or a sequence of per-direction knot vectors
+    (None entries: the open uniform one); f: a Python callable f(x) -> float
+    on physical points (sets rhs_kind RHS_CALLBACK).  The returned structure
+    keeps the arrays and the callback alive in its _keep attribute."""
     fr = list(freq) + [1] * (3 - len(freq))
-    return Problem(dim, degree, n_elem, geometry, rhs_kind, (C.c_int32 * 3)(*fr), pde)
+    pr = Problem(dim, degree, n_elem, geometry, rhs_kind, (C.c_int32 * 3)(*fr), pde)
+    keep = []
+    if knots is not None:
+        for a, t in enumerate(knots):
+            if t is None:
+                continue
+            arr = np.ascontiguousarray(t, dtype=np.float64)
+            keep.append(arr)
+            pr.knots[a] = arr.ctypes.data_as(_DP)
+    if f is not None:
+        cb = FN(lambda x, ctx: float(f(x[:dim])))
+        keep.append(cb)
+        pr.f = cb
+        pr.rhs_kind = RHS_CALLBACK
+    pr._keep = keep
+    return pr
 
 
 class Solver:
     """One set-up problem (pmg_setup handle) with the solve-phase entry points."""
 
     def __init__(self, dim=2, degree=2, n_elem=16, geometry=GEOM_BOX, rhs_kind=RHS_SINE,
-                 freq=(1, 1, 1), pde=0, **opts):
-        self.problem = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq, pde)
+                 freq=(1, 1, 1), pde=0, knots=None, f=None, operator=None, **opts):
+        """operator: None, or a scipy sparse matrix that replaces the assembled
+        A_p (pmg_setup_from_csr, test hook)."""
+        self.problem = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq, pde, knots, f)
         self.options = default_options(**opts)
         h = C.c_void_p()
-        _check(lib().pmg_setup(C.byref(self.problem), C.byref(self.options), C.byref(h)))
+        if operator is None:
+            _check(lib().pmg_setup(C.byref(self.problem), C.byref(self.options), C.byref(h)))
+        else:
+            import scipy.sparse as sp
+            A = sp.csr_matrix(operator)
+            A.sort_indices()
+            rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+            ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+            v = np.ascontiguousarray(A.data, dtype=np.float64)
+            _check(lib().pmg_setup_from_csr(C.byref(self.problem), A.shape[0], rp.ctypes.data_as(_I64P),
+                                            ci.ctypes.data_as(_I32P), v.ctypes.data_as(_DP),
+                                            C.byref(self.options), C.byref(h)))
         self._h = h
         self.info = self.get_info()
         self.n, self.n1 = int(self.info.n), int(self.info.n1)
@@ -371,9 +409,11 @@ class Server:
         return lib().pmg_server_prepare(self._h, C.byref(pr))
 
     def submit(self, dim, degree, n_elem, geometry=GEOM_BOX, rhs_kind=RHS_SINE, freq=(1, 1, 1), b=None,
-               pde=0):
-        """Queues a solve; returns (status, ticket)."""
-        pr = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq, pde)
+               pde=0, f=None):
+        """Queues a solve (b: host right-hand side, or f: a callback whose load
+        vector is computed at submit time, or neither: rhs_kind); returns
+        (status, ticket)."""
+        pr = make_problem(dim, degree, n_elem, geometry, rhs_kind, freq, pde, f=f)
         t = C.c_int64(-1)
         bp = None
         if b is not None:

@@ -1028,6 +1028,12 @@ void vcycle32(pmg_handle h, Workspace& ws, hipStream_t st) {
   }
 }
 
+
+}  // namespace
+
+// ----------------------------------------------------------- shared internals
+namespace pmgdev {
+
 bool valid_problem(const pmg_problem* p, std::string& msg) {
   if (!p) { msg = "problem is NULL"; return false; }
   if (p->dim != 2 && p->dim != 3) { msg = "dim must be 2 or 3"; return false; }
@@ -1035,13 +1041,33 @@ bool valid_problem(const pmg_problem* p, std::string& msg) {
   if (p->n_elem < 2) { msg = "n_elem must be >= 2"; return false; }
   if (p->geometry != PMG_GEOM_BOX && p->geometry != PMG_GEOM_QUARTER_ANNULUS) { msg = "unknown geometry"; return false; }
   if (p->geometry == PMG_GEOM_QUARTER_ANNULUS && p->dim != 2) { msg = "the quarter annulus is 2-D"; return false; }
-  if (p->rhs_kind != PMG_RHS_SINE && p->rhs_kind != PMG_RHS_ANNULUS) { msg = "unknown rhs_kind"; return false; }
+  if (p->rhs_kind != PMG_RHS_SINE && p->rhs_kind != PMG_RHS_ANNULUS && p->rhs_kind != PMG_RHS_CALLBACK) {
+    msg = "unknown rhs_kind";
+    return false;
+  }
+  if (p->rhs_kind == PMG_RHS_CALLBACK && !p->f) { msg = "rhs_kind PMG_RHS_CALLBACK needs f"; return false; }
   if (p->rhs_kind == PMG_RHS_ANNULUS && p->dim != 2) { msg = "the annulus right-hand side is 2-D"; return false; }
   if (p->dim == 3 && p->geometry != PMG_GEOM_BOX) { msg = "3-D supports the unit cube only"; return false; }
   if (p->pde != PMG_PDE_POISSON && p->pde != PMG_PDE_CDR) { msg = "unknown pde"; return false; }
-  if (p->pde == PMG_PDE_CDR && (p->dim != 2 || p->geometry != PMG_GEOM_BOX || p->rhs_kind != PMG_RHS_SINE)) {
-    msg = "the CDR problem is benchmark 2: unit square with the sine right-hand side";
+  if (p->pde == PMG_PDE_CDR && (p->dim != 2 || p->geometry != PMG_GEOM_BOX || p->rhs_kind == PMG_RHS_ANNULUS)) {
+    msg = "the CDR problem is benchmark 2: unit square, sine or callback right-hand side";
     return false;
+  }
+  if (p->degree >= 1 && p->degree <= 10 && p->n_elem >= 2 && p->n_elem < (1 << 20)) {
+    const int deg = p->degree, ne = p->n_elem, nk = ne + 2 * deg + 1;
+    for (int a = 0; a < p->dim; ++a) {
+      const double* t = p->knots[a];
+      if (!t) continue;
+      for (int k = 0; k < nk; ++k) {
+        const double want = k <= deg ? 0.0 : k >= ne + deg ? 1.0 : (double)(k - deg) / ne;
+        if (!(std::fabs(t[k] - want) <= 1e-12)) {
+          msg = "knots[" + std::to_string(a) + "][" + std::to_string(k) + "] = " + std::to_string(t[k]) +
+                ": only the open uniform knot vector of degree " + std::to_string(deg) + " on " +
+                std::to_string(ne) + " elements is supported (expected " + std::to_string(want) + ")";
+          return false;
+        }
+      }
+    }
   }
   for (int a = 0; a < p->dim; ++a)
     if (p->freq[a] < 1 && p->rhs_kind == PMG_RHS_SINE) { msg = "freq must be >= 1"; return false; }
@@ -1050,10 +1076,6 @@ bool valid_problem(const pmg_problem* p, std::string& msg) {
   return true;
 }
 
-}  // namespace
-
-// ----------------------------------------------------------- shared internals
-namespace pmgdev {
 
 size_t workspace_bytes(pmg_handle h, bool mixed, bool request_vectors) {
   const pmg::HostOps& H = h->H;
@@ -1346,12 +1368,44 @@ pmg_status pmg_default_options(pmg_options* o) {
   return PMG_OK;
 }
 
+// A caller's operator (pmg_setup_from_csr) checked and copied into M.
+static pmg_status take_csr(int64_t n, int64_t want_n, const int64_t* rp, const int32_t* ci, const double* v,
+                           pmg::Csr& M) {
+  if (n != want_n) return fail(PMG_EINVAL, "operator has " + std::to_string(n) + " rows, the problem " +
+                                               std::to_string(want_n) + " unknowns");
+  if (!rp || (rp[n] > 0 && (!ci || !v)) || rp[0] != 0) return fail(PMG_EINVAL, "invalid CSR arrays");
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return fail(PMG_EINVAL, "row pointers decrease at row " + std::to_string(i));
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] < 0 || ci[k] >= n || (k > rp[i] && ci[k] <= ci[k - 1]))
+        return fail(PMG_EINVAL, "columns out of range or not increasing in row " + std::to_string(i));
+  }
+  M.nrows = M.ncols = (int)n;
+  M.rp.assign(rp, rp + n + 1);
+  M.ci.assign(ci, ci + rp[n]);
+  M.v.assign(v, v + rp[n]);
+  return PMG_OK;
+}
+
+static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, const int64_t* inj_n,
+                             const int64_t* inj_rp, const int32_t* inj_ci, const double* inj_v, pmg_handle* out);
+
 pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle* out) {
+  return setup_impl(prob, opt, nullptr, nullptr, nullptr, nullptr, out);
+}
+
+pmg_status pmg_setup_from_csr(const pmg_problem* prob, int64_t n, const int64_t* rp, const int32_t* ci,
+                              const double* v, const pmg_options* opt, pmg_handle* out) {
+  return setup_impl(prob, opt, &n, rp, ci, v, out);
+}
+
+static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, const int64_t* inj_n,
+                             const int64_t* inj_rp, const int32_t* inj_ci, const double* inj_v, pmg_handle* out) {
   pmgdev::set_error("");
   if (!out) return fail(PMG_EINVAL, "out pointer is NULL");
   *out = nullptr;
   std::string msg;
-  if (!valid_problem(prob, msg)) return fail(PMG_EINVAL, msg);
+  if (!pmgdev::valid_problem(prob, msg)) return fail(PMG_EINVAL, msg);
   pmg_options o;
   if (opt) o = *opt; else pmg_default_options(&o);
   if (o.nu1 < 0 || o.nu2 < 0 || o.coarse_cycles < 1 || o.coarse_min_elems < 1 || o.max_iter < 0 ||
@@ -1378,6 +1432,8 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   sp.geom = prob->geometry;
   sp.rhs = prob->rhs_kind;
   sp.pde = prob->pde;
+  sp.fn = prob->f;
+  sp.fn_ctx = prob->f_ctx;
   for (int a = 0; a < 3; ++a) sp.freq[a] = prob->freq[a] > 0 ? prob->freq[a] : 1;
   sp.tau = o.ilut_tau;
   sp.fill = o.ilut_fill;
@@ -1390,6 +1446,10 @@ pmg_status pmg_setup(const pmg_problem* prob, const pmg_options* opt, pmg_handle
   int rc = pmg::assemble_all(sp, h->H, msg);
   if (rc) return fail((pmg_status)rc, msg);
   pmg::HostOps& H = h->H;
+  if (inj_n) {
+    pmg_status si = take_csr(*inj_n, H.n, inj_rp, inj_ci, inj_v, H.A);
+    if (si) return si;
+  }
   {
     auto t0 = std::chrono::steady_clock::now();
     int bad = -1;

@@ -22,6 +22,8 @@ struct SetupParams {
   bool consistent_mass = false;  // also assemble the consistent mass matrices Mp, M1
   int cdeg = 1;  // degree of the coarse space of the p-transfers (p - 1: indirect projection)
   int freq[3] = {1, 1, 1};
+  double (*fn)(const double*, void*) = nullptr;  // rhs 2: f at a physical point (caller's callback)
+  void* fn_ctx = nullptr;
   double tau = 1e-12, fill = 1.0;
   int limit_mode = 0;
   int coarse_min = 8;

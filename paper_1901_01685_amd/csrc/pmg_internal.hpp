@@ -190,6 +190,9 @@ namespace pmgdev {
 // ordered after that (with st == nullptr the device is synchronised).
 pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request_vectors,
                            hipStream_t st = nullptr);
+// Checks a problem description (sizes, kinds, knot vectors, callback); false
+// with the reason in msg.
+bool valid_problem(const pmg_problem* p, std::string& msg);
 // p[0..n) = 0 on stream st
 void zero(double* p, int64_t n, hipStream_t st);
 // Bytes a workspace of h would take.

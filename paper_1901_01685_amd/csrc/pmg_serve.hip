@@ -410,8 +410,10 @@ pmg_status pmg_server_prepare(pmg_server s, const pmg_problem* prob) {
 pmg_status pmg_server_submit(pmg_server s, const pmg_problem* prob, const double* b_host, int64_t* ticket) {
   if (!s || !prob || !ticket) return fail(PMG_EINVAL, "NULL argument");
   *ticket = -1;
-  if (prob->dim < 2 || prob->dim > 3 || prob->degree < 1 || prob->n_elem < 2)
-    return fail(PMG_EINVAL, "invalid problem");
+  {
+    std::string msg;
+    if (!pmgdev::valid_problem(prob, msg)) return fail(PMG_EINVAL, msg);
+  }
   const double submit_t = s->now();
   auto req = std::make_shared<Request>();
   req->prob = *prob;
@@ -442,6 +444,8 @@ pmg_status pmg_server_submit(pmg_server s, const pmg_problem* prob, const double
     sp.geom = prob->geometry;
     sp.rhs = prob->rhs_kind;
     sp.pde = prob->pde;
+    sp.fn = prob->f;
+    sp.fn_ctx = prob->f_ctx;
     for (int a = 0; a < 3; ++a) sp.freq[a] = prob->freq[a] > 0 ? prob->freq[a] : 1;
     std::string msg;
     if (pmg::load_vector(sp, req->b, msg)) {

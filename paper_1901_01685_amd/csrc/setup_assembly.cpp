@@ -40,36 +40,51 @@ static void parallel_for(int64_t n, int threads, const std::function<void(int64_
 }
 
 // --------------------------------------------------------------- quadrature
-// Roots of P_n by Newton iteration from cos(pi (k - 1/4) / (n + 1/2)); the
-// Legendre values come from Bonnet's recursion; w = 2 / ((1 - x^2) P_n'^2).
+// Golub-Welsch: the nodes of the n-point Gauss-Legendre rule are the
+// eigenvalues of the symmetric tridiagonal Jacobi matrix of the Legendre
+// recurrence (zero diagonal, off-diagonal b_k = k / sqrt(4 k^2 - 1)); the
+// weight of a node is 2 v_0^2 / |v|^2 for its eigenvector v.  Eigenvalues
+// are found by bisection on Sturm counts (the number of negative pivots of
+// J - x I), eigenvector components by the matrix's own three-term
+// recurrence from v_0 = 1, so w = 2 / sum_k v_k^2.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
-  for (int k = 1; k <= n; ++k) {
-    double z = std::cos(M_PI * (k - 0.25) / (n + 0.5));
-    double pn = 0, dpn = 0;
-    for (int it = 0; it < 100; ++it) {
-      double a = 1.0, b = 0.0;  // P_j, P_{j-1}
-      for (int j = 1; j <= n; ++j) {
-        double c = ((2 * j - 1) * z * a - (j - 1) * b) / j;
-        b = a;
-        a = c;
-      }
-      pn = a;
-      dpn = n * (z * a - b) / (z * z - 1.0);
-      double step = pn / dpn;
-      z -= step;
-      if (std::fabs(step) < 1e-16) break;
+  std::vector<double> b2(n > 1 ? n - 1 : 1), bk(n > 1 ? n - 1 : 1);
+  for (int k = 1; k < n; ++k) {
+    bk[k - 1] = k / std::sqrt(4.0 * k * k - 1.0);
+    b2[k - 1] = bk[k - 1] * bk[k - 1];
+  }
+  // eigenvalues of J below t
+  auto below = [&](double t) {
+    int cnt = 0;
+    double q = -t;
+    if (q < 0) ++cnt;
+    for (int k = 1; k < n; ++k) {
+      if (q == 0.0) q = 1e-300;
+      q = -t - b2[k - 1] / q;
+      if (q < 0) ++cnt;
     }
-    double a = 1.0, b = 0.0;
-    for (int j = 1; j <= n; ++j) {
-      double c = ((2 * j - 1) * z * a - (j - 1) * b) / j;
-      b = a;
-      a = c;
+    return cnt;
+  };
+  for (int i = 0; i < n; ++i) {
+    // the (i+1)-th smallest eigenvalue lies in [-1, 1]
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (below(mid) > i) hi = mid; else lo = mid;
     }
-    dpn = n * (z * a - b) / (z * z - 1.0);
-    x[n - k] = z;
-    w[n - k] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+    const double t = 0.5 * (lo + hi);
+    double vm = 0.0, v = 1.0, ss = 1.0;
+    for (int k = 1; k < n; ++k) {
+      const double vn = (t * v - (k > 1 ? bk[k - 2] * vm : 0.0)) / bk[k - 1];
+      vm = v;
+      v = vn;
+      ss += v * v;
+    }
+    x[i] = t;
+    w[i] = 2.0 / ss;
   }
 }
 
@@ -351,31 +366,33 @@ static void cdr_load(int p, int nel, const int* k, std::vector<double>& f) {
 
 // ------------------------------------------------------------------ annulus
 // F(xi, eta) = (1 + xi) C(eta), C(eta) the rational quadratic arc from (1,0)
-// to (0,1) with middle control point (1,1) and weight sqrt(2)/2.
+// to (0,1) with middle control point (1,1) and weight w = sqrt(2)/2.  The arc
+// lies on the unit circle, so C = (cos th, sin th) with th(eta) the angle of
+// its homogeneous point (N_x, N_y) = ((1-eta)^2 + 2 w eta (1-eta),
+// 2 w eta (1-eta) + eta^2); the angle's derivative is the cross product
+// (N_x N_y' - N_y N_x') / (N_x^2 + N_y^2), and in polar form the Jacobian of
+// F has determinant (1 + xi) th'.
 struct GeoPt {
   double x, y, det, ji[2][2];  // ji = J^{-1}
 };
 
 static GeoPt annulus_map(double xi, double eta) {
-  const double wm = std::sqrt(2.0) / 2.0;
-  double om = 1.0 - eta;
-  double b0 = om * om, b1 = 2.0 * eta * om, b2 = eta * eta;
-  double d0 = -2.0 * om, d1 = 2.0 - 4.0 * eta, d2 = 2.0 * eta;
-  double W = b0 + wm * b1 + b2, dW = d0 + wm * d1 + d2;
-  double nx = b0 + wm * b1, dnx = d0 + wm * d1;
-  double ny = wm * b1 + b2, dny = wm * d1 + d2;
-  double cx = nx / W, cy = ny / W;
-  double dcx = (dnx * W - nx * dW) / (W * W), dcy = (dny * W - ny * dW) / (W * W);
-  double r = 1.0 + xi;
+  const double wm = std::sqrt(0.5);
+  const double om = 1.0 - eta;
+  const double nx = om * om + 2.0 * wm * eta * om, ny = 2.0 * wm * eta * om + eta * eta;
+  const double dnx = -2.0 * om + 2.0 * wm * (1.0 - 2.0 * eta), dny = 2.0 * wm * (1.0 - 2.0 * eta) + 2.0 * eta;
+  const double th = std::atan2(ny, nx);
+  const double dth = (nx * dny - ny * dnx) / (nx * nx + ny * ny);
+  const double c = std::cos(th), sn = std::sin(th), r = 1.0 + xi;
   GeoPt g;
-  g.x = r * cx;
-  g.y = r * cy;
-  double J00 = cx, J01 = r * dcx, J10 = cy, J11 = r * dcy;
-  g.det = J00 * J11 - J01 * J10;
-  g.ji[0][0] = J11 / g.det;
-  g.ji[0][1] = -J01 / g.det;
-  g.ji[1][0] = -J10 / g.det;
-  g.ji[1][1] = J00 / g.det;
+  g.x = r * c;
+  g.y = r * sn;
+  // J = [[c, -r sn th'], [sn, r c th']] (columns d/dxi, d/deta)
+  g.det = r * dth;
+  g.ji[0][0] = c;
+  g.ji[0][1] = sn;
+  g.ji[1][0] = -sn / (r * dth);
+  g.ji[1][1] = c / (r * dth);
   return g;
 }
 
@@ -495,8 +512,15 @@ static Csr element_assemble_2d(int geom, int kind, int pr, int pc, int nel, int 
   return M;
 }
 
+// f at a physical point: the built-in right-hand sides or the caller's callback.
+static double rhs_value(const SetupParams& sp, int dim, const double* X) {
+  if (sp.rhs == 2) return sp.fn(X, sp.fn_ctx);
+  if (sp.rhs == 1) return annulus_f(X[0], X[1]);
+  return sine_f(dim, sp.freq, X);
+}
+
 // Load vector and lumped mass (int Phi_i) by an element loop in 2-D.
-static void element_vectors_2d(int geom, int rhs, const int* k, int p, int nel, int nq,
+static void element_vectors_2d(int geom, const SetupParams& sp, int p, int nel, int nq,
                                std::vector<double>* f, std::vector<double>* ml) {
   Table1D T = make_table(p, nel, nq);
   int n1 = nel + p - 2;
@@ -516,7 +540,7 @@ static void element_vectors_2d(int geom, int rhs, const int* k, int p, int nel, 
             X[1] = g.y;
           }
           double fx = 0.0;
-          if (f) fx = rhs == 1 ? annulus_f(X[0], X[1]) : sine_f(2, k, X);
+          if (f) fx = rhs_value(sp, 2, X);
           for (int ay = 0; ay <= p; ++ay) {
             int fy = ey + ay;
             if (fy == 0 || fy == nel + p - 1) continue;
@@ -686,9 +710,50 @@ static bool dense_lu_inverse(const Csr& A, std::vector<double>& inv) {
   return true;
 }
 
+// Load vector of a callback right-hand side on the unit cube by an element
+// loop (one thread: the callback need not be thread-safe).
+static void element_load_3d(const SetupParams& sp, int p, int nel, int nq, std::vector<double>& f) {
+  Table1D T = make_table(p, nel, nq);
+  const int n1 = nel + p - 2;
+  f.assign((size_t)n1 * n1 * n1, 0.0);
+  for (int ez = 0; ez < nel; ++ez)
+    for (int ey = 0; ey < nel; ++ey)
+      for (int ex = 0; ex < nel; ++ex)
+        for (int qz = 0; qz < nq; ++qz)
+          for (int qy = 0; qy < nq; ++qy)
+            for (int qx = 0; qx < nq; ++qx) {
+              const double X[3] = {T.u[(size_t)ex * nq + qx], T.u[(size_t)ey * nq + qy], T.u[(size_t)ez * nq + qz]};
+              const double wq = T.wt[(size_t)ex * nq + qx] * T.wt[(size_t)ey * nq + qy] * T.wt[(size_t)ez * nq + qz];
+              const double fw = wq * rhs_value(sp, 3, X);
+              for (int az = 0; az <= p; ++az) {
+                const int fz = ez + az;
+                if (fz == 0 || fz == nel + p - 1) continue;
+                for (int ay = 0; ay <= p; ++ay) {
+                  const int fy = ey + ay;
+                  if (fy == 0 || fy == nel + p - 1) continue;
+                  const double vyz = T.V(ey, qy, ay) * T.V(ez, qz, az);
+                  for (int ax = 0; ax <= p; ++ax) {
+                    const int fxi = ex + ax;
+                    if (fxi == 0 || fxi == nel + p - 1) continue;
+                    f[(fxi - 1) + (size_t)n1 * ((fy - 1) + (size_t)n1 * (fz - 1))] += fw * (T.V(ex, qx, ax) * vyz);
+                  }
+                }
+              }
+            }
+}
+
 int load_vector(const SetupParams& sp, std::vector<double>& f, std::string& msg) {
   const int dim = sp.dim, p = sp.p, nel = sp.nel;
   const int64_t n = ipow(nel + p - 2, dim);
+  if (sp.rhs == 2) {
+    if (!sp.fn) {
+      msg = "the callback right-hand side needs f";
+      return 1;
+    }
+    if (dim == 2) element_vectors_2d(sp.geom, sp, p, nel, p + 1, &f, nullptr);
+    else element_load_3d(sp, p, nel, p + 1, f);
+    return 0;
+  }
   if (sp.pde == 1) {
     cdr_load(p, nel, sp.freq, f);
     return 0;
@@ -717,7 +782,7 @@ int load_vector(const SetupParams& sp, std::vector<double>& f, std::string& msg)
     msg = "this right-hand side is two-dimensional";
     return 1;
   }
-  element_vectors_2d(sp.geom, sp.rhs, sp.freq, p, nel, p + 1, &f, nullptr);
+  element_vectors_2d(sp.geom, sp, p, nel, p + 1, &f, nullptr);
   return 0;
 }
 
@@ -776,6 +841,10 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
       H.f[r] = M_PI * M_PI * ks * s;
     }
     if (sp.pde == 1) cdr_load(p, nel, sp.freq, H.f);
+    if (sp.rhs == 2) {
+      const int rc = load_vector(sp, H.f, msg);
+      if (rc) return rc;
+    }
     for (int64_t r = 0; r < H.n1; ++r) {
       int64_t t = r;
       double m = 1.0;
@@ -792,8 +861,8 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
     }
     H.A = element_assemble_2d(1, 0, p, p, nel, p + 1, th);
     H.P = element_assemble_2d(1, 1, p, cdeg, nel, p + 1, th);
-    element_vectors_2d(1, sp.rhs, sp.freq, p, nel, p + 1, &H.f, &H.mlp);
-    element_vectors_2d(1, sp.rhs, sp.freq, cdeg, nel, cdeg + 1, nullptr, &H.ml1);
+    element_vectors_2d(1, sp, p, nel, p + 1, &H.f, &H.mlp);
+    element_vectors_2d(1, sp, cdeg, nel, cdeg + 1, nullptr, &H.ml1);
   }
   H.R = transpose(H.P);
   if (sp.consistent_mass) {

@@ -275,3 +275,53 @@ def test_hcycle_error_propagator_is_the_figure1_composition(dim, nel):
     ref = (np.eye(n) - E @ E) @ np.linalg.solve(A[0].toarray(), r1)
     got = o.coarse(r1)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _shifted(o, c):
+    """A_p - c lambda_min(A_p) I: indefinite for c > 1, so the positive
+    definite degree-1 coarse correction no longer matches it and the
+    iteration can grow (used to reach the divergence branch)."""
+    import scipy.sparse.linalg as sla
+    A = o.A()
+    lmin = sla.eigsh(A, k=1, sigma=0, which="LM")[0][0]
+    return (A - c * lmin * sp.eye(A.shape[0])).tocsr()
+
+
+def test_divergence_criterion_of_section5():
+    """Section 5: a solve has diverged when the relative residual exceeds
+    1e10 at the end of a V-cycle.  On an operator for which the iteration
+    grows, the oracle's solve must stop at the first V-cycle whose relative
+    residual, recomputed here with scipy from the iterates of single
+    V-cycles, exceeds 1e10, and not earlier or later; its history must be
+    that of the single cycles; and with the ratio set just below the first
+    cycle's residual it stops after one cycle (strictly greater: equal does
+    not stop)."""
+    o = O.Oracle(2, 3, 32)
+    B = _shifted(o, 2.0)
+    assert o.set_operator(B)[0] == 0
+    f = o.f()
+    r0 = np.linalg.norm(f)
+    x = np.zeros(o.n)
+    hist = []
+    for _ in range(100):
+        x, _ = o.vcycle(f, x)
+        hist.append(np.linalg.norm(f - B @ x) / r0)
+        if hist[-1] > 1e10:
+            break
+    K = len(hist)
+    assert 10 < K < 100 and hist[-1] > 1e10 and max(hist[:-1]) <= 1e10, (K, hist[-3:])
+    _, st, it, h = o.solve(f, tol=1e-8)
+    assert st == O.EDIVERGED and it == K, (st, it, K)
+    assert np.allclose(h[1:], hist, rtol=1e-10, atol=0)
+    # the criterion compares the relative residual, strictly, after each cycle
+    o2 = O.Oracle(2, 3, 32, opts=O.Options(diverge=hist[0]))
+    assert o2.set_operator(B)[0] == 0
+    _, st, it, h = o2.solve(f, tol=1e-8)
+    assert st == O.EDIVERGED and it == 2, (st, it)
+    o3 = O.Oracle(2, 2, 16)
+    f3 = o3.f()
+    _, st, it, h3 = o3.solve(f3, tol=1e-8)
+    assert st == 0 and it > 2
+    o4 = O.Oracle(2, 2, 16, opts=O.Options(diverge=0.999 * h3[1]))
+    _, st, it, h4 = o4.solve(f3, tol=1e-8)
+    assert st == O.EDIVERGED and it == 1 and h4[1] == h3[1]
