@@ -75,14 +75,13 @@ def _traffic(kernel_class, workload):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0):
+def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0, nel_s=128):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
     the workload: the same problem family (2-D unit square, same p) at
     h = 1/nel_s, V-cycles repeated for about budget_s seconds; reported in
     unknowns x V-cycles / second."""
     import numpy as np
     import oracle
-    nel_s = 128
     t0 = time.perf_counter()
     o = oracle.Oracle(2, p, nel_s, pde=pde)
     t_setup = time.perf_counter() - t0
@@ -98,15 +97,90 @@ def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0):
         if el >= budget_s or cycles >= 5000:
             break
     o.close()
+    model, ncpu = host_cpu()
     return {
         "value": o.n * cycles / el,
         "unit": "DOF*iter/s",
         "cores": 1,
         "kind": "oracle",
+        "host": {"cpu_model": model, "nproc": ncpu},
         "sample": (f"oracle V-cycles on the same 2-D unit-square {'CDR ' if pde else ''}p={p} problem at h=1/{nel_s} "
                    f"(n={o.n}; the timed workload is h=1/{nel_full}, n={n_full}): {cycles} cycles in "
                    f"{el:.1f} s, setup {t_setup:.1f} s excluded; single-threaded C, FP64"),
     }
+
+
+def host_cpu():
+    """CPU model and logical cores of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes (read + write counted), timed with
+    events on the copy's stream: the attainable HBM bandwidth beside the
+    8 TB/s peak."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    gbs = 2 * nbytes / t / 1e9
+    return {"GBps": round(gbs, 1), "bytes_per_copy": 2 * nbytes, "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def mixed_config4(pmg, torch, dev, reps=3):
+    """Benchmark 1 (quarter annulus, radii 1 and 2) at p = 5, h = 1/512:
+    FP32 V-cycles inside FP64 defect correction against plain FP64 V-cycles,
+    both from x = 0 to a 1e-10 relative FP64 residual, on the same operators
+    (one handle holding both precisions).  Reports ms per solve (median of
+    reps after one untimed solve), solves/s, outer steps, the final FP64
+    relative residual, and the mixed solution's relative difference from the
+    FP64 one."""
+    import numpy as np
+    t0 = time.perf_counter()
+    s = pmg.Solver(2, 5, 512, geometry=pmg.GEOM_QUARTER_ANNULUS, rhs_kind=pmg.RHS_ANNULUS,
+                   precision=pmg.FP32_IN_FP64, device=0)
+    t_setup = time.perf_counter() - t0
+    b = torch.empty(s.n, dtype=torch.float64, device=dev)
+    s.rhs(b)
+    res, xs = {}, {}
+    for name, prec in (("mixed", pmg.FP32_IN_FP64), ("fp64", pmg.FP64)):
+        s.set_precision(prec)
+        x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+        s.solve(b, x, tol=1e-10)
+        times = []
+        for _ in range(reps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, it, rel, *_ = s.solve(b, x, tol=1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+        ms = 1e3 * float(np.median(times))
+        res[name] = {"status": int(st), "outer_steps": int(it), "relres_fp64": float(rel), "ms": round(ms, 3),
+                     "solves_per_s": round(1e3 / ms, 2)}
+        xs[name] = x.clone()
+    diff = float(torch.linalg.vector_norm(xs["mixed"] - xs["fp64"]) / torch.linalg.vector_norm(xs["fp64"]))
+    out = {"workload": "2d-quarter-annulus-p5-h1/512", "unknowns": s.n, "tol": 1e-10,
+           "setup_s": round(t_setup, 1), **res, "mixed_vs_fp64_rel_diff": diff,
+           "speedup_mixed_over_fp64": round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)}
+    s.close()
+    return out
 
 
 def serve_bench(args):
@@ -243,6 +317,8 @@ def main():
     ap.add_argument("--mass", choices=("lumped", "consistent"), default="lumped",
                     help="consistent: consistent mass matrices in the transfers (Appendix B variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the benchmark-1 mixed-precision leg")
+    ap.add_argument("--no-copy", action="store_true", help="skip the device-copy bandwidth leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--serve", action="store_true", help="continuous-batching serving benchmark")
     ap.add_argument("--seed", type=int, default=0)
@@ -394,6 +470,15 @@ def main():
         "roofline": roofline,
         "solves": solves,
     }
+    s.close()
+    del b, x, r
+    torch.cuda.empty_cache()
+    if not args.no_copy:
+        out["copy_bandwidth"] = copy_bandwidth(torch, dev)
+        print(f"# device copy {out['copy_bandwidth']['GBps']} GB/s", file=sys.stderr, flush=True)
+    if not args.no_mixed and args.dim == 2 and pde == pmg.PDE_POISSON:
+        print("# benchmark 1 at p=5, h=1/512: mixed vs FP64 to 1e-10", file=sys.stderr, flush=True)
+        out["mixed_config4"] = mixed_config4(pmg, torch, dev)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.degree, args.nel, n, args.cpu_budget, pde=pde)

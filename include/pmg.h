@@ -110,7 +110,12 @@ typedef struct {
 typedef struct {
   double ilut_tau;          /* ILUT drop tolerance tau (rule 1) */
   double ilut_fill;         /* ILUT fill factor m (rule 2); <= 0: unlimited */
-  int32_t ilut_limit_mode;  /* PMG_LIMIT_PER_PART (M per L and per U) or PER_ROW */
+  int32_t ilut_limit_mode;  /* ILUT rule 2, M = floor(m nnz(A) / n): PMG_LIMIT_HALF_PER_PART
+                               (default: floor(M/2) largest in the strict lower and in the
+                               strict upper part, so at most M besides the diagonal in each
+                               row and nnz(L+U) close to nnz(A), as Section 3 states),
+                               PMG_LIMIT_PER_ROW (M largest of the whole row) or
+                               PMG_LIMIT_PER_PART (M in each part) */
   int32_t nu1, nu2;         /* pre/post ILUT smoothing steps */
   int32_t coarse_cycles;    /* h-multigrid V-cycles at p = 1 */
   int32_t coarse_min_elems; /* direct solve once n_elem <= this (or odd) */
@@ -153,6 +158,11 @@ typedef struct {
                                results since the previous such call are invalid.  A
                                correct schedule never reaches the default bound; small
                                values force the fault path (test hook). */
+  int32_t ilut_on_device;   /* 1 (default): ILUT is factored on the device (one wave per row,
+                               rows pipelined in order), with the host factorisation's
+                               arithmetic, so the factors are identical; rows too long for the
+                               kernel's working storage fall back to the host (reported in
+                               pmg_info.ilut_on_device).  0: on the host. */
 } pmg_options;
 
 typedef struct {
@@ -179,6 +189,8 @@ typedef struct {
       bytes_coarse;
   int64_t device_bytes;       /* device memory held by the handle */
   double t_assembly, t_ilut, t_upload; /* setup phase times, seconds */
+  double t_schedule;          /* triangular-solve schedules and sliced layouts (host), seconds */
+  int32_t ilut_on_device;     /* 1 if the ILUT factors were computed on the device */
 } pmg_info;
 
 /* ILUT ordering (Section 3, "Smoother": the factorisation follows a
@@ -285,6 +297,13 @@ pmg_status pmg_solve(pmg_handle h, const double *b, double *x, double tol, pmg_r
  * convergence) and a non-finite residual give PMG_EDIVERGED. */
 pmg_status pmg_bicgstab(pmg_handle h, const double *b, double *x, double tol, pmg_result *res,
                         double *hist, void *stream);
+
+/* Selects the precision of later pmg_solve calls on h: PMG_FP64 (plain FP64
+ * V-cycles) or PMG_FP32_IN_FP64 (FP32 V-cycles in FP64 defect correction).
+ * A handle set up with PMG_FP32_IN_FP64 holds both copies of its operators
+ * and may switch either way; one set up in FP64 cannot switch to mixed
+ * (EINVAL).  Lets one set of operators serve both forms of the solve. */
+pmg_status pmg_set_precision(pmg_handle h, int32_t precision);
 
 /* Sizes, DAG depths, algorithmic bytes and setup times. */
 pmg_status pmg_get_info(pmg_handle h, pmg_info *info);

@@ -782,7 +782,7 @@ int orc_ilut_raw(int n, const int64_t *rp, const int *ci, const double *v, doubl
     }
     int64_t keepL = 0, keepU = 0;
     if (mode == 0 || mode == 2) {
-      int64_t Mpart = mode == 2 ? M / 2 : M;
+      int64_t Mpart = mode == 2 && fill > 0 ? M / 2 : M;  /* fill <= 0: no limit in any mode */
       /* split into lower / upper, sort each by magnitude */
       int a = 0;
       for (int t = 0; t < nc; ++t)
@@ -878,7 +878,8 @@ typedef struct {
 void orc_default_opts(orc_opts *o) {
   o->tau = 1e-12;   /* Section 3: drop tolerance 1e-12 */
   o->fill = 1.0;    /* Section 3: fill factor m = 1 */
-  o->limit_mode = 0;
+  o->limit_mode = 2;  /* Section 3, rule 2: at most M entries besides the diagonal in each
+                         row, floor(M/2) in each part, so nnz(L+U) is close to nnz(A) */
   o->coarse_cycles = 2; /* Section 3: two h-multigrid V-cycles at p = 1 */
   o->gs_variant = 0;    /* multicolour Gauss-Seidel */
   o->coarse_min = 8;

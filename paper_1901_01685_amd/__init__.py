@@ -54,7 +54,7 @@ class Options(C.Structure):
                 ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
                 ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32),
-                ("projection", C.c_int32), ("poll_limit", C.c_int32)]
+                ("projection", C.c_int32), ("poll_limit", C.c_int32), ("ilut_on_device", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -72,7 +72,8 @@ class Info(C.Structure):
                 ("bytes_vcycle", C.c_int64), ("bytes_spmv", C.c_int64), ("bytes_trisolve_l", C.c_int64),
                 ("bytes_trisolve_u", C.c_int64), ("bytes_restrict", C.c_int64),
                 ("bytes_prolong", C.c_int64), ("bytes_coarse", C.c_int64), ("device_bytes", C.c_int64),
-                ("t_assembly", C.c_double), ("t_ilut", C.c_double), ("t_upload", C.c_double)]
+                ("t_assembly", C.c_double), ("t_ilut", C.c_double), ("t_upload", C.c_double),
+                ("t_schedule", C.c_double), ("ilut_on_device", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -123,6 +124,7 @@ SIGNATURES = {
     "pmg_vcycle": (C.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
     "pmg_solve": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(Result), _DP, _VP]),
     "pmg_get_info": (C.c_int, [_VP, C.POINTER(Info)]),
+    "pmg_set_precision": (C.c_int, [_VP, C.c_int32]),
     "pmg_export": (C.c_int, [_VP, C.c_int32, C.c_int32, _I64P, _I64P, _I32P, _DP]),
     "pmg_export_vec": (C.c_int, [_VP, C.c_int32, _DP]),
     "pmg_export_perm": (C.c_int, [_VP, _I32P]),
@@ -260,6 +262,10 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    def set_precision(self, precision):
+        _check(lib().pmg_set_precision(self._h, precision))
+        self.options.precision = precision
 
     def get_info(self) -> Info:
         i = Info()

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT, "libpmg.so")
 HOST_SRCS = ["setup_assembly.cpp", "setup_ilut.cpp"]
-DEV_SRCS = ["pmg_device.hip", "pmg_serve.hip"]
+DEV_SRCS = ["pmg_device.hip", "pmg_serve.hip", "setup_device.hip"]
 ARCH = "gfx950"
 
 

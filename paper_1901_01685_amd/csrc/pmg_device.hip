@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -341,6 +342,15 @@ pmg_status upload_mat(pmgdev::DevArena& mem, const pmg::Csr& M, DevMat& D, bool 
   }
   D.G = pick_group(D.nrows ? (double)D.nnz / D.nrows : 1.0);
   return PMG_OK;
+}
+
+// The shape of an operator whose values live in a stencil layout instead:
+// nothing is uploaded, the kernels read only the sizes.
+void describe_mat(const pmg::Csr& M, DevMat& D) {
+  D.nrows = M.nrows;
+  D.ncols = M.ncols;
+  D.nnz = M.nnz();
+  D.G = pick_group(D.nrows ? (double)D.nnz / D.nrows : 1.0);
 }
 
 // Offsets of A's stencil layout (see pmg::stencil_resid), or 0 when it is
@@ -744,19 +754,29 @@ void fill_pending(float* p, int64_t n, hipStream_t st) {
 }
 
 template <typename T>
-void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, hipStream_t st) {
+void lower_launch(pmg_handle h, const pmg::TriCtl& ctl, const T* r, T* y, hipStream_t st) {
   ProfScope ps(h, PMG_PROF_LOWER, st);
   fill_pending(y, h->H.n, st);
   const int g = tri_grid<T>(h->tl);
-  pmg::trisolve_lower<T><<<g, 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, tri_ctl(h, ws, 0));
+  pmg::trisolve_lower<T><<<g, 64, 0, st>>>(h->tl.nch, tri_dev<T>(h->tl), h->d_perm, r, y, ctl);
+}
+
+template <typename T>
+void upper_launch(pmg_handle h, const pmg::TriCtl& ctl, const T* y, T* e, T* x, hipStream_t st) {
+  ProfScope ps(h, PMG_PROF_UPPER, st);
+  fill_pending(e, h->H.n, st);
+  const int g = tri_grid<T>(h->tu);
+  pmg::trisolve_upper<T><<<g, 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x, ctl);
+}
+
+template <typename T>
+void lower_impl(pmg_handle h, Workspace& ws, const T* r, T* y, hipStream_t st) {
+  lower_launch<T>(h, tri_ctl(h, ws, 0), r, y, st);
 }
 
 template <typename T>
 void upper_impl(pmg_handle h, Workspace& ws, const T* y, T* e, T* x, hipStream_t st) {
-  ProfScope ps(h, PMG_PROF_UPPER, st);
-  fill_pending(e, h->H.n, st);
-  const int g = tri_grid<T>(h->tu);
-  pmg::trisolve_upper<T><<<g, 64, 0, st>>>(h->tu.nch, tri_dev<T>(h->tu), h->d_perm, y, e, x, tri_ctl(h, ws, 1));
+  upper_launch<T>(h, tri_ctl(h, ws, 1), y, e, x, st);
 }
 
 // x += U^{-1} L^{-1} P r (then permuted back) with work vectors y, e.
@@ -1348,7 +1368,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->ilut_tau = 1e-12;
   o->ilut_fill = 1.0;
-  o->ilut_limit_mode = PMG_LIMIT_PER_PART;
+  o->ilut_limit_mode = PMG_LIMIT_HALF_PER_PART;
   o->nu1 = 1;
   o->nu2 = 1;
   o->coarse_cycles = 2;
@@ -1365,6 +1385,8 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->tiled_gs = 1;
   o->mass_transfer = PMG_MASS_LUMPED;
   o->projection = PMG_PROJ_DIRECT;
+  o->poll_limit = 0;
+  o->ilut_on_device = 1;
   return PMG_OK;
 }
 
@@ -1455,15 +1477,34 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     int bad = -1;
     H.perm = pmg::line_ordering(prob->dim, prob->n_elem + prob->degree - 2, prob->degree, o.ordering, o.nd_leaf);
     pmg::Csr Ap = pmg::permute(H.A, H.perm, sp.threads);
-    rc = pmg::ilut_factor(Ap, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, sp.threads, H.L, H.U, bad);
+    bool factored = false;
+    int ndev = 0;
+    if (o.ilut_on_device && o.device >= 0 && hipGetDeviceCount(&ndev) == hipSuccess && o.device < ndev) {
+      // the same factors as the host factorisation, bit for bit; rows too
+      // long for the device kernel fall back to the host
+      PMG_HIP_OK(hipSetDevice(o.device));
+      std::string why;
+      const pmg_status sd = pmgdev::ilut_device(Ap, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, o.poll_limit, H.L,
+                                                H.U, bad, why);
+      if (sd == PMG_EZEROPIVOT)
+        return fail(PMG_EZEROPIVOT, "ILUT: zero or non-finite pivot in row " + std::to_string(bad));
+      if (sd != PMG_OK && sd != PMG_EINVAL) return sd;
+      factored = sd == PMG_OK;
+      h->info.ilut_on_device = factored ? 1 : 0;
+    }
+    if (!factored) {
+      rc = pmg::ilut_factor(Ap, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, sp.threads, H.L, H.U, bad);
+      if (rc) return fail(PMG_EZEROPIVOT, "ILUT: zero or non-finite pivot in row " + std::to_string(bad));
+    }
     H.t_ilut = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (rc) return fail(PMG_EZEROPIVOT, "ILUT: zero or non-finite pivot in row " + std::to_string(bad));
   }
   const int seg_len = prob->n_elem + prob->degree - 2;
   {
+    auto t0 = std::chrono::steady_clock::now();
     pmg_status bs = build_schedule(H.L, seg_len, false, h->tl);
     if (bs == PMG_OK) bs = build_schedule(H.U, seg_len, true, h->tu);
     if (bs != PMG_OK) return bs;
+    h->info.t_schedule = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   h->colors = 1 << prob->dim;
   h->partial_cap = (int)csr_grid(H.n, pick_group((double)H.A.nnz() / std::max(H.n, 1))) + 16;
@@ -1536,22 +1577,27 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     const bool mixed = o.precision == PMG_FP32_IN_FP64;
     pmgdev::DevArena& m = h->ops;
     pmg_status s;
-    if ((s = upload_mat(m, H.A, h->A, mixed))) return s;
+    // CSR copies only of the operators that have no stencil layout
+    if (h->a_stencil) describe_mat(H.A, h->A);
+    else if ((s = upload_mat(m, H.A, h->A, mixed))) return s;
     if ((s = upload_stencil(m, H, h->a_stencil, h->As, mixed))) return s;
     if ((s = upload_tri(m, h->tl, false, mixed))) return s;
     if ((s = upload_tri(m, h->tu, true, mixed))) return s;
     if ((s = size_tri_grid<double>(o.device, h->tl, h->tu))) return s;
     if (mixed && (s = size_tri_grid<float>(o.device, h->tl, h->tu))) return s;
     if (n1 > 0) {
-      if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
-      if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
+      const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
+      if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
+      if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
+      // (the consistent-mass transfers apply R and P unscaled, in CSR)
+      if (h->Rs.v && !sp.consistent_mass) describe_mat(H.R, h->R);
+      else if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
+      if (h->Ps.v && !sp.consistent_mass) describe_mat(H.P, h->P);
+      else if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
       if (sp.consistent_mass) {
         if ((s = upload_mat(m, H.Mp, h->Mp, false))) return s;
         if ((s = upload_mat(m, H.M1, h->M1, false))) return s;
       }
-      const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
-      if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
-      if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
     }
     h->A1.resize(H.nlev);
     h->Ph.resize(H.Ph.size());
@@ -1644,6 +1690,15 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
 
 pmg_status pmg_destroy(pmg_handle h) {
   delete h;
+  return PMG_OK;
+}
+
+pmg_status pmg_set_precision(pmg_handle h, int32_t precision) {
+  if (!h) return fail(PMG_EINVAL, "NULL handle");
+  if (precision != PMG_FP64 && precision != PMG_FP32_IN_FP64) return fail(PMG_EINVAL, "unknown precision");
+  if (precision == PMG_FP32_IN_FP64 && !h->ws.mixed)
+    return fail(PMG_EINVAL, "the handle was set up in FP64 only: set it up with precision PMG_FP32_IN_FP64");
+  h->opt.precision = precision;
   return PMG_OK;
 }
 

@@ -177,7 +177,7 @@ int ilut_factor(const Csr& A, double tau, double fill, int mode, int threads, Cs
           (j < i ? lo : up).push_back({j, x});
         }
         if (mode != 1) {
-          const int64_t Mp = mode == 2 ? M / 2 : M;
+          const int64_t Mp = mode == 2 && fill > 0 ? M / 2 : M;  // fill <= 0: no limit in any mode
           if ((int64_t)lo.size() > Mp) {
             std::nth_element(lo.begin(), lo.begin() + Mp, lo.end(), mag_before);
             lo.resize(Mp);

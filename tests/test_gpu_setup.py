@@ -1,0 +1,83 @@
+"""Setup on the device (ILUT(tau, m) of Section 3's smoother computed by the
+GPU kernel): the factors must be identical, bit for bit, to those of the host
+factorisation of the same permuted operator, which the host tests pin
+against the oracle.  Covers the three readings of rule 2, the nested
+dissection and natural orderings, both geometries, the cube and the
+non-symmetric benchmark-2 operator, and the zero-pivot branch."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import paper_1901_01685_amd as pmg
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(dim=2, degree=2, n_elem=16),
+    dict(dim=2, degree=5, n_elem=128),
+    dict(dim=2, degree=3, n_elem=64, geometry=pmg.GEOM_QUARTER_ANNULUS, rhs_kind=pmg.RHS_ANNULUS),
+    dict(dim=3, degree=2, n_elem=16),
+    dict(dim=3, degree=3, n_elem=12),
+    dict(dim=2, degree=4, n_elem=64, pde=pmg.PDE_CDR),
+    dict(dim=2, degree=3, n_elem=64, ilut_limit_mode=pmg.LIMIT_PER_PART),
+    dict(dim=2, degree=3, n_elem=64, ilut_limit_mode=pmg.LIMIT_PER_ROW),
+    dict(dim=2, degree=4, n_elem=48, ordering=pmg.ORDER_NATURAL),
+    dict(dim=2, degree=2, n_elem=64, ilut_fill=2.0),
+]
+
+
+def _id(c):
+    return "-".join(f"{k}{v}" for k, v in c.items())
+
+
+def _same(a, b):
+    a = a.tocsr(); b = b.tocsr()
+    return (np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+            and np.array_equal(a.data.view(np.int64), b.data.view(np.int64)))
+
+
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_device_ilut_equals_host_ilut(case):
+    print("device ILUT", case, flush=True)
+    g = pmg.Solver(device=0, **case)
+    h = pmg.Solver(device=-1, ilut_on_device=0, **case)
+    assert g.info.ilut_on_device == 1
+    assert h.info.ilut_on_device == 0
+    assert _same(g.export(pmg.OP_L), h.export(pmg.OP_L))
+    assert _same(g.export(pmg.OP_U), h.export(pmg.OP_U))
+    print(f"  n {g.n} nnz(L) {g.info.nnz_l} nnz(U) {g.info.nnz_u} t_ilut device {g.info.t_ilut:.3f} s "
+          f"host {h.info.t_ilut:.3f} s", flush=True)
+
+
+def test_device_ilut_zero_pivot_row():
+    o = O.Oracle(2, 2, 32, ilut=False)
+    A = o.A().tolil()
+    i = 123
+    A[i, :] = 0
+    A[:, i] = 0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.Solver(2, 2, 32, operator=A, device=0)
+    assert e.value.status == pmg.EZEROPIVOT
+    o2 = O.Oracle(2, 2, 32)
+    st, bad = o2.set_operator(A)
+    assert st == O.EZEROPIVOT and ("row %d" % bad) in str(e.value)
+
+
+def test_device_ilut_solves_like_the_oracle():
+    """The whole solve with device-factored ILUT against the oracle."""
+    import torch
+    dev = torch.device("cuda:0")
+    s = pmg.Solver(2, 4, 64, geometry=pmg.GEOM_QUARTER_ANNULUS, rhs_kind=pmg.RHS_ANNULUS, device=0)
+    assert s.info.ilut_on_device == 1
+    o = O.Oracle(2, 4, 64, geom=O.GEOM_ANNULUS, rhs=O.RHS_ANNULUS)
+    b = torch.empty(s.n, dtype=torch.float64, device=dev)
+    s.rhs(b)
+    x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    st, it, rel, r0, _, hist = s.solve(b, x, tol=1e-8)
+    _, sto, ito, histo = o.solve(o.f(), tol=1e-8)
+    k = min(len(hist), len(histo))
+    assert st == 0 and sto == 0 and abs(it - ito) <= 1
+    assert np.abs(hist[:k] - histo[:k]).max() <= 1e-10

@@ -60,7 +60,7 @@ def test_hand_worked_examples(case):
     assert np.allclose(U.toarray(), Ue, rtol=2e-16 * 4, atol=0)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("geom,dim,p,nel", [(0, 2, 3, 16), (1, 2, 4, 12), (0, 3, 2, 6)])
 def test_invariants_paper_constants(mode, geom, dim, p, nel):
     o = O.Oracle(dim, p, nel, geom=geom, rhs=geom, opts=O.Options(limit_mode=mode))
@@ -78,7 +78,10 @@ def test_invariants_paper_constants(mode, geom, dim, p, nel):
     nu = np.diff(U.indptr) - 1
     if mode == 0:
         assert nl.max() <= M and nu.max() <= M
+    elif mode == 1:
+        assert (nl + nu).max() <= M
     else:
+        assert nl.max() <= M // 2 and nu.max() <= M // 2
         assert (nl + nu).max() <= M
     assert (L.data != 0).all() and (U.data != 0).all()
     # bit-reproducible on rerun
