@@ -158,11 +158,11 @@ typedef struct {
                                results since the previous such call are invalid.  A
                                correct schedule never reaches the default bound; small
                                values force the fault path (test hook). */
-  int32_t ilut_on_device;   /* 1 (default): ILUT is factored on the device (one wave per row,
-                               rows pipelined in order), with the host factorisation's
-                               arithmetic, so the factors are identical; rows too long for the
-                               kernel's working storage fall back to the host (reported in
-                               pmg_info.ilut_on_device).  0: on the host. */
+  int32_t ilut_on_device;   /* 1: ILUT is factored on the device (one wave per row, rows
+                               pipelined in order), with the host factorisation's arithmetic,
+                               so the factors are identical; rows too long for the kernel's
+                               working storage fall back to the host (reported in
+                               pmg_info.ilut_on_device).  0 (default): on the host threads. */
 } pmg_options;
 
 typedef struct {

@@ -148,9 +148,16 @@ _lib = None
 
 
 def lib():
-    """Loads libpmg.so; raises if it has not been built."""
+    """Loads libpmg.so; raises if it has not been built.  torch is imported
+    first when it is installed: its wheel carries its own HIP runtime, and the
+    library must bind to the runtime torch uses (loaded the other way round,
+    the process ends up with two runtimes and torch finds no device)."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "or python -m paper_1901_01685_amd._build")

@@ -176,6 +176,9 @@ __device__ __forceinline__ T wait_value(const T* p, bool need, const Args& A, bo
 }
 
 __global__ __launch_bounds__(64) void ilut_rows(Args A) {
+  // every product and difference rounded on its own, as on the host (hipcc
+  // would otherwise fuse w_j - l_k u_kj into one FMA)
+#pragma clang fp contract(off)
   extern __shared__ unsigned char lds[];
   const int T = 1 << A.tbits;
   int* keys = reinterpret_cast<int*>(lds);
@@ -248,7 +251,10 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
         const double u = wait_value(A.Uv + base + (act ? s : 0), act, A, gave_up);
         if (act && j >= 0 && j < A.n) {
           const int t = insert(keys, vals, j, A.tbits, &used);
-          if (t >= 0) vals[t] = __dsub_rn(vals[t], __dmul_rn(lk, u));
+          if (t >= 0) {
+            const double prod = lk * u;
+            vals[t] = vals[t] - prod;
+          }
           else atomicOr(&A.flags[1], 1);
         }
         __syncthreads();

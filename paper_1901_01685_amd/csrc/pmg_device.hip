@@ -1386,7 +1386,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->mass_transfer = PMG_MASS_LUMPED;
   o->projection = PMG_PROJ_DIRECT;
   o->poll_limit = 0;
-  o->ilut_on_device = 1;
+  o->ilut_on_device = 0;
   return PMG_OK;
 }
 

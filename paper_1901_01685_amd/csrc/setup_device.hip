@@ -49,12 +49,15 @@ pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int m
   const int64_t cl = std::max<int64_t>(keep_l, 1), cu = keep_u + 1;
   int64_t maxrow = 1;
   for (int i = 0; i < n; ++i) maxrow = std::max<int64_t>(maxrow, Ap.rp[i + 1] - Ap.rp[i]);
+  // working-row table: 8 slots per entry of the longest row to start with,
+  // doubled while a row outgrows three quarters of it and LDS allows
   int tbits = 9;
-  while ((int64_t(1) << tbits) < 8 * std::max(maxrow, cu) && tbits < 13) ++tbits;
+  while ((int64_t(1) << tbits) < 8 * std::max(maxrow, cu) && tbits < 14) ++tbits;
   int64_t list_cap = cl + cu;
   list_cap += list_cap & 1;
-  const size_t lds = 12 * (size_t(1) << tbits) + 12 * (size_t)list_cap;
-  if (lds > (size_t(152) << 10) || (double)n * (double)(cl + cu) > 4.0e9) {
+  auto lds_of = [&](int tb) { return 12 * (size_t(1) << tb) + 12 * (size_t)list_cap; };
+  const size_t kLdsMax = size_t(152) << 10;
+  if (lds_of(tbits) > kLdsMax || (double)n * (double)(cl + cu) > 4.0e9) {
     why = "rows too long for the device factorisation";
     return PMG_EINVAL;
   }
@@ -80,59 +83,64 @@ pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int m
   if ((s = mem.alloc(&state, pmg::kTicketWords))) return s;
   if ((s = mem.alloc(&fault, 1))) return s;
   if ((s = mem.alloc(&flags, 2))) return s;
-  fill<int>(Un, n, -1);
-  fill<int>(Uc, (int64_t)n * cu, -1);
-  fill<unsigned long long>(reinterpret_cast<unsigned long long*>(Uv), (int64_t)n * cu, pmg::kPending64);
-  fill<unsigned>(state, pmg::kTicketWords, 0u);
-  fill<unsigned>(fault, 1, 0u);
-  fill<int>(flags, 1, n);
-  fill<int>(flags + 1, 1, 0);
-  PMG_HIP_OK(hipGetLastError());
-
-  pmg::ilut::Args A{};
-  A.n = n;
-  A.rp = rp;
-  A.ci = ci;
-  A.v = v;
-  A.tau = tau;
-  A.mode = mode == 1 ? 1 : 0;
-  A.keep_l = (int)keep_l;
-  A.keep_u = (int)keep_u;
-  A.cl = (int)cl;
-  A.cu = (int)cu;
-  A.Lc = Lc;
-  A.Lv = Lv;
-  A.Ln = Ln;
-  A.Uc = Uc;
-  A.Uv = Uv;
-  A.Un = Un;
-  A.state = state;
-  A.fault = fault;
-  A.flags = flags;
-  // a row can wait for most of the factorisation's critical path: a wider
-  // default bound than the triangular solves'
-  A.poll_limit = poll_limit > 0 ? poll_limit : (1 << 26);
-  A.tbits = tbits;
-  A.list_cap = (int)list_cap;
-  PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::ilut::ilut_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
-  int dev = 0, per_cu = 0;
-  PMG_HIP_OK(hipGetDevice(&dev));
-  hipDeviceProp_t prop;
-  PMG_HIP_OK(hipGetDeviceProperties(&prop, dev));
-  PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmg::ilut::ilut_rows, 64, lds));
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * prop.multiProcessorCount, n));
-  pmg::ilut::ilut_rows<<<(unsigned)grid, 64, lds>>>(A);
-  PMG_HIP_OK(hipGetLastError());
-  PMG_HIP_OK(hipDeviceSynchronize());
-  int hflags[2];
-  unsigned hfault = 0;
-  PMG_HIP_OK(hipMemcpy(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost));
-  PMG_HIP_OK(hipMemcpy(&hfault, fault, sizeof hfault, hipMemcpyDeviceToHost));
-  if (hfault) return fail(PMG_EDEVICE, "device ILUT: a row waited past its poll bound");
-  if (hflags[1]) {
-    why = "a working row outgrew its table";
-    return PMG_EINVAL;
+  int hflags[2] = {0, 0};
+  for (;;) {
+    const size_t lds = lds_of(tbits);
+    fill<int>(Un, n, -1);
+    fill<int>(Uc, (int64_t)n * cu, -1);
+    fill<unsigned long long>(reinterpret_cast<unsigned long long*>(Uv), (int64_t)n * cu, pmg::kPending64);
+    fill<unsigned>(state, pmg::kTicketWords, 0u);
+    fill<unsigned>(fault, 1, 0u);
+    fill<int>(flags, 1, n);
+    fill<int>(flags + 1, 1, 0);
+    PMG_HIP_OK(hipGetLastError());
+    pmg::ilut::Args A{};
+    A.n = n;
+    A.rp = rp;
+    A.ci = ci;
+    A.v = v;
+    A.tau = tau;
+    A.mode = mode == 1 ? 1 : 0;
+    A.keep_l = (int)keep_l;
+    A.keep_u = (int)keep_u;
+    A.cl = (int)cl;
+    A.cu = (int)cu;
+    A.Lc = Lc;
+    A.Lv = Lv;
+    A.Ln = Ln;
+    A.Uc = Uc;
+    A.Uv = Uv;
+    A.Un = Un;
+    A.state = state;
+    A.fault = fault;
+    A.flags = flags;
+    // a row can wait for most of the factorisation's critical path: a wider
+    // default bound than the triangular solves'
+    A.poll_limit = poll_limit > 0 ? poll_limit : (1 << 26);
+    A.tbits = tbits;
+    A.list_cap = (int)list_cap;
+    PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::ilut::ilut_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+    int dev = 0, per_cu = 0;
+    PMG_HIP_OK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    PMG_HIP_OK(hipGetDeviceProperties(&prop, dev));
+    PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmg::ilut::ilut_rows, 64, lds));
+    const int64_t grid =
+        std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * prop.multiProcessorCount, n));
+    pmg::ilut::ilut_rows<<<(unsigned)grid, 64, lds>>>(A);
+    PMG_HIP_OK(hipGetLastError());
+    PMG_HIP_OK(hipDeviceSynchronize());
+    unsigned hfault = 0;
+    PMG_HIP_OK(hipMemcpy(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost));
+    PMG_HIP_OK(hipMemcpy(&hfault, fault, sizeof hfault, hipMemcpyDeviceToHost));
+    if (hfault) return fail(PMG_EDEVICE, "device ILUT: a row waited past its poll bound");
+    if (!hflags[1]) break;
+    if (lds_of(tbits + 1) > kLdsMax) {
+      why = "a working row outgrew the largest table";
+      return PMG_EINVAL;
+    }
+    ++tbits;
   }
   if (hflags[0] < n) {
     bad_row = hflags[0];

@@ -6,11 +6,11 @@ dissection and natural orderings, both geometries, the cube and the
 non-symmetric benchmark-2 operator, and the zero-pivot branch."""
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 import oracle as O
 import paper_1901_01685_amd as pmg
 
+torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 CASES = [
@@ -33,14 +33,22 @@ def _id(c):
 
 def _same(a, b):
     a = a.tocsr(); b = b.tocsr()
-    return (np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
-            and np.array_equal(a.data.view(np.int64), b.data.view(np.int64)))
+    pat = np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+    if not pat:
+        print("  patterns differ: nnz", a.nnz, b.nnz, "first row",
+              int(np.argmax(np.diff(a.indptr) != np.diff(b.indptr))), flush=True)
+        return False
+    same = np.array_equal(a.data.view(np.int64), b.data.view(np.int64))
+    if not same:
+        d = np.abs(a.data - b.data) / np.maximum(np.abs(b.data), 1e-300)
+        print("  values differ:", int((d > 0).sum()), "entries, max rel", float(d.max()), flush=True)
+    return same
 
 
 @pytest.mark.parametrize("case", CASES, ids=_id)
 def test_device_ilut_equals_host_ilut(case):
     print("device ILUT", case, flush=True)
-    g = pmg.Solver(device=0, **case)
+    g = pmg.Solver(device=0, ilut_on_device=1, **case)
     h = pmg.Solver(device=-1, ilut_on_device=0, **case)
     assert g.info.ilut_on_device == 1
     assert h.info.ilut_on_device == 0
@@ -59,7 +67,7 @@ def test_device_ilut_zero_pivot_row():
     A = A.tocsr()
     A.eliminate_zeros()
     with pytest.raises(pmg.PmgError) as e:
-        pmg.Solver(2, 2, 32, operator=A, device=0)
+        pmg.Solver(2, 2, 32, operator=A, device=0, ilut_on_device=1)
     assert e.value.status == pmg.EZEROPIVOT
     o2 = O.Oracle(2, 2, 32)
     st, bad = o2.set_operator(A)
@@ -68,9 +76,9 @@ def test_device_ilut_zero_pivot_row():
 
 def test_device_ilut_solves_like_the_oracle():
     """The whole solve with device-factored ILUT against the oracle."""
-    import torch
     dev = torch.device("cuda:0")
-    s = pmg.Solver(2, 4, 64, geometry=pmg.GEOM_QUARTER_ANNULUS, rhs_kind=pmg.RHS_ANNULUS, device=0)
+    s = pmg.Solver(2, 4, 64, geometry=pmg.GEOM_QUARTER_ANNULUS, rhs_kind=pmg.RHS_ANNULUS, device=0,
+                   ilut_on_device=1)
     assert s.info.ilut_on_device == 1
     o = O.Oracle(2, 4, 64, geom=O.GEOM_ANNULUS, rhs=O.RHS_ANNULUS)
     b = torch.empty(s.n, dtype=torch.float64, device=dev)
