@@ -245,6 +245,19 @@ pmg_status pmg_residual(pmg_handle h, const double *b, const double *x, double *
  * x <- x + U^{-1} L^{-1} r, r given (normally b - A x).  r is not modified. */
 pmg_status pmg_smooth(pmg_handle h, const double *r, double *x, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pmg_smooth
+ * with its work vectors and counters in a static device array instead of the
+ * handle's workspace.  Same kernels and results as pmg_smooth (bit for bit).
+ * Limit: h's unknowns <= 2^21 (2,097,152); larger problems return EINVAL
+ * (use pmg_smooth).  The array (32 MiB + 4 KiB) exists once per device for
+ * the life of the process and is shared by every call on that device, so
+ * calls that overlap on one device race (calls on one stream are ordered).
+ * Allocates nothing: no hipMalloc, hipFree or allocating library call.  A
+ * poll-bound fault is recorded in h and reported by the next synchronising
+ * call on h, as for pmg_smooth.  r, x device, length n, distinct. */
+pmg_status pmg_smooth_static(pmg_handle h, const double *r, double *x, void *stream);
+
 /* Step a2 alone: y = L^{-1} r (forward substitution with the unit lower ILUT
  * factor, Section 3, "Smoother").  r, y device, length n, distinct. */
 pmg_status pmg_lower_solve(pmg_handle h, const double *r, double *y, void *stream);

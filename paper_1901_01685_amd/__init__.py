@@ -114,6 +114,7 @@ SIGNATURES = {
     "pmg_rhs": (C.c_int, [_VP, _VP, _VP]),
     "pmg_residual": (C.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
     "pmg_smooth": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pmg_smooth_static": (C.c_int, [_VP, _VP, _VP, _VP]),
     "pmg_lower_solve": (C.c_int, [_VP, _VP, _VP, _VP]),
     "pmg_upper_solve": (C.c_int, [_VP, _VP, _VP, _VP]),
     "pmg_profile_enable": (C.c_int, [_VP, C.c_int32]),
@@ -291,6 +292,9 @@ class Solver:
 
     def smooth(self, r, x, stream=None):
         _check(lib().pmg_smooth(self._h, _ptr(r), _ptr(x), _stream(stream)))
+
+    def smooth_static(self, r, x, stream=None):
+        _check(lib().pmg_smooth_static(self._h, _ptr(r), _ptr(x), _stream(stream)))
 
     def lower_solve(self, r, y, stream=None):
         _check(lib().pmg_lower_solve(self._h, _ptr(r), _ptr(y), _stream(stream)))

@@ -48,6 +48,39 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 
 }  // namespace pmgdev
 
+// Scratch of pmg_smooth_static, for callers that cannot allocate device
+// memory: the ticket counters of both triangular solves in the first
+// kStaticHead bytes, then the forward solve's output y and the backward
+// solve's output e for up to kStaticMaxN unknowns each (32 MiB in all).  One
+// copy per device, held until the process ends; every call on a device shares
+// it, so calls that overlap on one device race.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kStaticMaxN = int64_t(1) << 21;
+constexpr int64_t kStaticHead = 4096;
+static_assert(kStaticHead >= (int64_t)(2 * pmg::kTicketWords * sizeof(unsigned)), "counters fit the head");
+static __device__ __align__(256) unsigned char scratch[kStaticHead + 2 * sizeof(double) * kStaticMaxN];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+// Device address of `scratch` on device dev, which must be current; looked up
+// once per device.
+static pmg_status static_scratch(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= 64) return pmgdev::fail(PMG_EDEVICE, "device ordinal out of range for the static scratch");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return pmgdev::hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return pmgdev::fail(PMG_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return PMG_OK;
+}
+
 pmg_handle_s::~pmg_handle_s() {
   delete sub;
   if (on_device) {
@@ -1818,6 +1851,30 @@ pmg_status pmg_smooth(pmg_handle h, const double* r, double* x, void* stream) {
   NEED_DEVICE(h);
   if (!r || !x) return fail(PMG_EINVAL, "NULL vector");
   smooth_impl<double>(h, h->ws, r, x, h->ws.y, h->ws.e, (hipStream_t)stream);
+  PMG_HIP_OK(hipGetLastError());
+  return PMG_OK;
+}
+
+pmg_status pmg_smooth_static(pmg_handle h, const double* r, double* x, void* stream) {
+  NEED_DEVICE(h);
+  if (!r || !x) return fail(PMG_EINVAL, "NULL vector");
+  if ((int64_t)h->H.n > kStaticMaxN)
+    return fail(PMG_EINVAL, "pmg_smooth_static: " + std::to_string(h->H.n) +
+                                " unknowns exceed the static scratch (at most " + std::to_string(kStaticMaxN) +
+                                "); use pmg_smooth");
+  unsigned char* base = nullptr;
+  pmg_status s;
+  if ((s = static_scratch(h->device, &base))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned* tick = reinterpret_cast<unsigned*>(base);
+  double* y = reinterpret_cast<double*>(base + kStaticHead);
+  double* e = y + kStaticMaxN;
+  // the counters must start at zero (a kernel, not a memset, so the call can
+  // be captured into a graph); the fault word stays the handle's
+  fill<unsigned>(tick, 2 * pmg::kTicketWords, 0u, st);
+  const pmg::TriCtl lo = tri_ctl(h, h->ws, 0), up = tri_ctl(h, h->ws, 1);
+  lower_launch<double>(h, pmg::TriCtl{tick, lo.fault, lo.poll_limit}, r, y, st);
+  upper_launch<double>(h, pmg::TriCtl{tick + pmg::kTicketWords, up.fault, up.poll_limit}, y, e, x, st);
   PMG_HIP_OK(hipGetLastError());
   return PMG_OK;
 }
