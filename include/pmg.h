@@ -110,12 +110,12 @@ typedef struct {
 typedef struct {
   double ilut_tau;          /* ILUT drop tolerance tau (rule 1) */
   double ilut_fill;         /* ILUT fill factor m (rule 2); <= 0: unlimited */
-  int32_t ilut_limit_mode;  /* ILUT rule 2, M = floor(m nnz(A) / n): PMG_LIMIT_HALF_PER_PART
-                               (default: floor(M/2) largest in the strict lower and in the
-                               strict upper part, so at most M besides the diagonal in each
-                               row and nnz(L+U) close to nnz(A), as Section 3 states),
-                               PMG_LIMIT_PER_ROW (M largest of the whole row) or
-                               PMG_LIMIT_PER_PART (M in each part) */
+  int32_t ilut_limit_mode;  /* ILUT rule 2, M = floor(m nnz(A) / n): PMG_LIMIT_PER_PART
+                               (default: the M largest of the strict lower and of the strict
+                               upper part, as in the cited ILUT; the only reading that
+                               converges on every configuration of Table 4), PMG_LIMIT_PER_ROW
+                               (M largest of the whole row) or PMG_LIMIT_HALF_PER_PART
+                               (floor(M/2) in each part) */
   int32_t nu1, nu2;         /* pre/post ILUT smoothing steps */
   int32_t coarse_cycles;    /* h-multigrid V-cycles at p = 1 */
   int32_t coarse_min_elems; /* direct solve once n_elem <= this (or odd) */

@@ -115,7 +115,7 @@ def _i64p(a):
 class Options:
     tau: float = 1e-12
     fill: float = 1.0
-    limit_mode: int = 2      # rule 2: 0 M largest per part, 1 per row, 2 floor(M/2) per part
+    limit_mode: int = 0      # rule 2: 0 M largest per part, 1 per row, 2 floor(M/2) per part
     coarse_cycles: int = 2
     gs_variant: int = 0      # 0: multicolour, 1: lexicographic
     coarse_min: int = 8

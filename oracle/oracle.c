@@ -878,8 +878,8 @@ typedef struct {
 void orc_default_opts(orc_opts *o) {
   o->tau = 1e-12;   /* Section 3: drop tolerance 1e-12 */
   o->fill = 1.0;    /* Section 3: fill factor m = 1 */
-  o->limit_mode = 2;  /* Section 3, rule 2: at most M entries besides the diagonal in each
-                         row, floor(M/2) in each part, so nnz(L+U) is close to nnz(A) */
+  o->limit_mode = 0;  /* Section 3, rule 2, read per part as in the cited ILUT: the M
+                         largest of the strict lower and of the strict upper part */
   o->coarse_cycles = 2; /* Section 3: two h-multigrid V-cycles at p = 1 */
   o->gs_variant = 0;    /* multicolour Gauss-Seidel */
   o->coarse_min = 8;

@@ -10,16 +10,21 @@
 //   entries per rule 2 (magnitudes ranked in single precision, ties to the
 //   smaller column) and store them sorted by column, the diagonal first in U.
 //
-// One wave factors one row at a time; rows are drawn in increasing order from
-// a ticket counter, so the smallest unfinished row only waits for finished
-// rows and is held by a running wave (the argument of the triangular
-// solves).  The working row lives in LDS as an open-addressing hash table
+// One wave factors one row at a time; rows are drawn from a ticket counter in
+// an order in which every row comes after the rows it can depend on (the
+// blocks of the nested dissection by height, independent blocks interleaved),
+// so the smallest unfinished ticket only waits for finished rows and is held
+// by a running wave (the argument of the triangular solves).  The working row lives in LDS as an open-addressing hash table
 // keyed by column.  A row of U is published entry by entry with device-scope
 // stores into slots that hold a marker until written (column -1, value the
 // signalling-NaN marker, count -1): a wave waiting for row k reloads the
 // count and the entries it needs until no marker is left, so readiness
 // travels with the data and no fence is needed.  Waits are bounded as in the
-// triangular solves (poll_limit, fault word).
+// triangular solves (poll_limit, fault word).  Each pivot row is fetched in
+// one round of loads (count and slots together); the entries kept by rule 2
+// are found by a radix select on their rank keys and stored in the order they
+// are found (the host sorts each row by column afterwards; the factorisation
+// itself does not depend on the order of a row's entries).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -50,8 +55,8 @@ struct Args {
   unsigned* fault;  // set when a wait reached poll_limit
   int* flags;       // [0] smallest row with a zero or non-finite pivot (n: none), [1] table overflow
   int poll_limit;
-  int tbits;     // working row: 1 << tbits slots
-  int list_cap;  // kept entries staged per row (>= cl + cu)
+  int tbits;         // working row: 1 << tbits slots
+  const int* order;  // ticket -> row: every row after the rows it can depend on
 };
 
 __device__ __forceinline__ int ld_dev(const int* p) {
@@ -126,53 +131,119 @@ __device__ __forceinline__ unsigned long long rank_key(double v, int j) {
   return ((unsigned long long)(~bits) << 32) | (unsigned)j;
 }
 
-// The smallest key K with count(key <= K) >= want over the candidates of
-// this lane's slots (part: 0 lower, 1 upper, 2 both), by bisection on the
-// 64-bit key; all candidates are kept when there are at most `want`.
-__device__ __forceinline__ unsigned long long kth_key(const int* keys, const double* vals, int T, int lane, int i,
-                                                      double taui, int part, int want, int total) {
-  if (total <= want) return ~0ull;
-  unsigned long long lo = 0, hi = ~0ull;  // invariant: count(<= hi) >= want
-  while (lo < hi) {
-    const unsigned long long mid = lo + (hi - lo) / 2;
-    int c = 0;
-    for (int s = lane; s < T; s += kWave) {
-      const int j = keys[s];
-      if (j < 0 || j == i) continue;
-      const double x = vals[s];
-      if (x == 0.0 || fabs(x) < taui) continue;
-      if (part == 0 && j > i) continue;
-      if (part == 1 && j < i) continue;
-      c += rank_key(x, j) <= mid ? 1 : 0;
-    }
-    c = wave_sum(c);
-    if (c >= want) hi = mid; else lo = mid + 1;
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
   }
-  return lo;
+  return v;
 }
 
-// Waits (bounded) until *p is not `bad` for the lanes with `need`, reloading
-// with device-scope loads; returns the value.  A wave that gives up marks the
-// fault word and every later wait of any wave returns at once.
-template <typename T>
-__device__ __forceinline__ T wait_value(const T* p, bool need, const Args& A, bool& gave_up) {
-  T val = need ? ld_dev(p) : T(0);
-  int polls = 0;
-  for (;;) {
-    bool miss;
-    if constexpr (sizeof(T) == 8) miss = need && is_marker(val);
-    else miss = need && val == T(-1);
+// Whether slot s of the working row of row i holds a candidate of rule 2 in
+// `part` (0 lower, 1 upper, 2 both) after rule 1.
+__device__ __forceinline__ bool candidate(int j, double x, int i, double taui, int part) {
+  if (j < 0 || j == i || x == 0.0 || fabs(x) < taui) return false;
+  if (part == 0) return j < i;
+  if (part == 1) return j > i;
+  return true;
+}
+
+// The rank key K such that exactly `want` candidates of `part` have a key
+// <= K (all of them when there are at most `want`): a radix select on the
+// 64-bit key, 8 bits per pass from the top, over a 256-bin histogram in LDS;
+// it stops at the first pass whose boundary bin holds exactly the entries
+// still wanted (keys are unique, so the last pass always does).
+__device__ __forceinline__ unsigned long long select_key(const int* keys, const double* vals, int* hist, int T,
+                                                         int lane, int i, double taui, int part, int want,
+                                                         int total) {
+  if (total <= want) return ~0ull;
+  if (want <= 0) return 0ull;  // no finite entry has the key 0
+  unsigned long long prefix = 0;
+  int remaining = want;
+  for (int shift = 56;; shift -= 8) {
+    for (int b = lane; b < 256; b += kWave) hist[b] = 0;
+    __syncthreads();
+    const unsigned long long himask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+    for (int s = lane; s < T; s += kWave) {
+      const int j = keys[s];
+      const double x = vals[s];
+      if (!candidate(j, x, i, taui, part)) continue;
+      const unsigned long long key = rank_key(x, j);
+      if ((key & himask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1);
+    }
+    __syncthreads();
+    int h[4], loc = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h[q] = hist[4 * lane + q];
+      loc += h[q];
+    }
+    const int incl = wave_incl_scan(loc, lane);
+    // the lane whose bins hold the remaining-th entry
+    int c = incl - loc, bsel = -1, before = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (bsel < 0 && c + h[q] >= remaining) {
+        bsel = 4 * lane + q;
+        before = c;
+      }
+      c += h[q];
+    }
+    const unsigned long long owner = __ballot(bsel >= 0 && incl - loc < remaining);
+    const int src = __ffsll((long long)owner) - 1;
+    const int b = __shfl(bsel, src), bef = __shfl(before, src);
+    const int inb = hist[b];
+    __syncthreads();
+    prefix |= (unsigned long long)b << shift;
+    remaining -= bef;
+    if (inb == remaining || shift == 0) return prefix | (shift == 0 ? 0ull : ((1ull << shift) - 1));
+  }
+}
+
+// U rows of up to kMaxChunks * 64 slots are fetched in one round of loads.
+constexpr int kMaxChunks = 12;
+
+// Row k of U (count, and slot c * 64 + lane in chunk c), waiting until the
+// count and every slot below it are written; all loads of a round are in
+// flight together.
+__device__ __forceinline__ int fetch_u(const Args& A, int k, int nch, int lane, int (&uc)[kMaxChunks],
+                                       double (&uv)[kMaxChunks], bool& gave_up) {
+  const int64_t base = (int64_t)k * A.cu;
+  int cnt = ld_dev(A.Un + k);
+#pragma unroll
+  for (int c = 0; c < kMaxChunks; ++c) {
+    const int s = c * kWave + lane;
+    const bool act = c < nch && s < A.cu;
+    uc[c] = act ? ld_dev(A.Uc + base + s) : 0;
+    uv[c] = act ? ld_dev(A.Uv + base + s) : 0.0;
+  }
+  for (int polls = 0;; ++polls) {
+    const int lim = cnt >= 1 ? cnt : A.cu;
+    bool miss = cnt < 1;
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) {
+      const int s = c * kWave + lane;
+      miss |= c < nch && s < lim && (uc[c] == -1 || is_marker(uv[c]));
+    }
     if (__ballot(miss) == 0) break;
-    if (gave_up || polls >= A.poll_limit || ld_dev(reinterpret_cast<const int*>(A.fault)) != 0) {
+    if (gave_up || polls >= A.poll_limit ||
+        ((polls & 15) == 15 && ld_dev(reinterpret_cast<const int*>(A.fault)) != 0)) {
       gave_up = true;
       st_dev(A.fault, 1u);
-      break;
+      return cnt >= 1 ? cnt : 1;
     }
-    ++polls;
     __builtin_amdgcn_s_sleep(2);
-    if (miss) val = ld_dev(p);
+    if (cnt < 1) cnt = ld_dev(A.Un + k);
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) {
+      const int s = c * kWave + lane;
+      if (c < nch && s < A.cu && (uc[c] == -1 || is_marker(uv[c]))) {
+        uc[c] = ld_dev(A.Uc + base + s);
+        uv[c] = ld_dev(A.Uv + base + s);
+      }
+    }
   }
-  return val;
+  return cnt;
 }
 
 __global__ __launch_bounds__(64) void ilut_rows(Args A) {
@@ -183,14 +254,15 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
   const int T = 1 << A.tbits;
   int* keys = reinterpret_cast<int*>(lds);
   double* vals = reinterpret_cast<double*>(lds + sizeof(int) * T);
-  int* kc = reinterpret_cast<int*>(lds + 12 * (size_t)T);                       // kept columns
-  double* kv = reinterpret_cast<double*>(lds + 12 * (size_t)T + 4 * (size_t)A.list_cap);  // kept values
-  __shared__ int used, nkept;
+  int* hist = reinterpret_cast<int*>(lds + 12 * (size_t)T);  // 256 bins
+  const int nch = (A.cu + kWave - 1) / kWave;
+  __shared__ int used, nkl, nku;
   const int lane = threadIdx.x & 63;
   bool gave_up = false;
   for (;;) {
-    const int i = __builtin_amdgcn_readfirstlane((int)atomicAdd(A.state, lane == 0 ? 1u : 0u));
-    if (i >= A.n) break;
+    const int tk = __builtin_amdgcn_readfirstlane((int)atomicAdd(A.state, lane == 0 ? 1u : 0u));
+    if (tk >= A.n) break;
+    const int i = A.order[tk];
     for (int s = lane; s < T; s += kWave) keys[s] = -1;
     if (lane == 0) used = 0;
     __syncthreads();
@@ -216,7 +288,7 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
     __syncthreads();
     const int64_t nzi = r1 - r0;
     const double taui = nzi > 0 ? A.tau * (rs / (double)nzi) : 0.0;
-    bool over = used > (3 * T) / 4;
+    bool over = used > (7 * T) / 8;
     // elimination with the rows k < i, in increasing k
     int kprev = -1;
     while (!over) {
@@ -230,11 +302,11 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
       kprev = k;
       const int sk = find(keys, k, A.tbits);
       const double wk = vals[sk];
-      const int cnt = wait_value(A.Un + k, true, A, gave_up);
-      const int cntk = gave_up && cnt < 1 ? 1 : cnt;
-      const int64_t base = (int64_t)k * A.cu;
+      int uc[kMaxChunks];
+      double uv[kMaxChunks];
+      const int cntk = fetch_u(A, k, nch, lane, uc, uv, gave_up);
       // the diagonal first: the multiplier decides whether row k is used
-      const double ukk = __shfl(wait_value(A.Uv + base, lane == 0, A, gave_up), 0);
+      const double ukk = __shfl(uv[0], 0);
       const double lk = wk / ukk;
       __syncthreads();
       if (fabs(lk) < taui) {
@@ -244,22 +316,23 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
       }
       if (lane == 0) vals[sk] = lk;
       __syncthreads();
-      for (int b = 1; b < cntk; b += kWave) {
-        const int s = b + lane;
-        const bool act = s < cntk && s < A.cu;
-        const int j = wait_value(A.Uc + base + (act ? s : 0), act, A, gave_up);
-        const double u = wait_value(A.Uv + base + (act ? s : 0), act, A, gave_up);
-        if (act && j >= 0 && j < A.n) {
+#pragma unroll
+      for (int c = 0; c < kMaxChunks; ++c) {
+        if (c >= nch) break;
+        const int s = c * kWave + lane;
+        const int j = uc[c];
+        if (s >= 1 && s < cntk && s < A.cu && j >= 0 && j < A.n) {
           const int t = insert(keys, vals, j, A.tbits, &used);
           if (t >= 0) {
-            const double prod = lk * u;
+            const double prod = lk * uv[c];
             vals[t] = vals[t] - prod;
+          } else {
+            atomicOr(&A.flags[1], 1);
           }
-          else atomicOr(&A.flags[1], 1);
         }
         __syncthreads();
       }
-      over = used > (3 * T) / 4;
+      over = used > (7 * T) / 8;
     }
     if (over && lane == 0) atomicOr(&A.flags[1], 1);
     // pivot
@@ -278,60 +351,38 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
     nlo = wave_sum(nlo);
     nup = wave_sum(nup);
     unsigned long long kl, ku;
-    int keepL, keepU;
     if (A.mode == 1) {
-      kl = ku = kth_key(keys, vals, T, lane, i, taui, 2, A.keep_l, nlo + nup);
-      keepL = keepU = -1;  // counted below
+      kl = ku = select_key(keys, vals, hist, T, lane, i, taui, 2, A.keep_l, nlo + nup);
     } else {
-      kl = kth_key(keys, vals, T, lane, i, taui, 0, A.keep_l, nlo);
-      ku = kth_key(keys, vals, T, lane, i, taui, 1, A.keep_u, nup);
-      keepL = nlo < A.keep_l ? nlo : A.keep_l;
-      keepU = nup < A.keep_u ? nup : A.keep_u;
+      kl = select_key(keys, vals, hist, T, lane, i, taui, 0, A.keep_l, nlo);
+      ku = select_key(keys, vals, hist, T, lane, i, taui, 1, A.keep_u, nup);
     }
-    // stage the kept entries (lower first, upper after), unordered
-    if (lane == 0) nkept = 0;
+    // store the kept entries as they are found
+    if (lane == 0) nkl = nku = 0;
     __syncthreads();
+    const int64_t lb = (int64_t)i * A.cl, ub = (int64_t)i * A.cu;
     for (int s = lane; s < T; s += kWave) {
       const int j = keys[s];
-      if (j < 0 || j == i) continue;
       const double x = vals[s];
-      if (x == 0.0 || fabs(x) < taui) continue;
-      const unsigned long long key = rank_key(x, j);
-      if (key <= (j < i ? kl : ku)) {
-        const int q = atomicAdd(&nkept, 1);
-        if (q < A.list_cap) {
-          kc[q] = j;
-          kv[q] = x;
+      if (!candidate(j, x, i, taui, 2)) continue;
+      if (rank_key(x, j) > (j < i ? kl : ku)) continue;
+      if (j < i) {
+        const int q = atomicAdd(&nkl, 1);
+        if (q < A.cl) {
+          A.Lc[lb + q] = j;
+          A.Lv[lb + q] = x;
+        }
+      } else {
+        const int q = atomicAdd(&nku, 1);
+        if (q + 1 < A.cu) {
+          st_dev(A.Uc + ub + 1 + q, j);
+          st_dev(A.Uv + ub + 1 + q, x);
         }
       }
     }
     __syncthreads();
-    const int nk = nkept < A.list_cap ? nkept : A.list_cap;
-    if (A.mode == 1) {
-      int c = 0;
-      for (int q = lane; q < nk; q += kWave) c += kc[q] < i ? 1 : 0;
-      keepL = wave_sum(c);
-      keepU = nk - keepL;
-    }
-    // each kept entry's place: the kept entries of its part with a smaller column
-    const int64_t lb = (int64_t)i * A.cl, ub = (int64_t)i * A.cu;
-    for (int q = lane; q < nk; q += kWave) {
-      const int j = kc[q];
-      int pos = 0;
-      for (int t = 0; t < nk; ++t) {
-        const int jt = kc[t];
-        pos += ((jt < i) == (j < i) && jt < j) ? 1 : 0;
-      }
-      if (j < i) {
-        if (pos < A.cl) {
-          A.Lc[lb + pos] = j;
-          A.Lv[lb + pos] = kv[q];
-        }
-      } else if (pos + 1 < A.cu) {
-        st_dev(A.Uc + ub + 1 + pos, j);
-        st_dev(A.Uv + ub + 1 + pos, kv[q]);
-      }
-    }
+    const int keepL = nkl < A.cl ? nkl : A.cl;
+    const int keepU = nku < A.cu - 1 ? nku : A.cu - 1;
     if (lane == 0) {
       A.Ln[i] = keepL;
       st_dev(A.Uc + ub, i);

@@ -1401,7 +1401,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->ilut_tau = 1e-12;
   o->ilut_fill = 1.0;
-  o->ilut_limit_mode = PMG_LIMIT_HALF_PER_PART;
+  o->ilut_limit_mode = PMG_LIMIT_PER_PART;
   o->nu1 = 1;
   o->nu2 = 1;
   o->coarse_cycles = 2;
@@ -1517,8 +1517,17 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
       // long for the device kernel fall back to the host
       PMG_HIP_OK(hipSetDevice(o.device));
       std::string why;
-      const pmg_status sd = pmgdev::ilut_device(Ap, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, o.poll_limit, H.L,
-                                                H.U, bad, why);
+      // an injected operator may couple anything: rows strictly in order then
+      std::vector<int32_t> order;
+      if (inj_n) {
+        order.resize(H.n);
+        for (int i = 0; i < H.n; ++i) order[i] = i;
+      } else {
+        order = pmg::factor_ticket_order(prob->dim, prob->n_elem + prob->degree - 2, prob->degree, o.ordering,
+                                         o.nd_leaf);
+      }
+      const pmg_status sd = pmgdev::ilut_device(Ap, order, o.ilut_tau, o.ilut_fill, o.ilut_limit_mode, o.poll_limit,
+                                                H.L, H.U, bad, why);
       if (sd == PMG_EZEROPIVOT)
         return fail(PMG_EZEROPIVOT, "ILUT: zero or non-finite pivot in row " + std::to_string(bad));
       if (sd != PMG_OK && sd != PMG_EINVAL) return sd;

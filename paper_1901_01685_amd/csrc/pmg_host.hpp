@@ -69,6 +69,15 @@ Csr transpose(const Csr& A);
 // ILUT ordering over grid lines (natural or nested dissection).
 std::vector<int32_t> line_ordering(int dim, int nint, int p, int ordering, int leaf);
 
+// An order of the rows of P A P^T (P the ordering above) in which every row
+// comes after the rows its factorisation can depend on: the blocks of the
+// nested dissection by height in the dissection tree (uncut boxes first,
+// then separators level by level), the rows of the blocks of one height
+// interleaved, each block's rows in increasing order.  Rows of independent
+// blocks are therefore factored side by side.  Natural order: the rows in
+// order.
+std::vector<int32_t> factor_ticket_order(int dim, int nint, int p, int ordering, int leaf);
+
 // B = P A P^T, B_ij = A_{perm[i], perm[j]}, columns sorted.
 Csr permute(const Csr& A, const std::vector<int32_t>& perm, int threads);
 

@@ -196,8 +196,9 @@ pmg_status alloc_workspace(pmg_handle h, Workspace& ws, bool mixed, bool request
 // EZEROPIVOT with bad_row; EINVAL (reason in why) when the rows are too long
 // for the device kernel or the fill is unlimited, the caller then factoring
 // on the host; EDEVICE on a HIP error or a wait past the poll bound.
-pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill, int mode, int poll_limit, pmg::Csr& L,
-                       pmg::Csr& U, int& bad_row, std::string& why);
+// order: pmg::factor_ticket_order of the problem (rows after their dependencies).
+pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, double tau, double fill, int mode,
+                       int poll_limit, pmg::Csr& L, pmg::Csr& U, int& bad_row, std::string& why);
 // Checks a problem description (sizes, kinds, knot vectors, callback); false
 // with the reason in msg.
 bool valid_problem(const pmg_problem* p, std::string& msg);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ilut_kernels.hpp"
@@ -30,8 +31,8 @@ void fill(T* p, int64_t n, T v) {
 
 namespace pmgdev {
 
-pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int mode, int poll_limit, pmg::Csr& L,
-                       pmg::Csr& U, int& bad_row, std::string& why) {
+pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, double tau, double fill_factor, int mode,
+                       int poll_limit, pmg::Csr& L, pmg::Csr& U, int& bad_row, std::string& why) {
   const int n = Ap.nrows;
   const int64_t nnzA = Ap.nnz();
   bad_row = -1;
@@ -49,15 +50,16 @@ pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int m
   const int64_t cl = std::max<int64_t>(keep_l, 1), cu = keep_u + 1;
   int64_t maxrow = 1;
   for (int i = 0; i < n; ++i) maxrow = std::max<int64_t>(maxrow, Ap.rp[i + 1] - Ap.rp[i]);
-  // working-row table: 8 slots per entry of the longest row to start with,
-  // doubled while a row outgrows three quarters of it and LDS allows
+  // working-row table: 16 slots per entry of the longest row to start with
+  // (rows with fill reach 6-13 times their length; the table is full at 7/8),
+  // doubled while a row outgrows it and LDS allows
   int tbits = 9;
-  while ((int64_t(1) << tbits) < 8 * std::max(maxrow, cu) && tbits < 14) ++tbits;
-  int64_t list_cap = cl + cu;
-  list_cap += list_cap & 1;
-  auto lds_of = [&](int tb) { return 12 * (size_t(1) << tb) + 12 * (size_t)list_cap; };
+  while ((int64_t(1) << tbits) < 16 * std::max(maxrow, cu) && tbits < 14) ++tbits;
+  auto lds_of = [&](int tb) { return 12 * (size_t(1) << tb) + 256 * sizeof(int); };
   const size_t kLdsMax = size_t(152) << 10;
-  if (lds_of(tbits) > kLdsMax || (double)n * (double)(cl + cu) > 4.0e9) {
+  while (tbits > 9 && lds_of(tbits) > kLdsMax) --tbits;
+  if ((int64_t)order.size() != n || cu > pmg::ilut::kMaxChunks * pmg::ilut::kWave || lds_of(tbits) > kLdsMax ||
+      (double)n * (double)(cl + cu) > 4.0e9) {
     why = "rows too long for the device factorisation";
     return PMG_EINVAL;
   }
@@ -67,13 +69,14 @@ pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int m
     ~Release() { m.release(); }
   } rel{mem};
   int64_t *rp = nullptr;
-  int *ci = nullptr, *Lc = nullptr, *Ln = nullptr, *Uc = nullptr, *Un = nullptr, *flags = nullptr;
+  int *ci = nullptr, *Lc = nullptr, *Ln = nullptr, *Uc = nullptr, *Un = nullptr, *flags = nullptr, *ord = nullptr;
   double *v = nullptr, *Lv = nullptr, *Uv = nullptr;
   unsigned *state = nullptr, *fault = nullptr;
   pmg_status s;
   if ((s = mem.upload(&rp, Ap.rp.data(), Ap.rp.size()))) return s;
   if ((s = mem.upload(&ci, Ap.ci.data(), Ap.ci.size()))) return s;
   if ((s = mem.upload(&v, Ap.v.data(), Ap.v.size()))) return s;
+  if ((s = mem.upload(&ord, order.data(), order.size()))) return s;
   if ((s = mem.alloc(&Lc, (size_t)n * cl))) return s;
   if ((s = mem.alloc(&Lv, (size_t)n * cl))) return s;
   if ((s = mem.alloc(&Ln, n))) return s;
@@ -118,7 +121,7 @@ pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int m
     // default bound than the triangular solves'
     A.poll_limit = poll_limit > 0 ? poll_limit : (1 << 26);
     A.tbits = tbits;
-    A.list_cap = (int)list_cap;
+    A.order = ord;
     PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::ilut::ilut_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
     int dev = 0, per_cu = 0;
@@ -169,12 +172,37 @@ pmg_status ilut_device(const pmg::Csr& Ap, double tau, double fill_factor, int m
   L.v.resize(L.rp[n]);
   U.ci.resize(U.rp[n]);
   U.v.resize(U.rp[n]);
-  for (int i = 0; i < n; ++i) {
-    std::copy(lc.begin() + (size_t)i * cl, lc.begin() + (size_t)i * cl + ln[i], L.ci.begin() + L.rp[i]);
-    std::copy(lv.begin() + (size_t)i * cl, lv.begin() + (size_t)i * cl + ln[i], L.v.begin() + L.rp[i]);
-    std::copy(uc.begin() + (size_t)i * cu, uc.begin() + (size_t)i * cu + un[i], U.ci.begin() + U.rp[i]);
-    std::copy(uv.begin() + (size_t)i * cu, uv.begin() + (size_t)i * cu + un[i], U.v.begin() + U.rp[i]);
+  // rows were stored in the order their entries were found: sort each by
+  // column (U keeps its diagonal first)
+  auto place = [&](int lo, int hi) {
+    std::vector<std::pair<int, double>> row;
+    for (int i = lo; i < hi; ++i) {
+      row.clear();
+      for (int t = 0; t < ln[i]; ++t) row.emplace_back(lc[(size_t)i * cl + t], lv[(size_t)i * cl + t]);
+      std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      for (int t = 0; t < ln[i]; ++t) {
+        L.ci[L.rp[i] + t] = row[t].first;
+        L.v[L.rp[i] + t] = row[t].second;
+      }
+      row.clear();
+      for (int t = 1; t < un[i]; ++t) row.emplace_back(uc[(size_t)i * cu + t], uv[(size_t)i * cu + t]);
+      std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      U.ci[U.rp[i]] = uc[(size_t)i * cu];
+      U.v[U.rp[i]] = uv[(size_t)i * cu];
+      for (int t = 1; t < un[i]; ++t) {
+        U.ci[U.rp[i] + t] = row[t - 1].first;
+        U.v[U.rp[i] + t] = row[t - 1].second;
+      }
+    }
+  };
+  const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  const int chunk = (n + nth - 1) / nth;
+  for (int t = 0; t < nth; ++t) {
+    const int lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo < hi) pool.emplace_back(place, lo, hi);
   }
+  for (auto& th : pool) th.join();
   return PMG_OK;
 }
 

@@ -301,6 +301,74 @@ std::vector<int32_t> line_ordering(int dim, int nint, int p, int ordering, int l
   return perm;
 }
 
+namespace {
+
+struct NdBlock {
+  int64_t l0, l1;  // positions of its lines in the ordering, [l0, l1)
+  int height;      // 0 for an uncut box, 1 + the children's for a separator
+};
+
+// The blocks of the nested-dissection order, in emission order, following
+// the same cuts as line_ordering.  Returns the box's height (-1 if empty).
+int nd_blocks(int y0, int y1, int z0, int z1, bool whole, int nint, int p, int leaf, int64_t& pos,
+              std::vector<NdBlock>& out) {
+  const int ey = y1 - y0, ez = z1 - z0;
+  if (ey <= 0 || ez <= 0) return -1;
+  const int longest = std::max(ey, ez);
+  if (whole || ey * ez <= leaf || longest < 2 * p + 3) {
+    out.push_back({pos, pos + (int64_t)ey * ez, 0});
+    pos += (int64_t)ey * ez;
+    return 0;
+  }
+  int h1, h2;
+  NdBlock sep;
+  if (ey >= ez) {
+    const int m = y0 + (ey - p) / 2;
+    h1 = nd_blocks(y0, m, z0, z1, false, nint, p, leaf, pos, out);
+    h2 = nd_blocks(m + p, y1, z0, z1, false, nint, p, leaf, pos, out);
+    sep = {pos, pos + (int64_t)p * ez, 0};
+  } else {
+    const int m = z0 + (ez - p) / 2;
+    h1 = nd_blocks(y0, y1, z0, m, false, nint, p, leaf, pos, out);
+    h2 = nd_blocks(y0, y1, m + p, z1, false, nint, p, leaf, pos, out);
+    sep = {pos, pos + (int64_t)ey * p, 0};
+  }
+  sep.height = std::max(std::max(h1, h2), -1) + 1;
+  pos = sep.l1;
+  out.push_back(sep);
+  return sep.height;
+}
+
+}  // namespace
+
+std::vector<int32_t> factor_ticket_order(int dim, int nint, int p, int ordering, int leaf) {
+  const int64_t nlines = dim == 2 ? nint : (int64_t)nint * nint;
+  std::vector<NdBlock> blocks;
+  if (ordering == 0) {
+    blocks.push_back({0, nlines, 0});
+  } else {
+    int64_t pos = 0;
+    nd_blocks(0, nint, 0, dim == 2 ? 1 : nint, false, nint, p, leaf, pos, blocks);
+  }
+  int hmax = 0;
+  for (const NdBlock& b : blocks) hmax = std::max(hmax, b.height);
+  std::vector<int32_t> order;
+  order.reserve((size_t)nlines * nint);
+  for (int h = 0; h <= hmax; ++h) {
+    std::vector<const NdBlock*> lev;
+    int64_t longest = 0;
+    for (const NdBlock& b : blocks)
+      if (b.height == h) {
+        lev.push_back(&b);
+        longest = std::max(longest, (b.l1 - b.l0) * nint);
+      }
+    for (int64_t r = 0; r < longest; ++r)
+      for (const NdBlock* b : lev)
+        if (r < (b->l1 - b->l0) * nint) order.push_back((int32_t)(b->l0 * nint + r));
+  }
+  return order;
+}
+
 Csr permute(const Csr& A, const std::vector<int32_t>& perm, int threads) {
   const int n = A.nrows;
   std::vector<int32_t> inv(n);

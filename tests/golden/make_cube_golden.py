@@ -20,8 +20,10 @@ import oracle as O  # noqa: E402
 
 
 def main():
-    out = {"_source": "oracle/oracle.c via tests/golden/make_cube_golden.py (defaults: ILUT(1e-12, 1), "
-                      "rule 2 half per part, nested dissection, nu1 = nu2 = 1, two h-multigrid cycles)",
+    o_def = O.Options()
+    out = {"_source": "oracle/oracle.c via tests/golden/make_cube_golden.py (oracle defaults: ILUT(%g, %g), "
+                      "rule 2 mode %d, nested dissection, nu1 = nu2 = 1, two h-multigrid cycles)"
+                      % (o_def.tau, o_def.fill, o_def.limit_mode),
            "nel": 32, "tol": 1e-8, "cases": {}}
     for p in (2, 3):
         o = O.Oracle(3, p, 32)

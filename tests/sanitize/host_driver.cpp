@@ -55,8 +55,46 @@ static int run(int dim, int p, int nel, int geom, int pde, int mode, int orderin
   return (T.nnz() == H.A.nnz() && (int)f.size() == H.n) ? 0 : 1;
 }
 
+// The device factorisation's ticket order must put every row after the rows
+// its elimination can reach: checked against the pattern of the exact LU
+// (unlimited fill), which contains every pivot any ILUT meets.
+static int check_ticket_order(int dim, int p, int nel, int ordering) {
+  pmg::SetupParams sp;
+  sp.dim = dim;
+  sp.p = p;
+  sp.nel = nel;
+  sp.threads = 4;
+  pmg::HostOps H;
+  std::string msg;
+  if (pmg::assemble_all(sp, H, msg)) return 1;
+  const int nint = nel + p - 2;
+  H.perm = pmg::line_ordering(dim, nint, p, ordering, 8);
+  pmg::Csr Ap = pmg::permute(H.A, H.perm, 4);
+  pmg::Csr L, U;
+  int bad = -1;
+  if (pmg::ilut_factor(Ap, 0.0, 0.0, 0, 4, L, U, bad)) return 1;
+  const std::vector<int32_t> order = pmg::factor_ticket_order(dim, nint, p, ordering, 8);
+  if ((int)order.size() != H.n) return 1;
+  std::vector<int> pos(H.n, -1);
+  for (int t = 0; t < H.n; ++t) {
+    if (order[t] < 0 || order[t] >= H.n || pos[order[t]] >= 0) return 1;
+    pos[order[t]] = t;
+  }
+  int64_t violations = 0;
+  for (int i = 0; i < H.n; ++i)
+    for (int64_t k = L.rp[i]; k < L.rp[i + 1]; ++k) violations += pos[L.ci[k]] > pos[i];
+  std::printf("ticket order dim %d p %d nel %d ordering %d: n %d, exact-LU dependencies %lld, violations %lld\n", dim,
+              p, nel, ordering, H.n, (long long)L.nnz(), (long long)violations);
+  return violations != 0;
+}
+
 int main() {
   int bad = 0;
+  bad |= check_ticket_order(2, 2, 40, 1);
+  bad |= check_ticket_order(2, 5, 32, 1);
+  bad |= check_ticket_order(3, 2, 12, 1);
+  bad |= check_ticket_order(3, 3, 10, 1);
+  bad |= check_ticket_order(2, 3, 24, 0);
   bad |= run(2, 2, 16, 0, 0, 2, 1, 0, 4);
   bad |= run(2, 3, 32, 0, 0, 0, 1, 2, 3);
   bad |= run(2, 4, 16, 1, 0, 1, 0, 1, 2);

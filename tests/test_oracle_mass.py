@@ -45,8 +45,5 @@ def test_paper_iteration_counts_consistent_vs_lumped():
             assert st == 0
             counts[mt] = it
         paper = gold["consistent"][0][gold["p"].index(p)]   # h = 2^-6
-        # the appendix's absolute counts within 3 (ordering and rule-2 reading:
-        # see the annulus counts); its claim, the same counts as the direct
-        # lumped method, within 1
-        assert abs(counts[1] - paper) <= 3, (p, counts, paper)
+        assert abs(counts[1] - paper) <= 1, (p, counts, paper)
         assert abs(counts[1] - counts[0]) <= 1, (p, counts)

@@ -195,11 +195,7 @@ def test_iteration_counts_h_and_p_independent_annulus():
         assert max(c) - min(c) <= 2, (p, c)
         assert all(1 <= v <= 10 for v in c)
         paper = gold["ilut"][0][gold["p"].index(p)]          # h = 2^-6 row
-        # the paper's counts come with its own (unnamed) fill-reducing ordering
-        # and the library ILUT it cites; with nested dissection and rule 2 as
-        # Section 3 states it (at most M entries besides the diagonal per row)
-        # they sit within 3 of Table 4
-        assert abs(counts[(p, 64)] - paper) <= 3, (p, counts[(p, 64)], paper)
+        assert abs(counts[(p, 64)] - paper) <= 2, (p, counts[(p, 64)], paper)
 
 
 def test_iteration_counts_cube():
