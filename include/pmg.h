@@ -42,8 +42,8 @@ typedef enum {
   PMG_EINVAL = 1,     /* invalid argument or unsupported configuration */
   PMG_ENOMEM = 2,     /* host or device allocation failed */
   PMG_EDEVICE = 3,    /* HIP runtime error, no device for a device call, or a
-                         triangular solve that stopped at its poll bound (see
-                         pmg_options.poll_limit) */
+                         triangular solve or device ILUT row that stopped at its
+                         poll bound (see pmg_options.poll_limit) */
   PMG_EZEROPIVOT = 4, /* ILUT met a zero or non-finite pivot */
   PMG_EDIVERGED = 5,  /* relative residual above the divergence ratio */
   PMG_EMAXIT = 6,     /* max_iter V-cycles without reaching tol */
@@ -157,12 +157,19 @@ typedef struct {
                                pmg_bicgstab, a server step) returns PMG_EDEVICE, and the
                                results since the previous such call are invalid.  A
                                correct schedule never reaches the default bound; small
-                               values force the fault path (test hook). */
-  int32_t ilut_on_device;   /* 1: ILUT is factored on the device (one wave per row, rows
-                               pipelined in order), with the host factorisation's arithmetic,
-                               so the factors are identical; rows too long for the kernel's
-                               working storage fall back to the host (reported in
-                               pmg_info.ilut_on_device).  0 (default): on the host threads. */
+                               values force the fault path (test hook).  The same bound
+                               applies to a row of the device ILUT waiting for an earlier
+                               row of U (default there 1 << 26): pmg_setup then returns
+                               PMG_EDEVICE and builds no handle. */
+  int32_t ilut_on_device;   /* 1 (default): ILUT is factored on the device (one wave per row,
+                               rows of independent nested-dissection blocks side by side), with
+                               the host factorisation's arithmetic, so the factors are
+                               identical.  Problems the kernel does not take (fill <= 0, more
+                               than 767 entries per row of U, working rows beyond its largest
+                               tables) are factored on the host (reported in
+                               pmg_info.ilut_on_device).  0: on the host threads. */
+  int32_t tri_waves_per_cu; /* waves per compute unit of the triangular solves' persistent
+                               grid; 0 (default): as many as fit at once */
 } pmg_options;
 
 typedef struct {
@@ -385,8 +392,11 @@ const char *pmg_last_error(void);
 typedef struct pmg_server_s *pmg_server;
 
 typedef struct {
-  int64_t budget_bytes;    /* device memory for operators and slot workspaces */
-  int64_t max_class_bytes; /* classes estimated above this are rejected; 0: budget/4 */
+  int64_t budget_bytes;    /* device memory for operators and slot workspaces; 0 (default):
+                              70 % of the device's memory (about 200 GB on an MI355X) */
+  int64_t max_class_bytes; /* classes estimated above this are rejected; 0: budget/4 (with the
+                              default budget this rejects the 3-D classes with n_elem = 256 and
+                              those with n_elem = 128 at p >= 4) */
   int32_t max_slots;       /* requests in flight on the device */
   int32_t precision;       /* PMG_FP32_IN_FP64 (default) or PMG_FP64 */
   double tol;              /* relative FP64 residual target, default 1e-10 */

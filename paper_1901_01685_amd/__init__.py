@@ -54,7 +54,8 @@ class Options(C.Structure):
                 ("max_iter", C.c_int32), ("diverge_ratio", C.c_double), ("device", C.c_int32),
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
                 ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32),
-                ("projection", C.c_int32), ("poll_limit", C.c_int32), ("ilut_on_device", C.c_int32)]
+                ("projection", C.c_int32), ("poll_limit", C.c_int32), ("ilut_on_device", C.c_int32),
+                ("tri_waves_per_cu", C.c_int32)]
 
 
 class Result(C.Structure):

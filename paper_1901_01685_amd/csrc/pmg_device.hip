@@ -627,12 +627,16 @@ pmg::TriCtl tri_ctl(pmg_handle h, Workspace& ws, int factor) {
 // device at once (more would only start after others exit), at most one per
 // chunk.
 template <typename T>
-pmg_status size_tri_grid(int device, TriSched& L, TriSched& U) {
+pmg_status size_tri_grid(int device, int waves_per_cu, TriSched& L, TriSched& U) {
   hipDeviceProp_t prop;
   PMG_HIP_OK(hipGetDeviceProperties(&prop, device));
   int per_cu_l = 0, per_cu_u = 0;
   PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_l, pmg::trisolve_lower<T>, 64, 0));
   PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_u, pmg::trisolve_upper<T>, 64, 0));
+  if (waves_per_cu > 0) {
+    per_cu_l = std::min(per_cu_l, waves_per_cu);
+    per_cu_u = std::min(per_cu_u, waves_per_cu);
+  }
   const int64_t cl = (int64_t)std::max(per_cu_l, 1) * prop.multiProcessorCount;
   const int64_t cu = (int64_t)std::max(per_cu_u, 1) * prop.multiProcessorCount;
   const int gl = (int)std::max<int64_t>(1, std::min<int64_t>(cl, (int64_t)L.nch));
@@ -1419,7 +1423,8 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->mass_transfer = PMG_MASS_LUMPED;
   o->projection = PMG_PROJ_DIRECT;
   o->poll_limit = 0;
-  o->ilut_on_device = 0;
+  o->ilut_on_device = 1;
+  o->tri_waves_per_cu = 0;
   return PMG_OK;
 }
 
@@ -1471,7 +1476,8 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
       (o.ordering != PMG_ORDER_NATURAL && o.ordering != PMG_ORDER_NESTED_DISSECTION) || o.nd_leaf < 1 ||
       (o.mass_transfer != PMG_MASS_LUMPED && o.mass_transfer != PMG_MASS_CONSISTENT) ||
       (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64) ||
-      (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT) || o.poll_limit < 0)
+      (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT) || o.poll_limit < 0 ||
+      o.tri_waves_per_cu < 0)
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
@@ -1625,8 +1631,8 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     if ((s = upload_stencil(m, H, h->a_stencil, h->As, mixed))) return s;
     if ((s = upload_tri(m, h->tl, false, mixed))) return s;
     if ((s = upload_tri(m, h->tu, true, mixed))) return s;
-    if ((s = size_tri_grid<double>(o.device, h->tl, h->tu))) return s;
-    if (mixed && (s = size_tri_grid<float>(o.device, h->tl, h->tu))) return s;
+    if ((s = size_tri_grid<double>(o.device, o.tri_waves_per_cu, h->tl, h->tu))) return s;
+    if (mixed && (s = size_tri_grid<float>(o.device, o.tri_waves_per_cu, h->tl, h->tu))) return s;
     if (n1 > 0) {
       const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
       if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;

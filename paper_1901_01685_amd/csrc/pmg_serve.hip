@@ -352,7 +352,7 @@ extern "C" {
 pmg_status pmg_server_default_options(pmg_server_options* o) {
   if (!o) return fail(PMG_EINVAL, "NULL options");
   std::memset(o, 0, sizeof(*o));
-  o->budget_bytes = (int64_t)64 << 30;
+  o->budget_bytes = 0;  // 70 % of the device's memory, taken at pmg_server_create
   o->max_class_bytes = 0;
   o->max_slots = 16;
   o->precision = PMG_FP32_IN_FP64;
@@ -369,14 +369,19 @@ pmg_status pmg_server_create(const pmg_server_options* o, pmg_server* out) {
   *out = nullptr;
   pmg_server_options op;
   if (o) op = *o; else pmg_server_default_options(&op);
-  if (op.budget_bytes <= 0 || op.max_slots < 1 || op.max_slots > 256 || !(op.tol > 0) || op.max_iter < 1 ||
+  if (op.budget_bytes < 0 || op.max_slots < 1 || op.max_slots > 256 || !(op.tol > 0) || op.max_iter < 1 ||
       !(op.diverge_ratio > 0) || (op.precision != PMG_FP64 && op.precision != PMG_FP32_IN_FP64))
     return fail(PMG_EINVAL, "invalid server options");
-  if (op.max_class_bytes <= 0) op.max_class_bytes = op.budget_bytes / 4;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= op.device)
     return fail(PMG_EDEVICE, "no HIP device " + std::to_string(op.device));
   PMG_HIP_OK(hipSetDevice(op.device));
+  if (op.budget_bytes == 0) {
+    hipDeviceProp_t prop;
+    PMG_HIP_OK(hipGetDeviceProperties(&prop, op.device));
+    op.budget_bytes = (int64_t)((double)prop.totalGlobalMem * 0.7);
+  }
+  if (op.max_class_bytes <= 0) op.max_class_bytes = op.budget_bytes / 4;
   std::unique_ptr<pmg_server_s> s(new pmg_server_s());
   s->opt = op;
   s->t0 = std::chrono::steady_clock::now();

@@ -14,6 +14,13 @@
 
 namespace {
 
+// Largest working-row table in LDS (slots, log2), the longest working row
+// the first global-memory tables are sized for, and the most global memory
+// those tables may take together.
+constexpr int kLdsBitsMax = 12;
+constexpr int64_t kGlobalRowStart = 40000;
+constexpr double kGlobalTableBytes = 16.0e9;
+
 template <typename T>
 __global__ void fill_words(int64_t n, T* __restrict__ p, T v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -50,15 +57,29 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
   const int64_t cl = std::max<int64_t>(keep_l, 1), cu = keep_u + 1;
   int64_t maxrow = 1;
   for (int i = 0; i < n; ++i) maxrow = std::max<int64_t>(maxrow, Ap.rp[i + 1] - Ap.rp[i]);
-  // working-row table: 16 slots per entry of the longest row to start with
-  // (rows with fill reach 6-13 times their length; the table is full at 7/8),
-  // doubled while a row outgrows it and LDS allows
+  // working row in LDS: 20 slots per entry of the longest row of A (rows
+  // with fill reach about 16 times their length; a table counts as full at
+  // 7/8), at most 2^12 slots so that three waves share a compute unit.  A
+  // row that outgrows it is factored again in its wave's table in global
+  // memory, which is sized for the longest working rows of the largest
+  // problems and doubled (the factorisation run again) if a row outgrows it.
   int tbits = 9;
-  while ((int64_t(1) << tbits) < 16 * std::max(maxrow, cu) && tbits < 14) ++tbits;
+  while ((int64_t(1) << tbits) < 20 * std::max(maxrow, cu) && tbits < kLdsBitsMax) ++tbits;
   auto lds_of = [&](int tb) { return 12 * (size_t(1) << tb) + 256 * sizeof(int); };
-  const size_t kLdsMax = size_t(152) << 10;
-  while (tbits > 9 && lds_of(tbits) > kLdsMax) --tbits;
-  if ((int64_t)order.size() != n || cu > pmg::ilut::kMaxChunks * pmg::ilut::kWave || lds_of(tbits) > kLdsMax ||
+  auto full_of = [](int tb) { return (int)((int64_t(1) << tb) - (int64_t(1) << tb) / 8); };
+  int gbits = 0;
+  const int64_t nw0 = ((int64_t)n + 63) / 64;  // level-0 words of the lower-part bitmap
+  if (n > full_of(tbits)) {
+    gbits = tbits + 1;
+    while (full_of(gbits) < std::min<int64_t>(n, kGlobalRowStart)) ++gbits;
+    // the level-1 words of that bitmap take the LDS of the table
+    while (8 * ((nw0 + 63) / 64) > 12 * (int64_t(1) << tbits) && tbits < kLdsBitsMax) ++tbits;
+    if (8 * ((nw0 + 63) / 64) > 12 * (int64_t(1) << tbits)) {
+      why = "too many unknowns for the device factorisation's bitmaps";
+      return PMG_EINVAL;
+    }
+  }
+  if ((int64_t)order.size() != n || cu > pmg::ilut::kMaxChunks * pmg::ilut::kWave ||
       (double)n * (double)(cl + cu) > 4.0e9) {
     why = "rows too long for the device factorisation";
     return PMG_EINVAL;
@@ -87,8 +108,36 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
   if ((s = mem.alloc(&fault, 1))) return s;
   if ((s = mem.alloc(&flags, 2))) return s;
   int hflags[2] = {0, 0};
+  int dev = 0;
+  PMG_HIP_OK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  PMG_HIP_OK(hipGetDeviceProperties(&prop, dev));
+  const size_t lds = lds_of(tbits);
+  PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::ilut::ilut_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+  int per_cu = 0;
+  PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmg::ilut::ilut_rows, 64, lds));
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * prop.multiProcessorCount, n));
+  int* gkeys = nullptr;
+  double* gvals = nullptr;
+  unsigned long long* gb0 = nullptr;
+  DevArena gmem;
+  struct ReleaseG {
+    DevArena& m;
+    ~ReleaseG() { m.release(); }
+  } relg{gmem};
   for (;;) {
-    const size_t lds = lds_of(tbits);
+    if (gbits) {
+      if ((double)grid * (12.0 * (double)(int64_t(1) << gbits) + 8.0 * (double)nw0) > kGlobalTableBytes) {
+        why = "a working row outgrew the largest global-memory table";
+        return PMG_EINVAL;
+      }
+      gmem.release();
+      if ((s = gmem.alloc(&gkeys, (size_t)grid << gbits))) return s;
+      if ((s = gmem.alloc(&gvals, (size_t)grid << gbits))) return s;
+      if ((s = gmem.alloc(&gb0, (size_t)grid * (size_t)nw0))) return s;
+      fill<unsigned long long>(gb0, grid * nw0, 0ull);
+    }
     fill<int>(Un, n, -1);
     fill<int>(Uc, (int64_t)n * cu, -1);
     fill<unsigned long long>(reinterpret_cast<unsigned long long*>(Uv), (int64_t)n * cu, pmg::kPending64);
@@ -121,16 +170,14 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     // default bound than the triangular solves'
     A.poll_limit = poll_limit > 0 ? poll_limit : (1 << 26);
     A.tbits = tbits;
+    A.full = full_of(tbits);
     A.order = ord;
-    PMG_HIP_OK(hipFuncSetAttribute((const void*)pmg::ilut::ilut_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-    int dev = 0, per_cu = 0;
-    PMG_HIP_OK(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    PMG_HIP_OK(hipGetDeviceProperties(&prop, dev));
-    PMG_HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pmg::ilut::ilut_rows, 64, lds));
-    const int64_t grid =
-        std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * prop.multiProcessorCount, n));
+    A.gkeys = gkeys;
+    A.gvals = gvals;
+    A.gbits = gbits;
+    A.gfull = gbits ? full_of(gbits) : 0;
+    A.gbits0 = gb0;
+    A.nw0 = (int)nw0;
     pmg::ilut::ilut_rows<<<(unsigned)grid, 64, lds>>>(A);
     PMG_HIP_OK(hipGetLastError());
     PMG_HIP_OK(hipDeviceSynchronize());
@@ -139,11 +186,7 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     PMG_HIP_OK(hipMemcpy(&hfault, fault, sizeof hfault, hipMemcpyDeviceToHost));
     if (hfault) return fail(PMG_EDEVICE, "device ILUT: a row waited past its poll bound");
     if (!hflags[1]) break;
-    if (lds_of(tbits + 1) > kLdsMax) {
-      why = "a working row outgrew the largest table";
-      return PMG_EINVAL;
-    }
-    ++tbits;
+    gbits = gbits ? gbits + 1 : tbits + 1;
   }
   if (hflags[0] < n) {
     bad_row = hflags[0];

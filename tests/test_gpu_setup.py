@@ -3,7 +3,10 @@ GPU kernel): the factors must be identical, bit for bit, to those of the host
 factorisation of the same permuted operator, which the host tests pin
 against the oracle.  Covers the three readings of rule 2, the nested
 dissection and natural orderings, both geometries, the cube and the
-non-symmetric benchmark-2 operator, and the zero-pivot branch."""
+non-symmetric benchmark-2 operator, and the zero-pivot branch.  In the
+2-D degree-5 cases at h = 1/128 and 1/256 and the degree-3 cube at h = 1/24
+thousands of working rows outgrow the kernel's LDS table (4096 slots) and are
+factored again in the wave's table in global memory."""
 import numpy as np
 import pytest
 
@@ -24,6 +27,8 @@ CASES = [
     dict(dim=2, degree=3, n_elem=64, ilut_limit_mode=pmg.LIMIT_PER_ROW),
     dict(dim=2, degree=4, n_elem=48, ordering=pmg.ORDER_NATURAL),
     dict(dim=2, degree=2, n_elem=64, ilut_fill=2.0),
+    dict(dim=2, degree=5, n_elem=256),
+    dict(dim=3, degree=3, n_elem=24),
 ]
 
 
