@@ -18,6 +18,7 @@ event profiling requires), and the FP64 CPU oracle timed on a bounded sample
 of the same workload on this host's cores.
 """
 import argparse
+import subprocess
 import hashlib
 import json
 import os
@@ -75,15 +76,15 @@ def _traffic(kernel_class, workload):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0, nel_s=128):
+def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0, nel_s=256, dim=2):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
-    the workload: the same problem family (2-D unit square, same p) at
+    the workload: the same problem family (unit square or cube, same p) at
     h = 1/nel_s, V-cycles repeated for about budget_s seconds; reported in
     unknowns x V-cycles / second."""
     import numpy as np
     import oracle
     t0 = time.perf_counter()
-    o = oracle.Oracle(2, p, nel_s, pde=pde)
+    o = oracle.Oracle(dim, p, nel_s, pde=pde)
     t_setup = time.perf_counter() - t0
     b = o.f()
     x = np.zeros(o.n)
@@ -104,9 +105,11 @@ def cpu_baseline(p, nel_full, n_full, budget_s=20.0, pde=0, nel_s=128):
         "cores": 1,
         "kind": "oracle",
         "host": {"cpu_model": model, "nproc": ncpu},
-        "sample": (f"oracle V-cycles on the same 2-D unit-square {'CDR ' if pde else ''}p={p} problem at h=1/{nel_s} "
+        "sample": (f"oracle V-cycles on the same {'2-D unit-square' if dim == 2 else '3-D unit-cube'} "
+                   f"{'CDR ' if pde else ''}p={p} problem at h=1/{nel_s} "
                    f"(n={o.n}; the timed workload is h=1/{nel_full}, n={n_full}): {cycles} cycles in "
-                   f"{el:.1f} s, setup {t_setup:.1f} s excluded; single-threaded C, FP64"),
+                   f"{el:.1f} s, setup {t_setup:.1f} s excluded; single-threaded C, FP64, in a process of its "
+                   f"own beside the GPU legs"),
     }
 
 
@@ -357,6 +360,8 @@ def main():
     ap.add_argument("--serve-sample-cost", type=float, default=2.5e10,
                     help="default run: serve only classes whose host ILUT work n*M^2 is at most this")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default run")
+    ap.add_argument("--cpu-nel", type=int, default=256, help="elements per direction of the CPU oracle's sample")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 512 MiB (3 times), the reference for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -365,6 +370,20 @@ def main():
         print("bench.py measures one GPU: the solve phase here runs on a single MI355X; "
               "multi-GPU sharding is a design note only (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_baseline_only:
+        n_full = (args.nel + args.degree - 2) ** args.dim
+        print(json.dumps(cpu_baseline(args.degree, args.nel, n_full, args.cpu_budget, pde=int(args.pde == "cdr"),
+                                      nel_s=args.cpu_nel, dim=args.dim)), flush=True)
+        return
+    # the CPU oracle baseline runs in a process of its own, beside the GPU legs
+    cpu_proc = None
+    if not (args.no_cpu_baseline or args.serve or args.calibrate_copy):
+        cpu_proc = subprocess.Popen(
+            [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--dim", str(args.dim),
+             "--degree", str(args.degree), "--nel", str(args.nel), "--pde", args.pde,
+             "--cpu-budget", str(args.cpu_budget), "--cpu-nel", str(args.cpu_nel if args.dim == 2 else 16)],
+            stdout=subprocess.PIPE, text=True)
 
     import torch
     import paper_1901_01685_amd as pmg
@@ -384,6 +403,7 @@ def main():
         return
     t0 = time.perf_counter()
     pde = pmg.PDE_CDR if args.pde == "cdr" else pmg.PDE_POISSON
+    print(f"# setting up dim={args.dim} p={args.degree} h=1/{args.nel}", file=sys.stderr, flush=True)
     s = pmg.Solver(dim=args.dim, degree=args.degree, n_elem=args.nel, pde=pde, device=0,
                    projection=pmg.PROJ_INDIRECT if args.projection == "indirect" else pmg.PROJ_DIRECT,
                    mass_transfer=pmg.MASS_CONSISTENT if args.mass == "consistent" else pmg.MASS_LUMPED)
@@ -518,9 +538,10 @@ def main():
         sargs = argparse.Namespace(**vars(args))
         sargs.serve_requests, sargs.serve_warmup, sargs.closed_requests = 400, 50, 200
         out["serving"] = serve_leg(sargs, sample_cost=args.serve_sample_cost)
-    if not args.no_cpu_baseline:
-        print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.degree, args.nel, n, args.cpu_budget, pde=pde)
+    if cpu_proc is not None:
+        print("# waiting for the CPU oracle baseline", file=sys.stderr, flush=True)
+        so, _ = cpu_proc.communicate(timeout=900)
+        out["cpu_baseline"] = json.loads(so.strip().splitlines()[-1]) if cpu_proc.returncode == 0 else None
     print(json.dumps(out), flush=True)
 
 

@@ -483,20 +483,36 @@ __device__ __forceinline__ bool factor_row(const Args& A, int i, int* keys, doub
     }
     if (lane == 0) tv_st(vals + sk, lk);
     __syncthreads();
+    // w -= l_k (row k of U): the columns of row k are distinct, so all its
+    // slots are updated together; the first probe of every slot is loaded
+    // before any is used
+    int pk[kMaxChunks];
+    double pv[kMaxChunks];
 #pragma unroll
     for (int c = 0; c < kMaxChunks; ++c) {
-      if (c >= nch) break;
       const int s = c * kWave + lane;
       const int j = uc[c];
-      if (s >= 1 && s < cntk && s < A.cu && j >= 0 && j < A.n) {
-        bool fresh;
-        const double prod = lk * uv[c];
-        const int t = subtract(keys, vals, j, prod, tbits, &sh[0], fresh);
-        if (t < 0) sh[3] = 1;
-        if (GLOBAL && fresh && j < i) mark_lower(B, j);
-      }
-      __syncthreads();
+      const bool act = c < nch && s >= 1 && s < cntk && s < A.cu && j >= 0 && j < A.n;
+      uc[c] = act ? j : -1;
+      const unsigned q = act ? slot_of(j, tbits) : 0u;
+      pk[c] = act ? tk_ld(keys + q) : -2;
+      pv[c] = act ? tv_ld(vals + q) : 0.0;
     }
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) {
+      const int j = uc[c];
+      if (j < 0) continue;
+      const double prod = lk * uv[c];
+      if (pk[c] == j) {
+        tv_st(vals + slot_of(j, tbits), pv[c] - prod);
+        continue;
+      }
+      bool fresh;
+      const int t = subtract(keys, vals, j, prod, tbits, &sh[0], fresh);
+      if (t < 0) sh[3] = 1;
+      if (GLOBAL && fresh && j < i) mark_lower(B, j);
+    }
+    __syncthreads();
     over = sh[0] > full || sh[3] != 0;
     if (over && !last) return false;
   }
