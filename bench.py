@@ -70,9 +70,9 @@ def _traffic(kernel_class, workload):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_source_hash") != _kernel_source_hash() or d.get("workload") != workload:
+    if d.get("kernel_source_hash") != _kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel_class)
+    k = d.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel_class)
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -220,8 +220,9 @@ def serve_leg(args, sample_cost=None):
     freqs = rng.integers(1, 5, size=(total, 3))
     gaps = rng.exponential(1.0 / args.rate, size=total)
     arrivals = np.cumsum(gaps)
-    srv = pmg.Server(max_slots=args.slots, precision=pmg.FP32_IN_FP64, tol=1e-10)
-    opts = srv.options
+    srv = pmg.Server(max_slots=args.slots, precision=pmg.FP32_IN_FP64, tol=1e-10,
+                     tri_waves_per_cu=args.serve_tri_waves)
+    opts = srv.effective_options()
     all_classes = sorted(set(zip(dims.tolist(), degs.tolist(), nels.tolist())))
     in_sample = {c for c in all_classes if sample_cost is None or class_setup_cost(*c) <= sample_cost}
     t0 = time.perf_counter()
@@ -229,6 +230,7 @@ def serve_leg(args, sample_cost=None):
     for c in all_classes:
         if c not in in_sample:
             continue
+        print(f"# class {c}: setting up", file=sys.stderr, flush=True)
         st = srv.prepare(*c)
         if st == pmg.OK:
             admitted.add(c)
@@ -304,10 +306,10 @@ def serve_leg(args, sample_cost=None):
     srv.close()
     return {
         "workload": "serving: 2-D/3-D unit square/cube, p in 2..5, h in 1/32..1/256, freq 1..4, Poisson arrivals",
-        "seed": args.seed, "slots": args.slots, "tol": 1e-10,
+        "seed": args.seed, "slots": args.slots, "tol": 1e-10, "tri_waves_per_cu": args.serve_tri_waves,
         "budget_GB": round(opts.budget_bytes / 1e9, 1), "class_limit_GB": round(opts.max_class_bytes / 1e9, 1),
         "sample": (None if sample_cost is None else
-                   f"classes whose host ILUT work n*M^2 <= {sample_cost:.1e} (setup bounded for this run): "
+                   f"classes whose ILUT work n*M^2 <= {sample_cost:.1e} (setup bounded for this run): "
                    f"{len(in_sample)} of {len(all_classes)}"),
         "classes_admitted": len(admitted), "classes_rejected": [list(c) for c in rejected_classes],
         "setup_s": round(t_setup, 1),
@@ -325,7 +327,7 @@ def serve_bench(args):
     """--serve: the whole serving workload (every class the budget admits)."""
     out = {"metric": METRIC, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
            "dtype": "f32-in-f64", "data": "synthetic"}
-    leg = serve_leg(args)
+    leg = serve_leg(args, sample_cost=args.serve_sample_cost)
     out["value"] = leg["served_solves_per_s"]
     out["config"] = {"workload": leg["workload"]}
     out.update(leg)
@@ -357,9 +359,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--closed-requests", type=int, default=600)
-    ap.add_argument("--serve-sample-cost", type=float, default=2.5e10,
-                    help="default run: serve only classes whose host ILUT work n*M^2 is at most this")
+    ap.add_argument("--serve-sample-cost", type=float, default=None,
+                    help="serve only classes whose ILUT work n*M^2 is at most this (default run: 2.5e10; --serve: all)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default run")
+    ap.add_argument("--serve-tri-waves", type=int, default=0,
+                    help="waves per CU of each slot's triangular-solve grid (0: as many as fit)")
     ap.add_argument("--cpu-nel", type=int, default=256, help="elements per direction of the CPU oracle's sample")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -537,7 +541,7 @@ def main():
         print("# serving leg", file=sys.stderr, flush=True)
         sargs = argparse.Namespace(**vars(args))
         sargs.serve_requests, sargs.serve_warmup, sargs.closed_requests = 400, 50, 200
-        out["serving"] = serve_leg(sargs, sample_cost=args.serve_sample_cost)
+        out["serving"] = serve_leg(sargs, sample_cost=args.serve_sample_cost or 2.5e10)
     if cpu_proc is not None:
         print("# waiting for the CPU oracle baseline", file=sys.stderr, flush=True)
         so, _ = cpu_proc.communicate(timeout=900)

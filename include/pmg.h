@@ -404,6 +404,9 @@ typedef struct {
   int32_t device;          /* HIP device ordinal */
   int32_t setup_threads;   /* host threads per class setup; 0 = default */
   double diverge_ratio;    /* PMG_EDIVERGED above this relative residual, default 1e10 */
+  int32_t tri_waves_per_cu; /* pmg_options.tri_waves_per_cu of every class handle: waves per
+                               compute unit of each slot's triangular-solve grid (0, the
+                               default: as many as fit; the slots' grids then take turns) */
 } pmg_server_options;
 
 typedef struct {
@@ -445,6 +448,9 @@ pmg_status pmg_server_poll(pmg_server s, int64_t ticket, int32_t *done, double *
 /* Changes slots and precision; waits until no request is queued or active. */
 pmg_status pmg_server_configure(pmg_server s, int32_t max_slots, int32_t precision);
 pmg_status pmg_server_get_stats(pmg_server s, pmg_server_stats *st);
+/* The options in force, with the defaults filled in (budget_bytes and
+ * max_class_bytes as taken from the device at pmg_server_create). */
+pmg_status pmg_server_get_options(pmg_server s, pmg_server_options *o);
 /* Seconds since the server was created (the clock of pmg_request_info). */
 double pmg_server_clock(pmg_server s);
 /* Stops the threads (waiting for active requests) and frees everything. */

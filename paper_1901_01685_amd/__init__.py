@@ -83,7 +83,7 @@ class Info(C.Structure):
 class ServerOptions(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("max_class_bytes", C.c_int64), ("max_slots", C.c_int32),
                 ("precision", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("device", C.c_int32),
-                ("setup_threads", C.c_int32), ("diverge_ratio", C.c_double)]
+                ("setup_threads", C.c_int32), ("diverge_ratio", C.c_double), ("tri_waves_per_cu", C.c_int32)]
 
 
 class RequestInfo(C.Structure):
@@ -141,6 +141,7 @@ SIGNATURES = {
     "pmg_server_configure": (C.c_int, [_VP, C.c_int32, C.c_int32]),
     "pmg_server_get_stats": (C.c_int, [_VP, C.POINTER(ServerStats)]),
     "pmg_server_clock": (C.c_double, [_VP]),
+    "pmg_server_get_options": (C.c_int, [_VP, C.POINTER(ServerOptions)]),
     "pmg_server_destroy": (C.c_int, [_VP]),
     "pmg_status_str": (C.c_char_p, [C.c_int]),
     "pmg_last_error": (C.c_char_p, []),
@@ -478,3 +479,9 @@ class Server:
 
     def clock(self):
         return lib().pmg_server_clock(self._h)
+
+    def effective_options(self):
+        """The options in force, defaults filled in (pmg_server_get_options)."""
+        o = ServerOptions()
+        _check(lib().pmg_server_get_options(self._h, C.byref(o)))
+        return o

@@ -56,11 +56,13 @@ struct Args {
   int* Un;       // entries of each row of U (with the diagonal), -1 until written
   unsigned* state;  // [0] ticket counter, [kTicketStride] exited waves
   unsigned* fault;  // set when a wait reached poll_limit
-  int* flags;       // [0] smallest row with a zero or non-finite pivot (n: none), [1] table overflow
+  int* flags;       // [0] smallest row with a zero or non-finite pivot (n: none), [1] bit 0: table
+                    // overflow, bit 1: a pivot outside the working row or not ticketed before its row
   int poll_limit;
   int tbits;         // working row in LDS: 1 << tbits slots
   int full;          // occupied slots beyond which that table overflows
   const int* order;  // ticket -> row: every row after the rows it can depend on
+  const int* pos;    // row -> ticket (the inverse of order)
   // rows that outgrow the LDS table are factored again in a table of
   // 1 << gbits slots in global memory, one per wave (gbits 0: none)
   int* gkeys;        // gridDim.x << gbits
@@ -88,20 +90,23 @@ __device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
 }
 
 // The working row is touched only by the wave that owns it, in LDS or in
-// its own part of global memory; its accesses are relaxed atomics at
-// workgroup scope (plain loads and stores on LDS), so the workgroup barriers
-// between the phases of a row order them in either memory.
+// its own part of global memory.  Its accesses are relaxed atomics at agent
+// scope, the scope of the atomics that insert into it (compare-and-swap of a
+// key, OR into the pivot bitmap): a load is then never served from a copy of
+// the line cached by the CU before such an atomic changed it.  On LDS they
+// are plain accesses.  The workgroup barriers between the phases of a row
+// order them.
 __device__ __forceinline__ int tk_ld(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void tk_st(int* p, int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double tv_ld(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void tv_st(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool is_marker(double v) {
@@ -337,7 +342,7 @@ struct LowerBits {
 };
 
 __device__ __forceinline__ unsigned long long bits_ld(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void mark_lower(const LowerBits& B, int j) {
@@ -383,10 +388,10 @@ __device__ __forceinline__ void clear_lower(const LowerBits& B, int i, int lane)
     unsigned long long m = bits_ld(B.l1 + wi);
     while (m) {
       const int b = __ffsll((long long)m) - 1;
-      __hip_atomic_store(B.l0 + (wi << 6) + b, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(B.l0 + (wi << 6) + b, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       m &= m - 1;
     }
-    __hip_atomic_store(B.l1 + wi, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store(B.l1 + wi, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -401,8 +406,8 @@ __device__ __forceinline__ void clear_lower(const LowerBits& B, int i, int lane)
 // GLOBAL: the table is the wave's in global memory and the pivots are found
 // through the bitmaps B; otherwise (LDS) by a scan of the table.
 template <bool GLOBAL>
-__device__ __forceinline__ bool factor_row(const Args& A, int i, int* keys, double* vals, int tbits, int full,
-                                           int* hist, int* sh, int lane, int nch, bool& gave_up, bool last,
+__device__ __forceinline__ bool factor_row(const Args& A, int i, int tk, int* keys, double* vals, int tbits,
+                                           int full, int* hist, int* sh, int lane, int nch, bool& gave_up, bool last,
                                            const LowerBits& B) {
   // every product and difference rounded on its own, as on the host (hipcc
   // would otherwise fuse w_j - l_k u_kj into one FMA)
@@ -457,6 +462,13 @@ __device__ __forceinline__ bool factor_row(const Args& A, int i, int* keys, doub
       k = wave_min(cand);
     }
     if (k == 0x7fffffff) break;
+    // a row only ever waits for rows ticketed before it (so the smallest
+    // unfinished ticket never waits); a pivot that breaks this could only come
+    // from a corrupted working row: report it (the host factors instead)
+    if (A.pos[k] >= tk) {
+      if (lane == 0) atomicOr(&A.flags[1], 2);
+      break;
+    }
     kprev = k;
     // the first probe for w_k travels with the loads of row k of U
     const unsigned s0 = slot_of(k, tbits);
@@ -469,6 +481,10 @@ __device__ __forceinline__ bool factor_row(const Args& A, int i, int* keys, doub
     double wk = v0;
     if (k0 != k) {
       sk = find(keys, k, tbits);
+      if (sk < 0) {
+        if (lane == 0) atomicOr(&A.flags[1], 2);
+        break;
+      }
       wk = tv_ld(vals + sk);
     }
     if (GLOBAL && wk == 0.0) continue;  // the scan skips these
@@ -636,8 +652,8 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
     const int tk = __builtin_amdgcn_readfirstlane((int)atomicAdd(A.state, lane == 0 ? 1u : 0u));
     if (tk >= A.n) break;
     const int i = A.order[tk];
-    if (!factor_row<false>(A, i, keys, vals, A.tbits, A.full, hist, sh, lane, nch, gave_up, A.gbits == 0, B))
-      factor_row<true>(A, i, gk, gv, A.gbits, A.gfull, hist, sh, lane, nch, gave_up, true, B);
+    if (!factor_row<false>(A, i, tk, keys, vals, A.tbits, A.full, hist, sh, lane, nch, gave_up, A.gbits == 0, B))
+      factor_row<true>(A, i, tk, gk, gv, A.gbits, A.gfull, hist, sh, lane, nch, gave_up, true, B);
   }
   // the last wave out clears the counters for the next launch
   unsigned* exited = A.state + kTicketStride;

@@ -141,6 +141,7 @@ struct pmg_server_s {
     o.device = opt.device;
     o.setup_threads = opt.setup_threads;
     o.max_iter = opt.max_iter;
+    o.tri_waves_per_cu = opt.tri_waves_per_cu;
     c->setting_up = true;
     lk.unlock();
     auto t = std::chrono::steady_clock::now();
@@ -361,6 +362,7 @@ pmg_status pmg_server_default_options(pmg_server_options* o) {
   o->device = 0;
   o->setup_threads = 0;
   o->diverge_ratio = 1e10;
+  o->tri_waves_per_cu = 0;
   return PMG_OK;
 }
 
@@ -370,7 +372,8 @@ pmg_status pmg_server_create(const pmg_server_options* o, pmg_server* out) {
   pmg_server_options op;
   if (o) op = *o; else pmg_server_default_options(&op);
   if (op.budget_bytes < 0 || op.max_slots < 1 || op.max_slots > 256 || !(op.tol > 0) || op.max_iter < 1 ||
-      !(op.diverge_ratio > 0) || (op.precision != PMG_FP64 && op.precision != PMG_FP32_IN_FP64))
+      !(op.diverge_ratio > 0) || (op.precision != PMG_FP64 && op.precision != PMG_FP32_IN_FP64) ||
+      op.tri_waves_per_cu < 0)
     return fail(PMG_EINVAL, "invalid server options");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= op.device)
@@ -530,6 +533,15 @@ pmg_status pmg_server_get_stats(pmg_server s, pmg_server_stats* st) {
   for (auto& sl : s->slots) st->slots_active += sl.req ? 1 : 0;
   st->queued = (int32_t)s->queue.size();
   st->bytes_in_use = s->bytes_in_use;
+  return PMG_OK;
+}
+
+pmg_status pmg_server_get_options(pmg_server s, pmg_server_options* o) {
+  if (!s || !o) return fail(PMG_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *o = s->opt;
+  o->max_slots = s->max_slots;
+  o->precision = s->precision;
   return PMG_OK;
 }
 

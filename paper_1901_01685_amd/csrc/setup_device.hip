@@ -18,7 +18,7 @@ namespace {
 // the first global-memory tables are sized for, and the most global memory
 // those tables may take together.
 constexpr int kLdsBitsMax = 12;
-constexpr int64_t kGlobalRowStart = 40000;
+constexpr int64_t kGlobalRowStart = 100000;
 constexpr double kGlobalTableBytes = 16.0e9;
 
 template <typename T>
@@ -90,7 +90,8 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     ~Release() { m.release(); }
   } rel{mem};
   int64_t *rp = nullptr;
-  int *ci = nullptr, *Lc = nullptr, *Ln = nullptr, *Uc = nullptr, *Un = nullptr, *flags = nullptr, *ord = nullptr;
+  int *ci = nullptr, *Lc = nullptr, *Ln = nullptr, *Uc = nullptr, *Un = nullptr, *flags = nullptr, *ord = nullptr,
+      *pos = nullptr;
   double *v = nullptr, *Lv = nullptr, *Uv = nullptr;
   unsigned *state = nullptr, *fault = nullptr;
   pmg_status s;
@@ -98,6 +99,17 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
   if ((s = mem.upload(&ci, Ap.ci.data(), Ap.ci.size()))) return s;
   if ((s = mem.upload(&v, Ap.v.data(), Ap.v.size()))) return s;
   if ((s = mem.upload(&ord, order.data(), order.size()))) return s;
+  {
+    std::vector<int32_t> inv((size_t)n, -1);
+    for (int t = 0; t < n; ++t) {
+      if (order[t] < 0 || order[t] >= n || inv[order[t]] >= 0) {
+        why = "the ticket order is not a permutation";
+        return PMG_EINVAL;
+      }
+      inv[order[t]] = t;
+    }
+    if ((s = mem.upload(&pos, inv.data(), inv.size()))) return s;
+  }
   if ((s = mem.alloc(&Lc, (size_t)n * cl))) return s;
   if ((s = mem.alloc(&Lv, (size_t)n * cl))) return s;
   if ((s = mem.alloc(&Ln, n))) return s;
@@ -172,6 +184,7 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     A.tbits = tbits;
     A.full = full_of(tbits);
     A.order = ord;
+    A.pos = pos;
     A.gkeys = gkeys;
     A.gvals = gvals;
     A.gbits = gbits;
@@ -185,6 +198,10 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     PMG_HIP_OK(hipMemcpy(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost));
     PMG_HIP_OK(hipMemcpy(&hfault, fault, sizeof hfault, hipMemcpyDeviceToHost));
     if (hfault) return fail(PMG_EDEVICE, "device ILUT: a row waited past its poll bound");
+    if (hflags[1] & 2) {
+      why = "device ILUT met an inconsistent working row";
+      return PMG_EINVAL;
+    }
     if (!hflags[1]) break;
     gbits = gbits ? gbits + 1 : tbits + 1;
   }
