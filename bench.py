@@ -362,7 +362,7 @@ def main():
     ap.add_argument("--serve-sample-cost", type=float, default=None,
                     help="serve only classes whose ILUT work n*M^2 is at most this (default run: 2.5e10; --serve: all)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default run")
-    ap.add_argument("--serve-tri-waves", type=int, default=0,
+    ap.add_argument("--serve-tri-waves", type=int, default=1,
                     help="waves per CU of each slot's triangular-solve grid (0: as many as fit)")
     ap.add_argument("--cpu-nel", type=int, default=256, help="elements per direction of the CPU oracle's sample")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)

@@ -170,6 +170,12 @@ typedef struct {
                                pmg_info.ilut_on_device).  0: on the host threads. */
   int32_t tri_waves_per_cu; /* waves per compute unit of the triangular solves' persistent
                                grid; 0 (default): as many as fit at once */
+  int32_t segment_rows;     /* the triangular-solve schedules cut the rows into segments,
+                               runs of whole grid lines inside one block of the nested
+                               dissection holding at most this many rows (one line at
+                               least), and each segment into chunks of 64 rows; 0 (default):
+                               one line per segment when a line holds 64 rows or more,
+                               otherwise up to 512 rows */
 } pmg_options;
 
 typedef struct {
@@ -186,8 +192,8 @@ typedef struct {
   int32_t nlev;               /* levels of the p = 1 hierarchy incl. the direct one */
   int32_t n_coarsest;         /* unknowns of the direct solve */
   int64_t nnz_a1;             /* nnz of the finest p = 1 operator */
-  int32_t segments;           /* lines of the triangular-solve schedule */
-  int32_t seg_len;            /* rows per line */
+  int32_t segments;           /* segments of the triangular-solve schedule (pmg_options.segment_rows) */
+  int32_t seg_len;            /* rows per grid line */
   int32_t dag_levels_l, dag_levels_u; /* depth of the L and U dependency DAGs (rows) */
   int32_t chunks_l, chunks_u;             /* chunks of the triangular-solve schedules */
   int32_t chunk_levels_l, chunk_levels_u; /* depth of their chunk dependency graphs */
@@ -349,7 +355,8 @@ pmg_status pmg_export_perm(pmg_handle h, int32_t *out);
  * chunk, the chunks it reads), 3 off_ptr, 4 off_w, 5 off_col, 6 in_ptr,
  * 7 in_w, 8 in_j (int32 elements), 9 off_val, 10 in_val, 11 diag (double
  * elements; diag for the upper factor only), 12 chunk_row, 13 chunk_len
- * (first row and rows of each chunk, int32).  *count receives the number of
+ * (first row and rows of each chunk, int32), 14 segment starts (first row
+ * of each segment, then n; int32).  *count receives the number of
  * elements; out, when non-NULL, must hold that many.  Chunks are numbered
  * by first row.  EINVAL for an unknown factor or field. */
 pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int64_t *count, void *out);
@@ -405,8 +412,9 @@ typedef struct {
   int32_t setup_threads;   /* host threads per class setup; 0 = default */
   double diverge_ratio;    /* PMG_EDIVERGED above this relative residual, default 1e10 */
   int32_t tri_waves_per_cu; /* pmg_options.tri_waves_per_cu of every class handle: waves per
-                               compute unit of each slot's triangular-solve grid (0, the
-                               default: as many as fit; the slots' grids then take turns) */
+                               compute unit of each slot's triangular-solve grid; default 1,
+                               so that the grids of several slots are resident together
+                               (0: as many as fit, and the slots' grids take turns) */
 } pmg_server_options;
 
 typedef struct {

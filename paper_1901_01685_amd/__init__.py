@@ -55,7 +55,7 @@ class Options(C.Structure):
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
                 ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32),
                 ("projection", C.c_int32), ("poll_limit", C.c_int32), ("ilut_on_device", C.c_int32),
-                ("tri_waves_per_cu", C.c_int32)]
+                ("tri_waves_per_cu", C.c_int32), ("segment_rows", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -369,7 +369,8 @@ class Solver:
         return out
 
     SCHEDULE_FIELDS = ("order", "wptr", "deps", "off_ptr", "off_w", "off_col",
-                       "in_ptr", "in_w", "in_j", "off_val", "in_val", "diag", "chunk_row", "chunk_len")
+                       "in_ptr", "in_w", "in_j", "off_val", "in_val", "diag", "chunk_row", "chunk_len",
+                       "seg_start")
 
     def export_schedule(self, factor):
         """Schedule and chunk-sliced layout of the lower (0) or upper (1)

@@ -95,6 +95,8 @@ pmg_handle_s::~pmg_handle_s() {
 namespace {
 
 constexpr int kMaxCsrBlocks = 4096;
+// default upper bound of a triangular-solve segment's rows (pmg_options.segment_rows)
+constexpr int kSegmentRows = 512;
 
 int pick_group(double avg) {
   if (avg >= 128) return 64;
@@ -108,17 +110,22 @@ unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 unsigned csr_grid(int nrows, int G) { return std::min<unsigned>(nblocks(nrows, 256 / G), kMaxCsrBlocks); }
 
-// Chunk boundaries of the segment-ordered triangular solves.  A segment is
-// cut into chunks of 64 rows, counted in processing coordinates (forward
-// solve: position in the segment; backward solve: position from its end),
-// with the first chunk shortened by an offset o in [0, 64).  The offset of
-// each segment is chosen, in processing order, among even values so that
-// the segment's chunks reach the lowest levels of the chunk dependency graph
-// given the chunks of the segments before it: a chunk of one grid line reads
-// a few rows past its own end in the previous lines, and with aligned
-// boundaries it would wait for two chunks of each of them instead of one.
-// Returns per segment the processing-coordinate chunk starts (plus seg_len).
-std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int nseg, bool upper) {
+// Chunk boundaries of the segment-ordered triangular solves.  A segment (a
+// run of whole grid lines inside one block of the nested dissection, rows
+// seg[s] .. seg[s+1]-1) is cut into chunks of 64 rows, counted in processing
+// coordinates (forward solve: position in the segment; backward solve:
+// position from its end), with the first chunk shortened by an offset o in
+// [0, 64).  The offset of each segment is chosen, in processing order, among
+// even values so that the segment's chunks reach the lowest levels of the
+// chunk dependency graph given the chunks of the segments before it: a chunk
+// of one grid line reads a few rows past its own end in the previous lines,
+// and with aligned boundaries it would wait for two chunks of each of them
+// instead of one.  Returns per segment the processing-coordinate chunk starts
+// (plus the segment's length).
+std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, const std::vector<int32_t>& seg,
+                                            const std::vector<int32_t>& seg_of, bool upper) {
+  const int nseg = (int)seg.size() - 1;
+  auto len = [&](int t) { return seg[t + 1] - seg[t]; };
   // per segment: for each segment it reads, the furthest processing position
   // read by the row at each processing position (-1: none)
   struct Dep {
@@ -129,29 +136,30 @@ std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int 
   std::vector<int> slot(nseg, -1);
   for (int s = 0; s < nseg; ++s) {
     std::vector<int> touched;
-    for (int x = 0; x < seg_len; ++x) {
-      const int row = s * seg_len + x;
-      const int xp = upper ? seg_len - 1 - x : x;
+    const int ls = len(s);
+    for (int x = 0; x < ls; ++x) {
+      const int row = seg[s] + x;
+      const int xp = upper ? ls - 1 - x : x;
       for (int64_t k = T.rp[row] + (upper ? 1 : 0); k < T.rp[row + 1]; ++k) {
-        const int t = T.ci[k] / seg_len, y = T.ci[k] % seg_len;
+        const int t = seg_of[T.ci[k]], y = T.ci[k] - seg[t];
         if (t == s) continue;
         if (slot[t] < 0) {
           slot[t] = (int)deps[s].size();
-          deps[s].push_back(Dep{t, std::vector<int>(seg_len, -1)});
+          deps[s].push_back(Dep{t, std::vector<int>(ls, -1)});
           touched.push_back(t);
         }
         int& r = deps[s][slot[t]].reach[xp];
-        r = std::max(r, upper ? seg_len - 1 - y : y);
+        r = std::max(r, upper ? len(t) - 1 - y : y);
       }
     }
     for (int t : touched) slot[t] = -1;
   }
   std::vector<std::vector<int>> bounds(nseg), levels(nseg);
-  auto cut = [&](int o) {
+  auto cut = [&](int o, int ls) {
     std::vector<int> b{0};
-    for (int a = 64 - o; a < seg_len; a += 64)
+    for (int a = 64 - o; a < ls; a += 64)
       if (a > 0) b.push_back(a);
-    b.push_back(seg_len);
+    b.push_back(ls);
     return b;
   };
   std::vector<int> lv;
@@ -160,7 +168,7 @@ std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int 
     int best_last = INT32_MAX;
     int64_t best_sum = 0;
     for (int o = 0; o < 64; o += 2) {
-      const std::vector<int> b = cut(o);
+      const std::vector<int> b = cut(o, len(s));
       lv.assign(b.size() - 1, 0);
       int prev = 0;
       int64_t sum = 0;
@@ -192,24 +200,33 @@ std::vector<std::vector<int>> choose_chunks(const pmg::Csr& T, int seg_len, int 
 // (the layout is described with pmg::TriDev).  Forward: row i reads rows
 // j < i; backward (upper == true): row i reads rows j > i and chunks are
 // finished from the end of their segment.
-pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& S) {
+pmg_status build_schedule(const pmg::Csr& T, const std::vector<int32_t>& seg, int seg_len, bool upper,
+                          TriSched& S) {
   const int n = T.nrows;
   S.seg_len = seg_len;
   if ((int64_t)n * 8 >= INT32_MAX) return fail(PMG_EINVAL, "triangular factor has more than 2^28 rows");
+  if (seg.size() < 2 || seg.front() != 0 || seg.back() != n) return fail(PMG_EINVAL, "bad schedule segments");
   S.nrows = n;
-  S.nseg = n / seg_len;
+  S.nseg = (int)seg.size() - 1;
+  S.seg_start = seg;
+  std::vector<int32_t> seg_of(n);
+  for (int s = 0; s < S.nseg; ++s) {
+    if (seg[s + 1] <= seg[s]) return fail(PMG_EINVAL, "bad schedule segments");
+    for (int r = seg[s]; r < seg[s + 1]; ++r) seg_of[r] = s;
+  }
   // chunk geometry in natural order (segment-major, ascending rows)
-  const std::vector<std::vector<int>> bounds = choose_chunks(T, seg_len, S.nseg, upper);
+  const std::vector<std::vector<int>> bounds = choose_chunks(T, seg, seg_of, upper);
   S.chunk_row.clear();
   S.chunk_len.clear();
   for (int s = 0; s < S.nseg; ++s) {
     const std::vector<int>& b = bounds[s];
+    const int ls = seg[s + 1] - seg[s];
     const int K = (int)b.size() - 1;
     for (int k = 0; k < K; ++k) {
       const int kp = upper ? K - 1 - k : k;  // processing index of the k-th chunk by rows
-      const int a = upper ? seg_len - b[kp + 1] : b[kp];
-      const int e = upper ? seg_len - b[kp] : b[kp + 1];
-      S.chunk_row.push_back(s * seg_len + a);
+      const int a = upper ? ls - b[kp + 1] : b[kp];
+      const int e = upper ? ls - b[kp] : b[kp + 1];
+      S.chunk_row.push_back(seg[s] + a);
       S.chunk_len.push_back(e - a);
     }
   }
@@ -265,7 +282,7 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
   for (int qq = 0; qq < nq; ++qq) {
     const int q = upper ? nq - 1 - qq : qq;
     const int r0 = S.chunk_row[q], r1 = r0 + S.chunk_len[q];
-    const int s = r0 / seg_len;
+    const int s = seg_of[r0];
     touched.clear();
     auto add_dep = [&](int qd) {
       if (!mark[qd]) {
@@ -274,8 +291,8 @@ pmg_status build_schedule(const pmg::Csr& T, int seg_len, bool upper, TriSched& 
       }
     };
     // the previous chunk of the own segment, always
-    if (!upper && r0 > s * seg_len) add_dep(q - 1);
-    if (upper && r1 < (s + 1) * seg_len) add_dep(q + 1);
+    if (!upper && r0 > seg[s]) add_dep(q - 1);
+    if (upper && r1 < seg[s + 1]) add_dep(q + 1);
     for (int row = r0; row < r1; ++row) {
       const int l = row - r0;
       oc[l].clear();
@@ -1425,6 +1442,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->poll_limit = 0;
   o->ilut_on_device = 1;
   o->tri_waves_per_cu = 0;
+  o->segment_rows = 0;
   return PMG_OK;
 }
 
@@ -1477,7 +1495,7 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
       (o.mass_transfer != PMG_MASS_LUMPED && o.mass_transfer != PMG_MASS_CONSISTENT) ||
       (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64) ||
       (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT) || o.poll_limit < 0 ||
-      o.tri_waves_per_cu < 0)
+      o.tri_waves_per_cu < 0 || o.segment_rows < 0)
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
@@ -1549,8 +1567,21 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
   const int seg_len = prob->n_elem + prob->degree - 2;
   {
     auto t0 = std::chrono::steady_clock::now();
-    pmg_status bs = build_schedule(H.L, seg_len, false, h->tl);
-    if (bs == PMG_OK) bs = build_schedule(H.U, seg_len, true, h->tu);
+    // segments: runs of whole grid lines inside one block of the nested
+    // dissection (an injected operator: one line each)
+    std::vector<int32_t> seg;
+    if (inj_n) {
+      for (int r = 0; r < H.n; r += seg_len) seg.push_back(r);
+      seg.push_back(H.n);
+    } else {
+      // by default several lines only when a line is shorter than a chunk:
+      // there a chunk spanning lines saves chain steps, while cutting long
+      // lines at other places than their ends lengthens the chains
+      const int rows = o.segment_rows > 0 ? o.segment_rows : (seg_len >= 64 ? 1 : kSegmentRows);
+      seg = pmg::line_segments(prob->dim, seg_len, prob->degree, o.ordering, o.nd_leaf, rows);
+    }
+    pmg_status bs = build_schedule(H.L, seg, seg_len, false, h->tl);
+    if (bs == PMG_OK) bs = build_schedule(H.U, seg, seg_len, true, h->tu);
     if (bs != PMG_OK) return bs;
     h->info.t_schedule = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -1820,6 +1851,7 @@ pmg_status pmg_export_schedule(pmg_handle h, int32_t factor, int32_t field, int6
     case 11: dv = &S.diag; break;
     case 12: iv = &S.chunk_row; break;
     case 13: iv = &S.chunk_len; break;
+    case 14: iv = &S.seg_start; break;
     default: return fail(PMG_EINVAL, "unknown schedule field " + std::to_string(field));
   }
   if (iv) {

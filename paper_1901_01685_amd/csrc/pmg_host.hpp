@@ -78,6 +78,11 @@ std::vector<int32_t> line_ordering(int dim, int nint, int p, int ordering, int l
 // order.
 std::vector<int32_t> factor_ticket_order(int dim, int nint, int p, int ordering, int leaf);
 
+// Segments of the triangular-solve schedules: runs of whole grid lines of at
+// most max_rows rows (at least one line) that never cross a block of the
+// nested dissection, as row starts in the ordering (plus the row count).
+std::vector<int32_t> line_segments(int dim, int nint, int p, int ordering, int leaf, int max_rows);
+
 // B = P A P^T, B_ij = A_{perm[i], perm[j]}, columns sorted.
 Csr permute(const Csr& A, const std::vector<int32_t>& perm, int threads);
 

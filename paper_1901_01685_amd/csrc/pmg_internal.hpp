@@ -82,6 +82,7 @@ struct DevXStencil {
 // Schedule and chunk-sliced factor of one triangular solve (see TriDev).
 struct TriSched {
   int nrows = 0, nseg = 0, seg_len = 0, dag_levels = 0, chunk_levels = 0;
+  std::vector<int32_t> seg_start;  // first row of each segment, then nrows
   int nch = 0;  // chunks in all
   int grid64 = 1, grid32 = 1;  // persistent waves per launch (all resident)
   // all by natural chunk index

@@ -362,7 +362,7 @@ pmg_status pmg_server_default_options(pmg_server_options* o) {
   o->device = 0;
   o->setup_threads = 0;
   o->diverge_ratio = 1e10;
-  o->tri_waves_per_cu = 0;
+  o->tri_waves_per_cu = 1;
   return PMG_OK;
 }
 

@@ -369,6 +369,23 @@ std::vector<int32_t> factor_ticket_order(int dim, int nint, int p, int ordering,
   return order;
 }
 
+std::vector<int32_t> line_segments(int dim, int nint, int p, int ordering, int leaf, int max_rows) {
+  const int64_t nlines = dim == 2 ? nint : (int64_t)nint * nint;
+  std::vector<NdBlock> blocks;
+  if (ordering == 0) {
+    blocks.push_back({0, nlines, 0});
+  } else {
+    int64_t pos = 0;
+    nd_blocks(0, nint, 0, dim == 2 ? 1 : nint, false, nint, p, leaf, pos, blocks);
+  }
+  const int64_t k = std::max<int64_t>(1, max_rows / nint);  // lines per segment
+  std::vector<int32_t> starts;
+  for (const NdBlock& b : blocks)
+    for (int64_t l = b.l0; l < b.l1; l += k) starts.push_back((int32_t)(l * nint));
+  starts.push_back((int32_t)(nlines * nint));
+  return starts;
+}
+
 Csr permute(const Csr& A, const std::vector<int32_t>& perm, int threads) {
   const int n = A.nrows;
   std::vector<int32_t> inv(n);

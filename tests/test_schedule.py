@@ -25,15 +25,20 @@ CASES = [(2, 2, 16), (2, 3, 40), (2, 5, 24), (3, 2, 12)]
 
 def _emulate(s, factor, rhs):
     S = s.export_schedule(factor)
-    seg = s.info.seg_len
+    line = s.info.seg_len
     upper = factor == 1
     row0, nrows = S["chunk_row"], S["chunk_len"]
     nq = len(row0)
     assert nq == (s.info.chunks_u if upper else s.info.chunks_l)
+    # segments are runs of whole grid lines covering the rows
+    ss = S["seg_start"]
+    assert len(ss) == s.info.segments + 1 and ss[0] == 0 and ss[-1] == s.n
+    assert np.all(np.diff(ss) > 0) and np.all(ss % line == 0)
+    segof = lambda r: np.searchsorted(ss, r, side="right") - 1
     # chunks tile the rows, never cross a segment, hold at most 64 rows
     assert row0[0] == 0 and np.all(row0[1:] == row0[:-1] + nrows[:-1]) and row0[-1] + nrows[-1] == s.n
     assert np.all((nrows >= 1) & (nrows <= 64))
-    assert np.all(row0 // seg == (row0 + nrows - 1) // seg)
+    assert np.all(segof(row0) == segof(row0 + nrows - 1))
     row_chunk = np.repeat(np.arange(nq), nrows)
     order = S["order"]
     assert np.array_equal(np.sort(order), np.arange(nq)), "ticket order is not a permutation of the chunks"
@@ -43,13 +48,13 @@ def _emulate(s, factor, rhs):
     out = np.zeros(s.n)
     for tk, q in enumerate(order):
         r0, nrow = int(row0[q]), int(nrows[q])
-        sg = r0 // seg
+        sg = segof(r0)
         # dependency list: chunks of other tickets, all earlier
         deps = set(int(d) for d in S["deps"][S["wptr"][q]:S["wptr"][q + 1]])
         for dq in deps:
             assert ticket[dq] < tk, "chunk %d waits for chunk %d taken later" % (q, dq)
         own_prev = q - 1 if not upper else q + 1
-        if 0 <= own_prev < nq and row0[own_prev] // seg == sg:
+        if 0 <= own_prev < nq and segof(row0[own_prev]) == sg:
             assert own_prev in deps, "chunk %d does not wait for its segment's previous chunk" % q
         w, base = S["off_w"][q], S["off_ptr"][q]
         if w:
