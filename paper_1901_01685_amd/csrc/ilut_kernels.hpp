@@ -57,12 +57,11 @@ struct Args {
   unsigned* state;  // [0] ticket counter, [kTicketStride] exited waves
   unsigned* fault;  // set when a wait reached poll_limit
   int* flags;       // [0] smallest row with a zero or non-finite pivot (n: none), [1] bit 0: table
-                    // overflow, bit 1: a pivot outside the working row or not ticketed before its row
+                    // overflow, bit 1: a pivot missing from the working row (the host factors instead)
   int poll_limit;
   int tbits;         // working row in LDS: 1 << tbits slots
   int full;          // occupied slots beyond which that table overflows
   const int* order;  // ticket -> row: every row after the rows it can depend on
-  const int* pos;    // row -> ticket (the inverse of order)
   // rows that outgrow the LDS table are factored again in a table of
   // 1 << gbits slots in global memory, one per wave (gbits 0: none)
   int* gkeys;        // gridDim.x << gbits
@@ -406,7 +405,7 @@ __device__ __forceinline__ void clear_lower(const LowerBits& B, int i, int lane)
 // GLOBAL: the table is the wave's in global memory and the pivots are found
 // through the bitmaps B; otherwise (LDS) by a scan of the table.
 template <bool GLOBAL>
-__device__ __forceinline__ bool factor_row(const Args& A, int i, int tk, int* keys, double* vals, int tbits,
+__device__ __forceinline__ bool factor_row(const Args& A, int i, int* keys, double* vals, int tbits,
                                            int full, int* hist, int* sh, int lane, int nch, bool& gave_up, bool last,
                                            const LowerBits& B) {
   // every product and difference rounded on its own, as on the host (hipcc
@@ -462,13 +461,6 @@ __device__ __forceinline__ bool factor_row(const Args& A, int i, int tk, int* ke
       k = wave_min(cand);
     }
     if (k == 0x7fffffff) break;
-    // a row only ever waits for rows ticketed before it (so the smallest
-    // unfinished ticket never waits); a pivot that breaks this could only come
-    // from a corrupted working row: report it (the host factors instead)
-    if (A.pos[k] >= tk) {
-      if (lane == 0) atomicOr(&A.flags[1], 2);
-      break;
-    }
     kprev = k;
     // the first probe for w_k travels with the loads of row k of U
     const unsigned s0 = slot_of(k, tbits);
@@ -652,8 +644,8 @@ __global__ __launch_bounds__(64) void ilut_rows(Args A) {
     const int tk = __builtin_amdgcn_readfirstlane((int)atomicAdd(A.state, lane == 0 ? 1u : 0u));
     if (tk >= A.n) break;
     const int i = A.order[tk];
-    if (!factor_row<false>(A, i, tk, keys, vals, A.tbits, A.full, hist, sh, lane, nch, gave_up, A.gbits == 0, B))
-      factor_row<true>(A, i, tk, gk, gv, A.gbits, A.gfull, hist, sh, lane, nch, gave_up, true, B);
+    if (!factor_row<false>(A, i, keys, vals, A.tbits, A.full, hist, sh, lane, nch, gave_up, A.gbits == 0, B))
+      factor_row<true>(A, i, gk, gv, A.gbits, A.gfull, hist, sh, lane, nch, gave_up, true, B);
   }
   // the last wave out clears the counters for the next launch
   unsigned* exited = A.state + kTicketStride;

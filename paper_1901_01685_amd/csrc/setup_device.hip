@@ -14,11 +14,13 @@
 
 namespace {
 
-// Largest working-row table in LDS (slots, log2), the longest working row
-// the first global-memory tables are sized for, and the most global memory
-// those tables may take together.
+// Largest working-row table in LDS (slots, log2); the first global-memory
+// tables are sized for working rows of this many times the longest row of
+// A (the longest working rows measured on the host: 99 times at p = 5,
+// h = 1/512 in 2-D, 215 times at p = 3, h = 1/64 on the cube); the most
+// global memory the tables may take together.
 constexpr int kLdsBitsMax = 12;
-constexpr int64_t kGlobalRowStart = 100000;
+constexpr int64_t kGlobalRowsPerEntry = 300;
 constexpr double kGlobalTableBytes = 16.0e9;
 
 template <typename T>
@@ -71,7 +73,7 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
   const int64_t nw0 = ((int64_t)n + 63) / 64;  // level-0 words of the lower-part bitmap
   if (n > full_of(tbits)) {
     gbits = tbits + 1;
-    while (full_of(gbits) < std::min<int64_t>(n, kGlobalRowStart)) ++gbits;
+    while (full_of(gbits) < std::min<int64_t>(n, kGlobalRowsPerEntry * maxrow)) ++gbits;
     // the level-1 words of that bitmap take the LDS of the table
     while (8 * ((nw0 + 63) / 64) > 12 * (int64_t(1) << tbits) && tbits < kLdsBitsMax) ++tbits;
     if (8 * ((nw0 + 63) / 64) > 12 * (int64_t(1) << tbits)) {
@@ -90,8 +92,7 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     ~Release() { m.release(); }
   } rel{mem};
   int64_t *rp = nullptr;
-  int *ci = nullptr, *Lc = nullptr, *Ln = nullptr, *Uc = nullptr, *Un = nullptr, *flags = nullptr, *ord = nullptr,
-      *pos = nullptr;
+  int *ci = nullptr, *Lc = nullptr, *Ln = nullptr, *Uc = nullptr, *Un = nullptr, *flags = nullptr, *ord = nullptr;
   double *v = nullptr, *Lv = nullptr, *Uv = nullptr;
   unsigned *state = nullptr, *fault = nullptr;
   pmg_status s;
@@ -100,15 +101,14 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
   if ((s = mem.upload(&v, Ap.v.data(), Ap.v.size()))) return s;
   if ((s = mem.upload(&ord, order.data(), order.size()))) return s;
   {
-    std::vector<int32_t> inv((size_t)n, -1);
+    std::vector<char> seen((size_t)n, 0);
     for (int t = 0; t < n; ++t) {
-      if (order[t] < 0 || order[t] >= n || inv[order[t]] >= 0) {
+      if (order[t] < 0 || order[t] >= n || seen[order[t]]) {
         why = "the ticket order is not a permutation";
         return PMG_EINVAL;
       }
-      inv[order[t]] = t;
+      seen[order[t]] = 1;
     }
-    if ((s = mem.upload(&pos, inv.data(), inv.size()))) return s;
   }
   if ((s = mem.alloc(&Lc, (size_t)n * cl))) return s;
   if ((s = mem.alloc(&Lv, (size_t)n * cl))) return s;
@@ -184,7 +184,6 @@ pmg_status ilut_device(const pmg::Csr& Ap, const std::vector<int32_t>& order, do
     A.tbits = tbits;
     A.full = full_of(tbits);
     A.order = ord;
-    A.pos = pos;
     A.gkeys = gkeys;
     A.gvals = gvals;
     A.gbits = gbits;
