@@ -93,8 +93,7 @@ __device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
 // workgroup scope (plain accesses on LDS); the inserting atomics
 // (compare-and-swap of a key, OR into the pivot bitmap) are at agent scope,
 // which includes the workgroup, and the workgroup barriers between the
-// phases of a row order them all.  (Agent-scope loads, which bypass the
-// CU's cache, made the factorisation 24 % slower at p = 5, h = 1/1024.)
+// phases of a row order them all.
 __device__ __forceinline__ int tk_ld(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
