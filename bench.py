@@ -187,8 +187,9 @@ def mixed_config4(pmg, torch, dev, reps=3):
 
 
 def class_setup_cost(dim, p, nel):
-    """Work of a class's host ILUT, n * M^2 (M the rule-2 limit): it dominates
-    the class setup (about 1 s per 1.5e9 on the 16 host threads)."""
+    """Work of a class's ILUT, n * M^2 (M the rule-2 limit), which dominates
+    its setup: 3.2e10 for the cube at p = 3, h = 1/64 (51 s with the device
+    ILUT), 3.3e10 for the cube at p = 2, h = 1/128 (187 s)."""
     n1d = nel + p - 2
     return n1d ** dim * ((2 * p + 1) ** dim) ** 2
 
@@ -360,7 +361,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--closed-requests", type=int, default=600)
     ap.add_argument("--serve-sample-cost", type=float, default=None,
-                    help="serve only classes whose ILUT work n*M^2 is at most this (default run: 2.5e10; --serve: all)")
+                    help="serve only classes whose ILUT work n*M^2 is at most this (default run: 3.25e10; --serve: all)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default run")
     ap.add_argument("--serve-tri-waves", type=int, default=1,
                     help="waves per CU of each slot's triangular-solve grid (0: as many as fit)")
@@ -541,7 +542,7 @@ def main():
         print("# serving leg", file=sys.stderr, flush=True)
         sargs = argparse.Namespace(**vars(args))
         sargs.serve_requests, sargs.serve_warmup, sargs.closed_requests = 400, 50, 200
-        out["serving"] = serve_leg(sargs, sample_cost=args.serve_sample_cost or 2.5e10)
+        out["serving"] = serve_leg(sargs, sample_cost=args.serve_sample_cost or 3.25e10)
     if cpu_proc is not None:
         print("# waiting for the CPU oracle baseline", file=sys.stderr, flush=True)
         so, _ = cpu_proc.communicate(timeout=900)
