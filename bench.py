@@ -310,7 +310,7 @@ def serve_leg(args, sample_cost=None):
         "seed": args.seed, "slots": args.slots, "tol": 1e-10, "tri_waves_per_cu": args.serve_tri_waves,
         "budget_GB": round(opts.budget_bytes / 1e9, 1), "class_limit_GB": round(opts.max_class_bytes / 1e9, 1),
         "sample": (None if sample_cost is None else
-                   f"classes whose ILUT work n*M^2 <= {sample_cost:.1e} (setup bounded for this run): "
+                   f"classes whose ILUT work n*M^2 <= {sample_cost:.3g} (setup bounded for this run): "
                    f"{len(in_sample)} of {len(all_classes)}"),
         "classes_admitted": len(admitted), "classes_rejected": [list(c) for c in rejected_classes],
         "setup_s": round(t_setup, 1),
