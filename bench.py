@@ -390,6 +390,15 @@ def main():
              "--cpu-budget", str(args.cpu_budget), "--cpu-nel", str(args.cpu_nel if args.dim == 2 else 16)],
             stdout=subprocess.PIPE, text=True)
 
+    try:
+        gpu_legs(args, cpu_proc)
+    finally:
+        if cpu_proc is not None and cpu_proc.poll() is None:
+            cpu_proc.kill()
+            cpu_proc.communicate()
+
+
+def gpu_legs(args, cpu_proc):
     import torch
     import paper_1901_01685_amd as pmg
 
@@ -545,8 +554,13 @@ def main():
         out["serving"] = serve_leg(sargs, sample_cost=args.serve_sample_cost or 3.25e10)
     if cpu_proc is not None:
         print("# waiting for the CPU oracle baseline", file=sys.stderr, flush=True)
-        so, _ = cpu_proc.communicate(timeout=900)
-        out["cpu_baseline"] = json.loads(so.strip().splitlines()[-1]) if cpu_proc.returncode == 0 else None
+        try:
+            so, _ = cpu_proc.communicate(timeout=600)
+            out["cpu_baseline"] = json.loads(so.strip().splitlines()[-1]) if cpu_proc.returncode == 0 else None
+        except (subprocess.TimeoutExpired, ValueError, IndexError):
+            cpu_proc.kill()
+            cpu_proc.communicate()
+            out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -161,3 +161,32 @@ def test_cdr_requests_are_their_own_class():
         assert _oracle_relres(2, 3, 32, 0, (1, 1, 1), x_p) <= 1.01e-10
     finally:
         srv.close()
+
+
+def test_effective_options_take_the_budget_from_the_device():
+    import paper_1901_01685_amd as pmg
+    _need_gpu()
+    total = torch.cuda.get_device_properties(0).total_memory
+    srv = pmg.Server(max_slots=3)
+    try:
+        o = srv.effective_options()
+        # 70 % of the device's memory, a quarter of it per class, one wave per
+        # CU per slot grid; the requested fields unchanged
+        assert abs(o.budget_bytes - 0.7 * total) <= 1 << 20, (o.budget_bytes, total)
+        assert o.max_class_bytes == o.budget_bytes // 4
+        assert o.tri_waves_per_cu == 1 and o.max_slots == 3 and o.precision == pmg.FP32_IN_FP64
+    finally:
+        srv.close()
+    srv = pmg.Server(max_slots=2, budget_bytes=300 << 20, max_class_bytes=100 << 20, tri_waves_per_cu=0)
+    try:
+        o = srv.effective_options()
+        assert o.budget_bytes == 300 << 20 and o.max_class_bytes == 100 << 20 and o.tri_waves_per_cu == 0
+        st, t = srv.submit(2, 3, 32)
+        assert st == pmg.OK
+        st, info, _ = srv.wait(t)
+        assert st == pmg.OK and info["relres"] <= 1e-10
+    finally:
+        srv.close()
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.Server(tri_waves_per_cu=-1)
+    assert e.value.status == pmg.EINVAL
