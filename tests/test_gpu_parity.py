@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [
     # (dim, p, nel, geom): several 64-row chunks per line, ragged tails
-    (2, 2, 16, 0),     # configs[0]: 256 unknowns, one partial chunk per line
+    (2, 2, 16, 0),     # the smallest workload: 256 unknowns, one partial chunk per line
     (2, 3, 128, 0),    # 129-row lines: 2 full chunks + 1-row tail
     (2, 5, 64, 0),     # 67-row lines
     (2, 4, 32, 1),     # quarter annulus
