@@ -33,16 +33,19 @@ METRIC = "V-cycle DOF·iter/s + HBM GB/s frac; served solves/s, p50/p99 latency 
 
 # kernel class -> (kernel name in the rocprofv3 trace, info field of its bytes per launch)
 def kernel_map(info, dim, degree):
-    """Residual and p-transfers use the stencil kernels whenever the library
-    chose that layout (it reads fewer bytes than CSR), which shows in the
-    algorithmic byte counts it reports."""
-    stencil_a = info.bytes_spmv != 12 * info.nnz_a + 4 * (info.n + 1) + 24 * info.n
+    """The residual's kernel follows the layout the library reports (Kronecker
+    factors on the box, the stencil layout, or CSR); the p-transfers use the
+    stencil kernels whenever the library chose that layout (it reads fewer
+    bytes than CSR), which shows in the algorithmic byte counts it reports."""
+    kron_a = info.residual_layout == 2
+    stencil_a = info.residual_layout == 1
     stencil_r = info.bytes_restrict != 12 * info.nnz_r + 4 * (info.n1 + 1) + 8 * info.n + 16 * info.n1
     stencil_p = info.bytes_prolong != 12 * info.nnz_p + 4 * (info.n + 1) + 8 * info.n1 + 24 * info.n
     return {
         # the stencil kernel is instantiated per stencil width up to 11 (degree 5)
-        "residual": ((f"stencil_resid<double, {dim}, false, {2 * degree + 1}>" if degree <= 5
-                      else f"stencil_resid<double, {dim}, false, 0>") if stencil_a
+        "residual": (f"kron_resid<double, {dim}, false, {2 * degree + 1}>" if kron_a
+                     else (f"stencil_resid<double, {dim}, false, {2 * degree + 1}>" if degree <= 5
+                           else f"stencil_resid<double, {dim}, false, 0>") if stencil_a
                      else "csr_kernel<double, G, 0>", "bytes_spmv"),
         "lower": ("trisolve_lower<double>", "bytes_trisolve_l"),
         "upper": ("trisolve_upper<double>", "bytes_trisolve_u"),

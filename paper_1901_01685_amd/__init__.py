@@ -55,7 +55,7 @@ class Options(C.Structure):
                 ("setup_threads", C.c_int32), ("ordering", C.c_int32), ("nd_leaf", C.c_int32),
                 ("graphs", C.c_int32), ("tiled_gs", C.c_int32), ("mass_transfer", C.c_int32),
                 ("projection", C.c_int32), ("poll_limit", C.c_int32), ("ilut_on_device", C.c_int32),
-                ("tri_waves_per_cu", C.c_int32), ("segment_rows", C.c_int32)]
+                ("tri_waves_per_cu", C.c_int32), ("segment_rows", C.c_int32), ("kron_residual", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -74,7 +74,7 @@ class Info(C.Structure):
                 ("bytes_trisolve_u", C.c_int64), ("bytes_restrict", C.c_int64),
                 ("bytes_prolong", C.c_int64), ("bytes_coarse", C.c_int64), ("device_bytes", C.c_int64),
                 ("t_assembly", C.c_double), ("t_ilut", C.c_double), ("t_upload", C.c_double),
-                ("t_schedule", C.c_double), ("ilut_on_device", C.c_int32)]
+                ("t_schedule", C.c_double), ("ilut_on_device", C.c_int32), ("residual_layout", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

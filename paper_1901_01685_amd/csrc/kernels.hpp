@@ -152,6 +152,86 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Coefficient of A = sum over directions a of (K in direction a) (x) (M in
+// the others) at one offset, from the 1-D factors' entries in each
+// direction: the products and sums of the assembly in its order, each
+// rounded on its own, so the value is the stored A_ij bit for bit.
+__device__ __forceinline__ double kron2(double Kx, double Mx, double Ky, double My) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  s = s + Kx * My;
+  s = s + Mx * Ky;
+  return s;
+}
+__device__ __forceinline__ double kron3(double Kx, double Mx, double Ky, double My, double Kz, double Mz) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  s = s + (Kx * My) * Mz;
+  s = s + (Mx * Ky) * Mz;
+  s = s + (Mx * My) * Kz;
+  return s;
+}
+
+// Residual r = b - A x (PLAIN: r = A x) for Poisson on the unit box, where A
+// is a Kronecker sum: the coefficients are formed from the bands kK, kM of
+// the 1-D stiffness and mass (nx interior rows of WX = 2p+1 entries, 0
+// outside the grid) instead of read, so only the vectors come from HBM.  The
+// loop order, the masking of offsets outside the grid and the block partials
+// are those of stencil_resid, and the coefficients equal the stored values,
+// so both kernels give the same results bit for bit.
+template <typename T, int DIM, bool PLAIN, int WX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void kron_resid(
+    int n, int nx, int p, const double* __restrict__ kK, const double* __restrict__ kM, const T* __restrict__ x,
+    const T* __restrict__ b, T* __restrict__ r, double* __restrict__ partial) {
+  const int ny = nx;
+  const int nz = DIM == 3 ? n / (nx * ny) : 1;
+  double sq = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int ix = i % nx, t = i / nx, iy = t % ny, iz = t / ny;
+    const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
+    const int dy0 = max(-p, -iy), dy1 = min(p, ny - 1 - iy);
+    const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
+    double Kx[WX], Mx[WX];
+#pragma unroll
+    for (int u = 0; u < WX; ++u) {
+      Kx[u] = kK[ix * WX + u];
+      Mx[u] = kM[ix * WX + u];
+    }
+    T acc = 0;
+    for (int dz = dz0; dz <= dz1; ++dz) {
+      const double Kz = DIM == 3 ? kK[iz * WX + dz + p] : 0.0, Mz = DIM == 3 ? kM[iz * WX + dz + p] : 0.0;
+      for (int dy = dy0; dy <= dy1; ++dy) {
+        const double Ky = kK[iy * WX + dy + p], My = kM[iy * WX + dy + p];
+        const T* xr = x + i + (dz * ny + dy) * nx;
+        T vv[WX], xx[WX];
+#pragma unroll
+        for (int u = 0; u < WX; ++u) {
+          const int dx = u - WX / 2;
+          const bool ok = dx >= dx0 && dx <= dx1;
+          vv[u] = (T)(DIM == 3 ? kron3(Kx[u], Mx[u], Ky, My, Kz, Mz) : kron2(Kx[u], Mx[u], Ky, My));
+          xx[u] = xr[ok ? dx : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < WX; ++u) {
+          const int dx = u - WX / 2;
+          acc += (dx >= dx0 && dx <= dx1 ? vv[u] : (T)0) * xx[u];
+        }
+      }
+    }
+    const T res = PLAIN ? acc : b[i] - acc;  // PLAIN: r = A x
+    r[i] = res;
+    sq += (double)res * (double)res;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // y = d .* (M x) (or y += d .* (M x) with ADD) for a transfer M between the
 // degree-p and degree-1 grids (nxr nodes per axis for the rows, nxc for the
 // columns).  Row i at grid position (ix, iy, iz) couples only to the column

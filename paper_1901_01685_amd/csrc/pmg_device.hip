@@ -424,10 +424,22 @@ int stencil_slots(const pmg::HostOps& H) {
   return S;
 }
 
-pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, DevStencil& D, bool with32) {
+pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, bool kron, DevStencil& D,
+                          bool with32) {
   if (S == 0) return PMG_OK;
   const int d = H.dim, p = H.p, nx = H.nel + p - 2, w = 2 * p + 1;
   const int64_t n = H.n;
+  D.dim = d;
+  D.p = p;
+  D.nx = D.ny = nx;
+  D.S = S;
+  if (kron) {
+    // the coefficients are formed from the 1-D factors in the kernel
+    pmg_status s;
+    if ((s = mem.upload(&D.kK, H.kK.data(), H.kK.size()))) return s;
+    if ((s = mem.upload(&D.kM, H.kM.data(), H.kM.size()))) return s;
+    return PMG_OK;
+  }
   std::vector<double> V((size_t)S * n, 0.0);
   for (int64_t i = 0; i < n; ++i) {
     const int64_t ix = i % nx, iy = (i / nx) % nx, iz = i / ((int64_t)nx * nx);
@@ -444,10 +456,6 @@ pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, D
     std::vector<float> V32(V.begin(), V.end());
     if ((s = mem.upload(&D.v32, V32.data(), V32.size()))) return s;
   }
-  D.dim = d;
-  D.p = p;
-  D.nx = D.ny = nx;
-  D.S = S;
   return PMG_OK;
 }
 
@@ -763,11 +771,38 @@ void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const
   }
 }
 
+// kron_resid with the offset loop unrolled (widths 3..11)
+template <typename T, int DIM, bool PLAIN>
+void launch_kron(const DevStencil& S, int n, unsigned grid, const T* x, const T* b, T* r, double* partial,
+                 hipStream_t st) {
+  switch (2 * S.p + 1) {
+#define PMG_KRON_W(W)                                                                                   \
+  case W:                                                                                               \
+    pmg::kron_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.p, S.kK, S.kM, x, b, r, partial); \
+    return;
+    PMG_KRON_W(3)
+    PMG_KRON_W(5)
+    PMG_KRON_W(7)
+    PMG_KRON_W(9)
+    PMG_KRON_W(11)
+#undef PMG_KRON_W
+  }
+}
+
 // r = b - A_{h,p} x with block partials of sum(r^2) in partial; returns the
 // number of partials written.
 template <typename T>
 unsigned resid_a(pmg_handle h, const T* x, const T* b, T* r, double* partial, hipStream_t st) {
   const DevStencil& S = h->As;
+  if (S.kK) {
+    const int n = h->A.nrows;
+    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    if (S.dim == 2)
+      launch_kron<T, 2, false>(S, n, grid, x, b, r, partial, st);
+    else
+      launch_kron<T, 3, false>(S, n, grid, x, b, r, partial, st);
+    return grid;
+  }
   if (S.v) {
     const T* V;
     if constexpr (sizeof(T) == 8) V = S.v; else V = S.v32;
@@ -1264,6 +1299,15 @@ void vcycle64(pmg_handle h, Workspace& ws, const double* b, double* x, double* r
 // y = A x (plain product, FP64)
 void matvec_a(pmg_handle h, Workspace& ws, const double* x, double* y, hipStream_t st) {
   const DevStencil& S = h->As;
+  if (S.kK) {
+    const int n = h->A.nrows;
+    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    if (S.dim == 2)
+      launch_kron<double, 2, true>(S, n, grid, x, x, y, ws.partial, st);
+    else
+      launch_kron<double, 3, true>(S, n, grid, x, x, y, ws.partial, st);
+    return;
+  }
   if (S.v) {
     const int n = h->A.nrows;
     const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
@@ -1443,6 +1487,7 @@ pmg_status pmg_default_options(pmg_options* o) {
   o->ilut_on_device = 1;
   o->tri_waves_per_cu = 0;
   o->segment_rows = 0;
+  o->kron_residual = 1;
   return PMG_OK;
 }
 
@@ -1495,7 +1540,7 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
       (o.mass_transfer != PMG_MASS_LUMPED && o.mass_transfer != PMG_MASS_CONSISTENT) ||
       (o.mass_transfer == PMG_MASS_CONSISTENT && o.precision != PMG_FP64) ||
       (o.projection != PMG_PROJ_DIRECT && o.projection != PMG_PROJ_INDIRECT) || o.poll_limit < 0 ||
-      o.tri_waves_per_cu < 0 || o.segment_rows < 0)
+      o.tri_waves_per_cu < 0 || o.segment_rows < 0 || (o.kron_residual != 0 && o.kron_residual != 1))
     return fail(PMG_EINVAL, "invalid options");
   std::unique_ptr<pmg_handle_s> h(new pmg_handle_s());
   h->prob = *prob;
@@ -1528,6 +1573,10 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
   if (inj_n) {
     pmg_status si = take_csr(*inj_n, H.n, inj_rp, inj_ci, inj_v, H.A);
     if (si) return si;
+    // an injected operator is no Kronecker sum
+    H.nk = 0;
+    H.kK.clear();
+    H.kM.clear();
   }
   {
     auto t0 = std::chrono::steady_clock::now();
@@ -1613,9 +1662,17 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
   I.chunk_levels_l = h->tl.chunk_levels;
   I.chunk_levels_u = h->tu.chunk_levels;
   const int64_t n = H.n, n1 = H.n1;
-  h->a_stencil = stencil_slots(H);
-  I.bytes_spmv = h->a_stencil ? 8 * (int64_t)h->a_stencil * H.n + 24 * (int64_t)H.n
-                              : 12 * I.nnz_a + 4 * (n + 1) + 24 * n;
+  // Kronecker factors on the box (for degrees whose stencil width is
+  // unrolled), else the stencil layout where it reads fewer bytes than CSR
+  h->a_kron = o.kron_residual && H.nk > 0 && prob->degree <= 5;
+  {
+    const int w = 2 * prob->degree + 1;
+    h->a_stencil = h->a_kron ? (prob->dim == 2 ? w * w : w * w * w) : stencil_slots(H);
+  }
+  I.residual_layout = h->a_kron ? 2 : h->a_stencil ? 1 : 0;
+  I.bytes_spmv = h->a_kron ? 2 * 8 * (int64_t)H.kK.size() + 24 * (int64_t)H.n
+                 : h->a_stencil ? 8 * (int64_t)h->a_stencil * H.n + 24 * (int64_t)H.n
+                                : 12 * I.nnz_a + 4 * (n + 1) + 24 * n;
   I.bytes_trisolve_l = 12 * I.nnz_l + 4 * (n + 1) + 16 * n;
   I.bytes_trisolve_u = 12 * I.nnz_u + 4 * (n + 1) + 32 * n;
   {
@@ -1659,7 +1716,7 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     // CSR copies only of the operators that have no stencil layout
     if (h->a_stencil) describe_mat(H.A, h->A);
     else if ((s = upload_mat(m, H.A, h->A, mixed))) return s;
-    if ((s = upload_stencil(m, H, h->a_stencil, h->As, mixed))) return s;
+    if ((s = upload_stencil(m, H, h->a_stencil, h->a_kron, h->As, mixed))) return s;
     if ((s = upload_tri(m, h->tl, false, mixed))) return s;
     if ((s = upload_tri(m, h->tu, true, mixed))) return s;
     if ((s = size_tri_grid<double>(o.device, o.tri_waves_per_cu, h->tl, h->tu))) return s;

@@ -40,6 +40,13 @@ struct HostOps {
   Csr P;                       // P_1^p (n x n1)
   Csr Mp, M1;                  // consistent interior mass matrices (only when requested)
   std::vector<double> f, mlp, ml1;
+  // Poisson on the unit box: A is the sum over the directions a of the
+  // Kronecker product of the 1-D stiffness K in direction a and the 1-D mass
+  // M in the others.  kK, kM hold the interior rows of K and M as bands (nk
+  // rows of 2p+1 entries for the offsets -p..p, 0 outside the grid); empty
+  // for other problems.
+  int nk = 0;
+  std::vector<double> kK, kM;
   int nlev = 0;
   std::vector<int> lnel, ln;   // elements / unknowns per degree-1 level
   std::vector<Csr> A1;         // rediscretised degree-1 operators

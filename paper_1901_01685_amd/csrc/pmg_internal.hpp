@@ -69,6 +69,8 @@ struct DevStencil {
   int dim = 0, p = 0, nx = 0, ny = 0, S = 0;  // S = (2p+1)^dim offsets
   double* v = nullptr;
   float* v32 = nullptr;
+  double* kK = nullptr;  // Kronecker factors (pmg::kron_resid) instead of v
+  double* kM = nullptr;
 };
 
 // A transfer between the degree-p and degree-1 grids in stencil layout
@@ -152,6 +154,7 @@ struct pmg_handle_s {
   pmgdev::DevMat Mp, M1;  // consistent masses (mass_transfer = consistent)
   pmgdev::DevStencil As;  // A in stencil layout (As.v == nullptr: CSR is used)
   int a_stencil = 0;      // offsets of that layout, 0 if CSR is used
+  bool a_kron = false;    // residual from the Kronecker factors (As.kK, As.kM)
   pmgdev::DevXStencil Rs, Ps;  // P_p^1 and P_1^p in stencil layout
   std::vector<pmgdev::DevMat> A1, Ph, Rh;
   std::vector<pmg::GridLevel> grid;  // degree-1 levels in stencil layout (empty: CSR path)

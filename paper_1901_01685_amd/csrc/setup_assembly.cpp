@@ -812,6 +812,18 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
       H.A = kron_assemble(dim, c.terms(), th);
     } else {
       H.A = kron_assemble(dim, termsA, th);
+      // the factors as bands of their interior rows (interior index i is
+      // full index i + 1)
+      const int nk = nel + p - 2, w = 2 * p + 1;
+      H.nk = nk;
+      H.kK.assign((size_t)nk * w, 0.0);
+      H.kM.assign((size_t)nk * w, 0.0);
+      for (int i = 0; i < nk; ++i)
+        for (int d = -p; d <= p; ++d)
+          if (i + d >= 0 && i + d < nk) {
+            H.kK[(size_t)i * w + d + p] = K.get(i + 1, i + d + 1);
+            H.kM[(size_t)i * w + d + p] = M.get(i + 1, i + d + 1);
+          }
     }
     Band1D X = matrix_1d(1, p, cdeg, nel, p + 1);
     H.P = kron_assemble(dim, {std::vector<const Band1D*>(dim, &X)}, th);

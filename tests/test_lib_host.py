@@ -96,15 +96,20 @@ def test_info_sizes_and_bytes():
     assert i.seg_len == 67 and i.segments == 67
     # lower bound on the natural-order DAG depth of the ILU(0) pattern
     assert i.dag_levels_l >= (5 + 2) * (67 - 1) + 1
-    # the residual reads A in stencil layout (8 bytes per offset slot, 11^2
+    # on the box the residual forms A's coefficients from the 1-D factors of
+    # its Kronecker sum (two bands of 67 x 11 entries) and reads the vectors
+    assert i.residual_layout == 2 and i.bytes_spmv == 2 * 8 * 67 * 11 + 24 * i.n
+    # otherwise it reads A in stencil layout (8 bytes per offset slot, 11^2
     # slots per row) when that is fewer bytes than CSR (12 per non-zero)
-    stencil = 8 * 11 ** 2 * i.n + 24 * i.n
-    csr = 12 * i.nnz_a + 4 * (i.n + 1) + 24 * i.n
-    assert stencil < csr and i.bytes_spmv == stencil
-    assert i.bytes_vcycle > 3 * i.bytes_spmv
+    k = P.Solver(2, 5, 64, device=-1, ordering=0, kron_residual=0).info
+    stencil = 8 * 11 ** 2 * k.n + 24 * k.n
+    csr = 12 * k.nnz_a + 4 * (k.n + 1) + 24 * k.n
+    assert k.residual_layout == 1 and stencil < csr and k.bytes_spmv == stencil
+    assert k.bytes_vcycle > 3 * k.bytes_spmv
     # on a small 3-D grid the zero slots at the boundary make CSR cheaper
-    j = P.Solver(3, 3, 8, device=-1).info
-    assert j.bytes_spmv == 12 * j.nnz_a + 4 * (j.n + 1) + 24 * j.n
+    j = P.Solver(3, 3, 8, device=-1, kron_residual=0).info
+    assert j.residual_layout == 0 and j.bytes_spmv == 12 * j.nnz_a + 4 * (j.n + 1) + 24 * j.n
+    assert P.Solver(3, 3, 8, device=-1).info.residual_layout == 2
 
 
 def test_status_codes_host():
