@@ -33,14 +33,17 @@ METRIC = "V-cycle DOF·iter/s + HBM GB/s frac; served solves/s, p50/p99 latency 
 
 # kernel class -> (kernel name in the rocprofv3 trace, info field of its bytes per launch)
 def kernel_map(info, dim, degree):
-    """The residual's kernel follows the layout the library reports (Kronecker
-    factors on the box, the stencil layout, or CSR); the p-transfers use the
-    stencil kernels whenever the library chose that layout (it reads fewer
-    bytes than CSR), which shows in the algorithmic byte counts it reports."""
+    """Each kernel follows the layout the library reports for its operator:
+    Kronecker factors on the box, the stencil layout, or CSR."""
     kron_a = info.residual_layout == 2
     stencil_a = info.residual_layout == 1
-    stencil_r = info.bytes_restrict != 12 * info.nnz_r + 4 * (info.n1 + 1) + 8 * info.n + 16 * info.n1
-    stencil_p = info.bytes_prolong != 12 * info.nnz_p + 4 * (info.n + 1) + 8 * info.n1 + 24 * info.n
+
+    def transfer(add, cls):
+        if info.transfer_layout == 2:
+            return f"kron_xgrid<double, {dim}, {add}>"
+        if info.transfer_layout == 1:
+            return f"xgrid_spmv<double, {dim}, {add}>"
+        return f"csr_kernel<double, G, {cls}>"
     return {
         # the stencil kernel is instantiated per stencil width up to 11 (degree 5)
         "residual": (f"kron_resid<double, {dim}, false, {2 * degree + 1}>" if kron_a
@@ -49,10 +52,8 @@ def kernel_map(info, dim, degree):
                      else "csr_kernel<double, G, 0>", "bytes_spmv"),
         "lower": ("trisolve_lower<double>", "bytes_trisolve_l"),
         "upper": ("trisolve_upper<double>", "bytes_trisolve_u"),
-        "restrict": (f"xgrid_spmv<double, {dim}, false>" if stencil_r else "csr_kernel<double, G, 2>",
-                     "bytes_restrict"),
-        "prolong": (f"xgrid_spmv<double, {dim}, true>" if stencil_p else "csr_kernel<double, G, 3>",
-                    "bytes_prolong"),
+        "restrict": (transfer("false", 2), "bytes_restrict"),
+        "prolong": (transfer("true", 3), "bytes_prolong"),
     }
 
 

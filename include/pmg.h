@@ -176,11 +176,12 @@ typedef struct {
                                least), and each segment into chunks of 64 rows; 0 (default):
                                one line per segment when a line holds 64 rows or more,
                                otherwise up to 512 rows */
-  int32_t kron_residual;    /* 1 (default): on the unit box (Poisson, degree <= 5) the
-                               residual forms A's coefficients from the 1-D stiffness and
-                               mass factors of its Kronecker sum (the values of the
-                               assembled A, bit for bit) instead of reading them; 0: A's
-                               stencil layout */
+  int32_t kron_residual;    /* 1 (default): on the unit box the residual (Poisson, degree
+                               <= 5) forms A's coefficients from the 1-D stiffness and mass
+                               factors of its Kronecker sum, and the p-transfers (lumped
+                               masses) form theirs from the 1-D factor of theirs, instead of
+                               reading them (the assembled values, bit for bit); 0: the
+                               stencil layouts */
 } pmg_options;
 
 typedef struct {
@@ -211,6 +212,7 @@ typedef struct {
   int32_t ilut_on_device;     /* 1 if the ILUT factors were computed on the device */
   int32_t residual_layout;    /* how the residual reads A: 0 CSR, 1 stencil layout, 2 Kronecker
                                  factors (pmg_options.kron_residual) */
+  int32_t transfer_layout;    /* the same for the p-transfers R and P */
 } pmg_info;
 
 /* ILUT ordering (Section 3, "Smoother": the factorisation follows a

@@ -91,57 +91,19 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
   }
 }
 
-// Residual r = b - A x (PLAIN: r = A x) with A in stencil layout.  With the tensor-product
-// B-spline basis of degree p, row i (grid position (ix, iy, iz), x fastest,
-// nx * ny per plane) couples only to the rows at offsets |dx|, |dy|, |dz| <=
-// p; the value of offset k of row i is V[k * n + i] (k lexicographic in
-// (dz, dy, dx), 0 where the offset leaves the grid), so no column indices
-// are stored and both V and x are read contiguously across a wave's rows.
-// Sums run over dz, dy, dx ascending; block partials of sum(r^2) as for the
-// CSR residual.
-// WX > 0: the stencil width 2 p + 1 known at compile time, so the offsets of
-// a stencil row are unrolled and all their loads issued together (offsets
-// outside the grid read offset 0 with weight 0, which adds an exact zero).
-template <typename T, int DIM, bool PLAIN = false, int WX = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void stencil_resid(int n, int nx, int ny, int p, const T* __restrict__ V,
-                                                     const T* __restrict__ x, const T* __restrict__ b,
-                                                     T* __restrict__ r, double* __restrict__ partial) {
-  const int w = 2 * p + 1;
-  const int nz = DIM == 3 ? n / (nx * ny) : 1;
-  double sq = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int ix = i % nx, t = i / nx, iy = t % ny, iz = t / ny;
-    const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
-    const int dy0 = max(-p, -iy), dy1 = min(p, ny - 1 - iy);
-    const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
-    T acc = 0;
-    for (int dz = dz0; dz <= dz1; ++dz)
-      for (int dy = dy0; dy <= dy1; ++dy) {
-        const int k0 = ((DIM == 3 ? (dz + p) * w : 0) + (dy + p)) * w + p;  // offset index of dx = 0
-        const T* vr = V + (size_t)k0 * n + i;
-        const T* xr = x + i + (dz * ny + dy) * nx;
-        if constexpr (WX > 0) {
-          T vv[WX], xx[WX];
-#pragma unroll
-          for (int u = 0; u < WX; ++u) {
-            const int dx = u - WX / 2;
-            const bool ok = dx >= dx0 && dx <= dx1;
-            vv[u] = vr[(int64_t)(ok ? dx : 0) * n];
-            xx[u] = xr[ok ? dx : 0];
-          }
-#pragma unroll
-          for (int u = 0; u < WX; ++u) {
-            const int dx = u - WX / 2;
-            acc += (dx >= dx0 && dx <= dx1 ? vv[u] : (T)0) * xx[u];
-          }
-        } else {
-          for (int dx = dx0; dx <= dx1; ++dx) acc += vr[(int64_t)dx * n] * xr[dx];
-        }
-      }
-    const T res = PLAIN ? acc : b[i] - acc;  // PLAIN: r = A x
-    r[i] = res;
-    sq += (double)res * (double)res;
-  }
+// Rows of the residual kernels per thread: rb <= kResidRows consecutive rows
+// in y of one grid column (ix, iz), so a line of x is loaded once for all of
+// them (2p + rb lines instead of (2p + 1) rb); the lanes of a wave hold
+// consecutive ix, so every load and store is contiguous across the wave.
+constexpr int kResidRows = 4;
+
+__host__ __device__ inline int resid_threads(int n, int nx, int ny, int rb) {
+  return nx * ((ny + rb - 1) / rb) * (n / (nx * ny));
+}
+
+// Block partials of sum(r^2) for the residual kernels (threads' sums in
+// order, then a tree over the block).
+__device__ __forceinline__ void resid_partial(double sq, double* partial) {
   __shared__ double red[256];
   red[threadIdx.x] = sq;
   __syncthreads();
@@ -150,6 +112,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Residual r = b - A x (PLAIN: r = A x) with A in stencil layout.  With the tensor-product
+// B-spline basis of degree p, row i (grid position (ix, iy, iz), x fastest,
+// nx * ny per plane) couples only to the rows at offsets |dx|, |dy|, |dz| <=
+// p; the value of offset k of row i is V[k * n + i] (k lexicographic in
+// (dz, dy, dx), 0 where the offset leaves the grid), so no column indices
+// are stored and both V and x are read contiguously across a wave's rows.
+// Each row's sum runs over dz, dy, dx ascending, whatever line of x is
+// loaded first; a thread takes rb rows (resid_threads threads).
+// WX > 0: the stencil width 2 p + 1 known at compile time, so the offsets of
+// a stencil row are unrolled and all their loads issued together (offsets
+// outside the grid read offset 0 with weight 0, which adds an exact zero).
+template <typename T, int DIM, bool PLAIN = false, int WX = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void stencil_resid(int n, int nx, int ny, int p, int rb, const T* __restrict__ V,
+                                                     const T* __restrict__ x, const T* __restrict__ b,
+                                                     T* __restrict__ r, double* __restrict__ partial) {
+  constexpr int RB = kResidRows;
+  const int w = 2 * p + 1;
+  const int nz = DIM == 3 ? n / (nx * ny) : 1;
+  const int nyb = (ny + rb - 1) / rb, nt = nx * nyb * nz;
+  double sq = 0.0;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
+    const int ix = t % nx, u = t / nx, iy0 = (u % nyb) * rb, iz = u / nyb;
+    const int nr = min(rb, ny - iy0);
+    const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
+    const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
+    const int i0 = (iz * ny + iy0) * nx + ix;  // row (ix, iy0, iz)
+    const int y0 = max(0, iy0 - p), y1 = min(ny - 1, iy0 + nr - 1 + p);
+    T acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = 0;
+    for (int dz = dz0; dz <= dz1; ++dz)
+      for (int y = y0; y <= y1; ++y) {
+        const T* xr = x + ((iz + dz) * ny + y) * nx + ix;
+        if constexpr (WX > 0) {
+          T xx[WX];
+#pragma unroll
+          for (int k = 0; k < WX; ++k) {
+            const int dx = k - WX / 2;
+            xx[k] = xr[dx >= dx0 && dx <= dx1 ? dx : 0];
+          }
+#pragma unroll
+          for (int q = 0; q < RB; ++q) {
+            const int dy = y - iy0 - q;
+            if (q < nr && dy >= -p && dy <= p) {
+              const int k0 = ((DIM == 3 ? (dz + p) * w : 0) + (dy + p)) * w + p;  // offset index of dx = 0
+              const T* vr = V + (size_t)k0 * n + i0 + q * nx;
+              T vv[WX];
+#pragma unroll
+              for (int k = 0; k < WX; ++k) {
+                const int dx = k - WX / 2;
+                vv[k] = vr[(int64_t)(dx >= dx0 && dx <= dx1 ? dx : 0) * n];
+              }
+#pragma unroll
+              for (int k = 0; k < WX; ++k) {
+                const int dx = k - WX / 2;
+                acc[q] += (dx >= dx0 && dx <= dx1 ? vv[k] : (T)0) * xx[k];
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < RB; ++q) {
+            const int dy = y - iy0 - q;
+            if (q < nr && dy >= -p && dy <= p) {
+              const int k0 = ((DIM == 3 ? (dz + p) * w : 0) + (dy + p)) * w + p;
+              const T* vr = V + (size_t)k0 * n + i0 + q * nx;
+              for (int dx = dx0; dx <= dx1; ++dx) acc[q] += vr[(int64_t)dx * n] * xr[dx];
+            }
+          }
+        }
+      }
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (q < nr) {
+        const int i = i0 + q * nx;
+        const T res = PLAIN ? acc[q] : b[i] - acc[q];  // PLAIN: r = A x
+        r[i] = res;
+        sq += (double)res * (double)res;
+      }
+  }
+  resid_partial(sq, partial);
 }
 
 // Coefficient of A = sum over directions a of (K in direction a) (x) (M in
@@ -176,60 +221,72 @@ __device__ __forceinline__ double kron3(double Kx, double Mx, double Ky, double 
 // is a Kronecker sum: the coefficients are formed from the bands kK, kM of
 // the 1-D stiffness and mass (nx interior rows of WX = 2p+1 entries, 0
 // outside the grid) instead of read, so only the vectors come from HBM.  The
-// loop order, the masking of offsets outside the grid and the block partials
-// are those of stencil_resid, and the coefficients equal the stored values,
-// so both kernels give the same results bit for bit.
+// rows of a thread, the loop order, the masking of offsets outside the grid
+// and the block partials are those of stencil_resid, and the coefficients
+// equal the stored values, so both kernels give the same results bit for
+// bit.  The row's x-factors stay in registers; the y- and z-factors are
+// loaded per offset line (the same for the lanes of one grid line).
 template <typename T, int DIM, bool PLAIN, int WX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void kron_resid(
-    int n, int nx, int p, const double* __restrict__ kK, const double* __restrict__ kM, const T* __restrict__ x,
-    const T* __restrict__ b, T* __restrict__ r, double* __restrict__ partial) {
+    int n, int nx, int p, int rb, const double* __restrict__ kK, const double* __restrict__ kM,
+    const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r, double* __restrict__ partial) {
+  constexpr int RB = kResidRows;
   const int ny = nx;
   const int nz = DIM == 3 ? n / (nx * ny) : 1;
+  const int nyb = (ny + rb - 1) / rb, nt = nx * nyb * nz;
   double sq = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int ix = i % nx, t = i / nx, iy = t % ny, iz = t / ny;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
+    const int ix = t % nx, u = t / nx, iy0 = (u % nyb) * rb, iz = u / nyb;
+    const int nr = min(rb, ny - iy0);
     const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
-    const int dy0 = max(-p, -iy), dy1 = min(p, ny - 1 - iy);
     const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
+    const int i0 = (iz * ny + iy0) * nx + ix;
+    const int y0 = max(0, iy0 - p), y1 = min(ny - 1, iy0 + nr - 1 + p);
     double Kx[WX], Mx[WX];
 #pragma unroll
-    for (int u = 0; u < WX; ++u) {
-      Kx[u] = kK[ix * WX + u];
-      Mx[u] = kM[ix * WX + u];
+    for (int k = 0; k < WX; ++k) {
+      Kx[k] = kK[ix * WX + k];
+      Mx[k] = kM[ix * WX + k];
     }
-    T acc = 0;
+    T acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = 0;
     for (int dz = dz0; dz <= dz1; ++dz) {
       const double Kz = DIM == 3 ? kK[iz * WX + dz + p] : 0.0, Mz = DIM == 3 ? kM[iz * WX + dz + p] : 0.0;
-      for (int dy = dy0; dy <= dy1; ++dy) {
-        const double Ky = kK[iy * WX + dy + p], My = kM[iy * WX + dy + p];
-        const T* xr = x + i + (dz * ny + dy) * nx;
-        T vv[WX], xx[WX];
+      for (int y = y0; y <= y1; ++y) {
+        const T* xr = x + ((iz + dz) * ny + y) * nx + ix;
+        T xx[WX];
 #pragma unroll
-        for (int u = 0; u < WX; ++u) {
-          const int dx = u - WX / 2;
-          const bool ok = dx >= dx0 && dx <= dx1;
-          vv[u] = (T)(DIM == 3 ? kron3(Kx[u], Mx[u], Ky, My, Kz, Mz) : kron2(Kx[u], Mx[u], Ky, My));
-          xx[u] = xr[ok ? dx : 0];
+        for (int k = 0; k < WX; ++k) {
+          const int dx = k - WX / 2;
+          xx[k] = xr[dx >= dx0 && dx <= dx1 ? dx : 0];
         }
 #pragma unroll
-        for (int u = 0; u < WX; ++u) {
-          const int dx = u - WX / 2;
-          acc += (dx >= dx0 && dx <= dx1 ? vv[u] : (T)0) * xx[u];
+        for (int q = 0; q < RB; ++q) {
+          const int dy = y - iy0 - q;
+          if (q < nr && dy >= -p && dy <= p) {
+            const int iy = iy0 + q;
+            const double Ky = kK[iy * WX + dy + p], My = kM[iy * WX + dy + p];
+#pragma unroll
+            for (int k = 0; k < WX; ++k) {
+              const int dx = k - WX / 2;
+              const T c = (T)(DIM == 3 ? kron3(Kx[k], Mx[k], Ky, My, Kz, Mz) : kron2(Kx[k], Mx[k], Ky, My));
+              acc[q] += (dx >= dx0 && dx <= dx1 ? c : (T)0) * xx[k];
+            }
+          }
         }
       }
     }
-    const T res = PLAIN ? acc : b[i] - acc;  // PLAIN: r = A x
-    r[i] = res;
-    sq += (double)res * (double)res;
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (q < nr) {
+        const int i = i0 + q * nx;
+        const T res = PLAIN ? acc[q] : b[i] - acc[q];  // PLAIN: r = A x
+        r[i] = res;
+        sq += (double)res * (double)res;
+      }
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = sq;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  resid_partial(sq, partial);
 }
 
 // y = d .* (M x) (or y += d .* (M x) with ADD) for a transfer M between the
@@ -253,6 +310,57 @@ __global__ __launch_bounds__(256) void xgrid_spmv(int nrow, int nxr, int nxc, in
         const T* vr = V + (size_t)((DIM == 3 ? kz * W : 0) + ky) * W * nrow + i;
         const T* xr = x + ((size_t)(jz + kz) * nxc + (jy + ky)) * nxc + jx;
         for (int kx = kx0; kx < kx1; ++kx) acc += vr[(int64_t)kx * nrow] * xr[kx];
+      }
+    out[i] = ADD ? out[i] + d[i] * acc : d[i] * acc;
+  }
+}
+
+// xgrid_spmv for a transfer that is the Kronecker product of one 1-D matrix
+// in every direction (P on the unit box, and R = P^T): the value of slot
+// (kz, ky, kx) of row (ix, iy, iz) is formed from the 1-D factor's entries
+// tab[ix W + kx] * tab[iy W + ky] (* tab[iz W + kz]), in the assembly's order
+// and rounding, so it equals the stored value; same loops and sums as
+// xgrid_spmv, so the results agree bit for bit.  KW > 0: W <= KW, and the
+// row's x-factors are held in registers (loaded once, not per ky and kz);
+// KW = 0: any W, the factors read in the loop.
+__device__ __forceinline__ double kron_prod(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+template <typename T, int DIM, bool ADD, int KW>
+__global__ __launch_bounds__(256) void kron_xgrid(int nrow, int nxr, int nxc, int o, int W,
+                                                  const double* __restrict__ tab, const T* __restrict__ x,
+                                                  const T* __restrict__ d, T* out) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nrow; i += gridDim.x * 256) {
+    const int ix = i % nxr, t = i / nxr, iy = t % nxr, iz = t / nxr;
+    const int jx = ix + o, jy = iy + o, jz = DIM == 3 ? iz + o : 0;
+    const int kx0 = max(0, -jx), kx1 = min(W, nxc - jx);
+    const int ky0 = max(0, -jy), ky1 = min(W, nxc - jy);
+    const int kz0 = DIM == 3 ? max(0, -jz) : 0, kz1 = DIM == 3 ? min(W, nxc - jz) : 1;
+    double fx[KW > 0 ? KW : 1];
+    if constexpr (KW > 0) {
+#pragma unroll
+      for (int k = 0; k < KW; ++k) fx[k] = k < W ? tab[ix * W + k] : 0.0;
+    }
+    T acc = 0;
+    for (int kz = kz0; kz < kz1; ++kz)
+      for (int ky = ky0; ky < ky1; ++ky) {
+        const double ty = tab[iy * W + ky], tz = DIM == 3 ? tab[iz * W + kz] : 1.0;
+        const T* xr = x + ((size_t)(jz + kz) * nxc + (jy + ky)) * nxc + jx;
+        if constexpr (KW > 0) {
+#pragma unroll
+          for (int k = 0; k < KW; ++k)
+            if (k >= kx0 && k < kx1) {
+              const double c = DIM == 3 ? kron_prod(kron_prod(fx[k], ty), tz) : kron_prod(fx[k], ty);
+              acc += (T)c * xr[k];
+            }
+        } else {
+          for (int kx = kx0; kx < kx1; ++kx) {
+            const double tx = tab[ix * W + kx];
+            const double c = DIM == 3 ? kron_prod(kron_prod(tx, ty), tz) : kron_prod(tx, ty);
+            acc += (T)c * xr[kx];
+          }
+        }
       }
     out[i] = ADD ? out[i] + d[i] * acc : d[i] * acc;
   }

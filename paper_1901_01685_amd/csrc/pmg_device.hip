@@ -569,6 +569,34 @@ pmg_status upload_xstencil(pmgdev::DevArena& mem, const pmg::Csr& M, int dim, in
   return PMG_OK;
 }
 
+// A transfer on the unit box as the 1-D factor of its Kronecker product
+// (pmg::kron_xgrid): row ix of the nxr^d grid, slot kx -> column ix + lo + kx
+// of the nxc^d grid; P's factor is X (rows: degree-p functions), R's is X^T.
+pmg_status upload_xkron(pmgdev::DevArena& mem, const pmg::HostOps& H, const pmg::Csr& M, bool transposed, int dim,
+                        int nxr, int nxc, DevXStencil& D) {
+  int lo = 0, W = 0;
+  xstencil_shape(M, dim, nxr, nxc, lo, W);
+  if (M.nnz() == 0 || W <= 0) return PMG_OK;
+  auto X = [&](int i, int j) {  // full indices
+    const int k = j - i + H.xlo;
+    return i < 0 || i >= H.xnr || k < 0 || k >= H.xw ? 0.0 : H.kX[(size_t)i * H.xw + k];
+  };
+  std::vector<double> tab((size_t)nxr * W, 0.0);
+  for (int ix = 0; ix < nxr; ++ix)
+    for (int kx = 0; kx < W; ++kx) {
+      const int jx = ix + lo + kx;
+      if (jx < 0 || jx >= nxc) continue;
+      tab[(size_t)ix * W + kx] = transposed ? X(jx + 1, ix + 1) : X(ix + 1, jx + 1);
+    }
+  pmg_status s;
+  if ((s = mem.upload(&D.tab, tab.data(), tab.size()))) return s;
+  D.nxr = nxr;
+  D.nxc = nxc;
+  D.o = lo;
+  D.W = W;
+  return PMG_OK;
+}
+
 // Host slot-major order (slot u of lane l at ptr + 64 u + l) to the device's
 // 16-byte groups of G slots per lane (ptr + 64 u + G l + u % G).  Chunks start
 // at multiples of 64 * kColGroup entries, so the groups never straddle two
@@ -728,6 +756,24 @@ void csr_launch(int mode, int nrows, const int* rows, const DevMat& M, const T* 
 template <typename T>
 void transfer(const DevMat& M, const DevXStencil& X, int dim, const T* x, const T* d, T* out, bool add,
               hipStream_t st) {
+  if (X.tab) {
+    const unsigned grid = std::min<unsigned>(nblocks(M.nrows, 256), kMaxCsrBlocks);
+#define PMG_KRON_X(D, ADD, KW) \
+  pmg::kron_xgrid<T, D, ADD, KW><<<grid, 256, 0, st>>>(M.nrows, X.nxr, X.nxc, X.o, X.W, X.tab, x, d, out)
+#define PMG_KRON_XW(D, ADD) \
+  if (X.W <= 8)             \
+    PMG_KRON_X(D, ADD, 8);  \
+  else                      \
+    PMG_KRON_X(D, ADD, 0)
+    if (dim == 2) {
+      if (add) PMG_KRON_XW(2, true); else PMG_KRON_XW(2, false);
+    } else {
+      if (add) PMG_KRON_XW(3, true); else PMG_KRON_XW(3, false);
+    }
+#undef PMG_KRON_XW
+#undef PMG_KRON_X
+    return;
+  }
   if (X.v) {
     const T* V;
     if constexpr (sizeof(T) == 8) V = X.v; else V = X.v32;
@@ -750,15 +796,31 @@ void transfer(const DevMat& M, const DevXStencil& X, int dim, const T* x, const 
   csr_launch<T>(add ? pmg::kScaleAdd : pmg::kScale, M.nrows, nullptr, M, v, x, nullptr, d, out, nullptr, st);
 }
 
+// Rows per thread of a residual launch: kResidRows while that still leaves
+// about three waves per SIMD on the 256 CUs, else one row, for the latency
+// of the loads.  The stencil and Kronecker kernels take the same rows per
+// thread and workgroup, so their block partials are the same sums.
+constexpr int kResidMinThreads = 3 * 4 * 256 * 64;
+int resid_rows(const DevStencil& S, int n) {
+  return pmg::resid_threads(n, S.nx, S.ny, pmg::kResidRows) >= kResidMinThreads ? pmg::kResidRows : 1;
+}
+
+// Workgroups of a residual launch (grid-stride beyond kMaxCsrBlocks
+// workgroups), which is also its number of partials.
+unsigned resid_grid(const DevStencil& S, int n) {
+  return std::min<unsigned>(nblocks(pmg::resid_threads(n, S.nx, S.ny, resid_rows(S, n)), 256), kMaxCsrBlocks);
+}
+
 // stencil_resid with the offset loop unrolled for stencil widths up to 11
 // (degrees 1..5), the runtime loop otherwise.
 template <typename T, int DIM, bool PLAIN>
 void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const T* x, const T* b, T* r,
                     double* partial, hipStream_t st) {
+  const int rb = resid_rows(S, n);
   switch (2 * S.p + 1) {
 #define PMG_STENCIL_W(W)                                                                            \
   case W:                                                                                           \
-    pmg::stencil_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial); \
+    pmg::stencil_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, rb, V, x, b, r, partial); \
     return;
     PMG_STENCIL_W(3)
     PMG_STENCIL_W(5)
@@ -767,7 +829,7 @@ void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const
     PMG_STENCIL_W(11)
 #undef PMG_STENCIL_W
     default:
-      pmg::stencil_resid<T, DIM, PLAIN, 0><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
+      pmg::stencil_resid<T, DIM, PLAIN, 0><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, rb, V, x, b, r, partial);
   }
 }
 
@@ -775,10 +837,11 @@ void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const
 template <typename T, int DIM, bool PLAIN>
 void launch_kron(const DevStencil& S, int n, unsigned grid, const T* x, const T* b, T* r, double* partial,
                  hipStream_t st) {
+  const int rb = resid_rows(S, n);
   switch (2 * S.p + 1) {
 #define PMG_KRON_W(W)                                                                                   \
   case W:                                                                                               \
-    pmg::kron_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.p, S.kK, S.kM, x, b, r, partial); \
+    pmg::kron_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.p, rb, S.kK, S.kM, x, b, r, partial); \
     return;
     PMG_KRON_W(3)
     PMG_KRON_W(5)
@@ -796,7 +859,7 @@ unsigned resid_a(pmg_handle h, const T* x, const T* b, T* r, double* partial, hi
   const DevStencil& S = h->As;
   if (S.kK) {
     const int n = h->A.nrows;
-    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    const unsigned grid = resid_grid(S, n);
     if (S.dim == 2)
       launch_kron<T, 2, false>(S, n, grid, x, b, r, partial, st);
     else
@@ -807,7 +870,7 @@ unsigned resid_a(pmg_handle h, const T* x, const T* b, T* r, double* partial, hi
     const T* V;
     if constexpr (sizeof(T) == 8) V = S.v; else V = S.v32;
     const int n = h->A.nrows;
-    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    const unsigned grid = resid_grid(S, n);
     if (S.dim == 2)
       launch_stencil<T, 2, false>(S, n, grid, V, x, b, r, partial, st);
     else
@@ -1301,7 +1364,7 @@ void matvec_a(pmg_handle h, Workspace& ws, const double* x, double* y, hipStream
   const DevStencil& S = h->As;
   if (S.kK) {
     const int n = h->A.nrows;
-    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    const unsigned grid = resid_grid(S, n);
     if (S.dim == 2)
       launch_kron<double, 2, true>(S, n, grid, x, x, y, ws.partial, st);
     else
@@ -1310,7 +1373,7 @@ void matvec_a(pmg_handle h, Workspace& ws, const double* x, double* y, hipStream
   }
   if (S.v) {
     const int n = h->A.nrows;
-    const unsigned grid = std::min<unsigned>(nblocks(n, 256), kMaxCsrBlocks);
+    const unsigned grid = resid_grid(S, n);
     if (S.dim == 2)
       launch_stencil<double, 2, true>(S, n, grid, S.v, x, x, y, ws.partial, st);
     else
@@ -1676,12 +1739,21 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
   I.bytes_trisolve_l = 12 * I.nnz_l + 4 * (n + 1) + 16 * n;
   I.bytes_trisolve_u = 12 * I.nnz_u + 4 * (n + 1) + 32 * n;
   {
+    const bool cmass = sp.consistent_mass;
     const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
     int lo, W;
     const int64_t sr = n1 > 0 ? xstencil_shape(H.R, prob->dim, nx1, nxp, lo, W) : 0;
+    const int wr = W;
     const int64_t sp = n1 > 0 ? xstencil_shape(H.P, prob->dim, nxp, nx1, lo, W) : 0;
-    I.bytes_restrict = (sr ? 8 * sr * n1 : 12 * I.nnz_r + 4 * (n1 + 1)) + 8 * n + 16 * n1;
-    I.bytes_prolong = (sp ? 8 * sp * n : 12 * I.nnz_p + 4 * (n + 1)) + 8 * n1 + 24 * n;
+    const int wp = W;
+    // the transfers on the box from the 1-D factor of their Kronecker product
+    // (not with consistent masses, which apply R and P in CSR)
+    h->x_kron = o.kron_residual && n1 > 0 && !H.kX.empty() && !cmass;
+    I.transfer_layout = h->x_kron ? 2 : (n1 > 0 && sr && sp) ? 1 : 0;
+    I.bytes_restrict = (h->x_kron ? 8 * (int64_t)nx1 * wr : sr ? 8 * sr * n1 : 12 * I.nnz_r + 4 * (n1 + 1)) +
+                       8 * n + 16 * n1;
+    I.bytes_prolong = (h->x_kron ? 8 * (int64_t)nxp * wp : sp ? 8 * sp * n : 12 * I.nnz_p + 4 * (n + 1)) +
+                      8 * n1 + 24 * n;
   }
   int64_t bc = 0;
   for (int l = 0; l < H.nlev; ++l) {
@@ -1723,12 +1795,17 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     if (mixed && (s = size_tri_grid<float>(o.device, o.tri_waves_per_cu, h->tl, h->tu))) return s;
     if (n1 > 0) {
       const int nxp = prob->n_elem + prob->degree - 2, nx1 = prob->n_elem + sp.cdeg - 2;
-      if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
-      if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
+      if (h->x_kron) {
+        if ((s = upload_xkron(m, H, H.R, true, prob->dim, nx1, nxp, h->Rs))) return s;
+        if ((s = upload_xkron(m, H, H.P, false, prob->dim, nxp, nx1, h->Ps))) return s;
+      } else {
+        if ((s = upload_xstencil(m, H.R, prob->dim, nx1, nxp, h->Rs, mixed))) return s;
+        if ((s = upload_xstencil(m, H.P, prob->dim, nxp, nx1, h->Ps, mixed))) return s;
+      }
       // (the consistent-mass transfers apply R and P unscaled, in CSR)
-      if (h->Rs.v && !sp.consistent_mass) describe_mat(H.R, h->R);
+      if ((h->Rs.v || h->Rs.tab) && !sp.consistent_mass) describe_mat(H.R, h->R);
       else if ((s = upload_mat(m, H.R, h->R, mixed))) return s;
-      if (h->Ps.v && !sp.consistent_mass) describe_mat(H.P, h->P);
+      if ((h->Ps.v || h->Ps.tab) && !sp.consistent_mass) describe_mat(H.P, h->P);
       else if ((s = upload_mat(m, H.P, h->P, mixed))) return s;
       if (sp.consistent_mass) {
         if ((s = upload_mat(m, H.Mp, h->Mp, false))) return s;

@@ -47,6 +47,12 @@ struct HostOps {
   // for other problems.
   int nk = 0;
   std::vector<double> kK, kM;
+  // On the unit box P is the Kronecker product of one 1-D matrix X (rows the
+  // degree-p functions, columns the coarse-space ones, full indices) in every
+  // direction, and R its transpose: X as a band (entry (i, j) at
+  // i * xw + j - i + xlo, xnr rows); empty on other geometries.
+  int xnr = 0, xlo = 0, xw = 0;
+  std::vector<double> kX;
   int nlev = 0;
   std::vector<int> lnel, ln;   // elements / unknowns per degree-1 level
   std::vector<Csr> A1;         // rediscretised degree-1 operators

@@ -79,6 +79,7 @@ struct DevXStencil {
   int nxr = 0, nxc = 0, o = 0, W = 0;
   double* v = nullptr;
   float* v32 = nullptr;
+  double* tab = nullptr;  // Kronecker factor (pmg::kron_xgrid) instead of v: nxr x W
 };
 
 // Schedule and chunk-sliced factor of one triangular solve (see TriDev).
@@ -155,6 +156,7 @@ struct pmg_handle_s {
   pmgdev::DevStencil As;  // A in stencil layout (As.v == nullptr: CSR is used)
   int a_stencil = 0;      // offsets of that layout, 0 if CSR is used
   bool a_kron = false;    // residual from the Kronecker factors (As.kK, As.kM)
+  bool x_kron = false;    // p-transfers from their Kronecker factor (Rs.tab, Ps.tab)
   pmgdev::DevXStencil Rs, Ps;  // P_p^1 and P_1^p in stencil layout
   std::vector<pmgdev::DevMat> A1, Ph, Rh;
   std::vector<pmg::GridLevel> grid;  // degree-1 levels in stencil layout (empty: CSR path)

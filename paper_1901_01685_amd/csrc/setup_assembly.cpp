@@ -827,6 +827,10 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
     }
     Band1D X = matrix_1d(1, p, cdeg, nel, p + 1);
     H.P = kron_assemble(dim, {std::vector<const Band1D*>(dim, &X)}, th);
+    H.xnr = X.nr;
+    H.xlo = X.lo;
+    H.xw = X.width;
+    H.kX = X.a;
     // lumped masses = int Phi_i = product of 1-D integrals; load vector
     // f = pi^2 (sum k^2) prod_a int sin(k_a pi x) phi
     auto ip = integrals_1d(p, nel, p + 1, 0), i1 = integrals_1d(cdeg, nel, cdeg + 1, 0);
