@@ -37,18 +37,20 @@ def kernel_map(info, dim, degree):
     Kronecker factors on the box, the stencil layout, or CSR."""
     kron_a = info.residual_layout == 2
     stencil_a = info.residual_layout == 1
+    rb = info.resid_rows  # rows per thread, the residual kernels' last template argument
 
     def transfer(add, cls):
         if info.transfer_layout == 2:
-            return f"kron_xgrid<double, {dim}, {add}>"
+            # the 1-D factor has W = p + 2 entries per row; held in registers up to 8
+            return f"kron_xgrid<double, {dim}, {add}, {8 if degree + 2 <= 8 else 0}>"
         if info.transfer_layout == 1:
             return f"xgrid_spmv<double, {dim}, {add}>"
         return f"csr_kernel<double, G, {cls}>"
     return {
         # the stencil kernel is instantiated per stencil width up to 11 (degree 5)
-        "residual": (f"kron_resid<double, {dim}, false, {2 * degree + 1}>" if kron_a
-                     else (f"stencil_resid<double, {dim}, false, {2 * degree + 1}>" if degree <= 5
-                           else f"stencil_resid<double, {dim}, false, 0>") if stencil_a
+        "residual": (f"kron_resid<double, {dim}, false, {2 * degree + 1}, {rb}>" if kron_a
+                     else (f"stencil_resid<double, {dim}, false, {2 * degree + 1}, {rb}>" if degree <= 5
+                           else f"stencil_resid<double, {dim}, false, 0, {rb}>") if stencil_a
                      else "csr_kernel<double, G, 0>", "bytes_spmv"),
         "lower": ("trisolve_lower<double>", "bytes_trisolve_l"),
         "upper": ("trisolve_upper<double>", "bytes_trisolve_u"),

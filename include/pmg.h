@@ -213,6 +213,8 @@ typedef struct {
   int32_t residual_layout;    /* how the residual reads A: 0 CSR, 1 stencil layout, 2 Kronecker
                                  factors (pmg_options.kron_residual) */
   int32_t transfer_layout;    /* the same for the p-transfers R and P */
+  int32_t resid_rows;         /* rows in y that one thread of the residual kernels takes (4 on
+                                 grids that still fill the device that way, else 1; 0 with CSR) */
 } pmg_info;
 
 /* ILUT ordering (Section 3, "Smoother": the factorisation follows a

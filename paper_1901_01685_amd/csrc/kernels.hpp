@@ -91,10 +91,10 @@ __global__ __launch_bounds__(256) void csr_kernel(int nrows, const int* __restri
   }
 }
 
-// Rows of the residual kernels per thread: rb <= kResidRows consecutive rows
-// in y of one grid column (ix, iz), so a line of x is loaded once for all of
-// them (2p + rb lines instead of (2p + 1) rb); the lanes of a wave hold
-// consecutive ix, so every load and store is contiguous across the wave.
+// Rows of the residual kernels per thread: RB (1 or kResidRows) consecutive
+// rows in y of one grid column (ix, iz), so a line of x is loaded once for
+// all of them (2p + RB lines instead of (2p + 1) RB); the lanes of a wave
+// hold consecutive ix, so every load and store is contiguous across the wave.
 constexpr int kResidRows = 4;
 
 __host__ __device__ inline int resid_threads(int n, int nx, int ny, int rb) {
@@ -121,22 +121,21 @@ __device__ __forceinline__ void resid_partial(double sq, double* partial) {
 // (dz, dy, dx), 0 where the offset leaves the grid), so no column indices
 // are stored and both V and x are read contiguously across a wave's rows.
 // Each row's sum runs over dz, dy, dx ascending, whatever line of x is
-// loaded first; a thread takes rb rows (resid_threads threads).
+// loaded first; a thread takes RB rows (resid_threads threads).
 // WX > 0: the stencil width 2 p + 1 known at compile time, so the offsets of
 // a stencil row are unrolled and all their loads issued together (offsets
 // outside the grid read offset 0 with weight 0, which adds an exact zero).
-template <typename T, int DIM, bool PLAIN = false, int WX = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void stencil_resid(int n, int nx, int ny, int p, int rb, const T* __restrict__ V,
+template <typename T, int DIM, bool PLAIN, int WX, int RB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void stencil_resid(int n, int nx, int ny, int p, const T* __restrict__ V,
                                                      const T* __restrict__ x, const T* __restrict__ b,
                                                      T* __restrict__ r, double* __restrict__ partial) {
-  constexpr int RB = kResidRows;
   const int w = 2 * p + 1;
   const int nz = DIM == 3 ? n / (nx * ny) : 1;
-  const int nyb = (ny + rb - 1) / rb, nt = nx * nyb * nz;
+  const int nyb = (ny + RB - 1) / RB, nt = nx * nyb * nz;
   double sq = 0.0;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
-    const int ix = t % nx, u = t / nx, iy0 = (u % nyb) * rb, iz = u / nyb;
-    const int nr = min(rb, ny - iy0);
+    const int ix = t % nx, u = t / nx, iy0 = (u % nyb) * RB, iz = u / nyb;
+    const int nr = min(RB, ny - iy0);
     const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
     const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
     const int i0 = (iz * ny + iy0) * nx + ix;  // row (ix, iy0, iz)
@@ -226,18 +225,17 @@ __device__ __forceinline__ double kron3(double Kx, double Mx, double Ky, double 
 // equal the stored values, so both kernels give the same results bit for
 // bit.  The row's x-factors stay in registers; the y- and z-factors are
 // loaded per offset line (the same for the lanes of one grid line).
-template <typename T, int DIM, bool PLAIN, int WX>
+template <typename T, int DIM, bool PLAIN, int WX, int RB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void kron_resid(
-    int n, int nx, int p, int rb, const double* __restrict__ kK, const double* __restrict__ kM,
-    const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r, double* __restrict__ partial) {
-  constexpr int RB = kResidRows;
+    int n, int nx, int p, const double* __restrict__ kK, const double* __restrict__ kM, const T* __restrict__ x,
+    const T* __restrict__ b, T* __restrict__ r, double* __restrict__ partial) {
   const int ny = nx;
   const int nz = DIM == 3 ? n / (nx * ny) : 1;
-  const int nyb = (ny + rb - 1) / rb, nt = nx * nyb * nz;
+  const int nyb = (ny + RB - 1) / RB, nt = nx * nyb * nz;
   double sq = 0.0;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
-    const int ix = t % nx, u = t / nx, iy0 = (u % nyb) * rb, iz = u / nyb;
-    const int nr = min(rb, ny - iy0);
+    const int ix = t % nx, u = t / nx, iy0 = (u % nyb) * RB, iz = u / nyb;
+    const int nr = min(RB, ny - iy0);
     const int dx0 = max(-p, -ix), dx1 = min(p, nx - 1 - ix);
     const int dz0 = DIM == 3 ? max(-p, -iz) : 0, dz1 = DIM == 3 ? min(p, nz - 1 - iz) : 0;
     const int i0 = (iz * ny + iy0) * nx + ix;

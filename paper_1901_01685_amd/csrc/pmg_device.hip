@@ -801,9 +801,10 @@ void transfer(const DevMat& M, const DevXStencil& X, int dim, const T* x, const 
 // of the loads.  The stencil and Kronecker kernels take the same rows per
 // thread and workgroup, so their block partials are the same sums.
 constexpr int kResidMinThreads = 3 * 4 * 256 * 64;
-int resid_rows(const DevStencil& S, int n) {
-  return pmg::resid_threads(n, S.nx, S.ny, pmg::kResidRows) >= kResidMinThreads ? pmg::kResidRows : 1;
+int resid_rows(int n, int nx, int ny) {
+  return pmg::resid_threads(n, nx, ny, pmg::kResidRows) >= kResidMinThreads ? pmg::kResidRows : 1;
 }
+int resid_rows(const DevStencil& S, int n) { return resid_rows(n, S.nx, S.ny); }
 
 // Workgroups of a residual launch (grid-stride beyond kMaxCsrBlocks
 // workgroups), which is also its number of partials.
@@ -812,15 +813,14 @@ unsigned resid_grid(const DevStencil& S, int n) {
 }
 
 // stencil_resid with the offset loop unrolled for stencil widths up to 11
-// (degrees 1..5), the runtime loop otherwise.
-template <typename T, int DIM, bool PLAIN>
-void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const T* x, const T* b, T* r,
-                    double* partial, hipStream_t st) {
-  const int rb = resid_rows(S, n);
+// (degrees 1..5), the runtime loop otherwise; RB rows per thread.
+template <typename T, int DIM, bool PLAIN, int RB>
+void launch_stencil_rb(const DevStencil& S, int n, unsigned grid, const T* V, const T* x, const T* b, T* r,
+                       double* partial, hipStream_t st) {
   switch (2 * S.p + 1) {
-#define PMG_STENCIL_W(W)                                                                            \
-  case W:                                                                                           \
-    pmg::stencil_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, rb, V, x, b, r, partial); \
+#define PMG_STENCIL_W(W)                                                                                    \
+  case W:                                                                                                   \
+    pmg::stencil_resid<T, DIM, PLAIN, W, RB><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial); \
     return;
     PMG_STENCIL_W(3)
     PMG_STENCIL_W(5)
@@ -829,19 +829,26 @@ void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const
     PMG_STENCIL_W(11)
 #undef PMG_STENCIL_W
     default:
-      pmg::stencil_resid<T, DIM, PLAIN, 0><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, rb, V, x, b, r, partial);
+      pmg::stencil_resid<T, DIM, PLAIN, 0, RB><<<grid, 256, 0, st>>>(n, S.nx, S.ny, S.p, V, x, b, r, partial);
   }
 }
-
-// kron_resid with the offset loop unrolled (widths 3..11)
 template <typename T, int DIM, bool PLAIN>
-void launch_kron(const DevStencil& S, int n, unsigned grid, const T* x, const T* b, T* r, double* partial,
-                 hipStream_t st) {
-  const int rb = resid_rows(S, n);
+void launch_stencil(const DevStencil& S, int n, unsigned grid, const T* V, const T* x, const T* b, T* r,
+                    double* partial, hipStream_t st) {
+  if (resid_rows(S, n) == pmg::kResidRows)
+    launch_stencil_rb<T, DIM, PLAIN, pmg::kResidRows>(S, n, grid, V, x, b, r, partial, st);
+  else
+    launch_stencil_rb<T, DIM, PLAIN, 1>(S, n, grid, V, x, b, r, partial, st);
+}
+
+// kron_resid with the offset loop unrolled (widths 3..11); RB rows per thread.
+template <typename T, int DIM, bool PLAIN, int RB>
+void launch_kron_rb(const DevStencil& S, int n, unsigned grid, const T* x, const T* b, T* r, double* partial,
+                    hipStream_t st) {
   switch (2 * S.p + 1) {
-#define PMG_KRON_W(W)                                                                                   \
-  case W:                                                                                               \
-    pmg::kron_resid<T, DIM, PLAIN, W><<<grid, 256, 0, st>>>(n, S.nx, S.p, rb, S.kK, S.kM, x, b, r, partial); \
+#define PMG_KRON_W(W)                                                                                       \
+  case W:                                                                                                   \
+    pmg::kron_resid<T, DIM, PLAIN, W, RB><<<grid, 256, 0, st>>>(n, S.nx, S.p, S.kK, S.kM, x, b, r, partial); \
     return;
     PMG_KRON_W(3)
     PMG_KRON_W(5)
@@ -850,6 +857,14 @@ void launch_kron(const DevStencil& S, int n, unsigned grid, const T* x, const T*
     PMG_KRON_W(11)
 #undef PMG_KRON_W
   }
+}
+template <typename T, int DIM, bool PLAIN>
+void launch_kron(const DevStencil& S, int n, unsigned grid, const T* x, const T* b, T* r, double* partial,
+                 hipStream_t st) {
+  if (resid_rows(S, n) == pmg::kResidRows)
+    launch_kron_rb<T, DIM, PLAIN, pmg::kResidRows>(S, n, grid, x, b, r, partial, st);
+  else
+    launch_kron_rb<T, DIM, PLAIN, 1>(S, n, grid, x, b, r, partial, st);
 }
 
 // r = b - A_{h,p} x with block partials of sum(r^2) in partial; returns the
@@ -1733,6 +1748,10 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     h->a_stencil = h->a_kron ? (prob->dim == 2 ? w * w : w * w * w) : stencil_slots(H);
   }
   I.residual_layout = h->a_kron ? 2 : h->a_stencil ? 1 : 0;
+  {
+    const int nxa = prob->n_elem + prob->degree - 2;  // grid lines of A's layouts (both axes)
+    I.resid_rows = I.residual_layout ? resid_rows((int)n, nxa, nxa) : 0;
+  }
   I.bytes_spmv = h->a_kron ? 2 * 8 * (int64_t)H.kK.size() + 24 * (int64_t)H.n
                  : h->a_stencil ? 8 * (int64_t)h->a_stencil * H.n + 24 * (int64_t)H.n
                                 : 12 * I.nnz_a + 4 * (n + 1) + 24 * n;

@@ -24,6 +24,7 @@ def test_kron_residual_equals_the_stencil_residual_bitwise(dim, p, nel):
     k = pmg.Solver(dim, p, nel, device=0, kron_residual=1)
     s = pmg.Solver(dim, p, nel, device=0, kron_residual=0)
     assert k.info.residual_layout == 2 and s.info.residual_layout == 1
+    assert k.info.resid_rows == 1 and s.info.resid_rows == 1
     assert k.info.transfer_layout == 2 and s.info.transfer_layout in (0, 1)
     assert k.info.bytes_spmv < s.info.bytes_spmv and k.info.bytes_restrict < s.info.bytes_restrict
     g = torch.Generator(device="cpu").manual_seed(dim * 100 + p * 10 + nel)
@@ -96,6 +97,7 @@ def test_four_rows_per_thread_on_a_large_grid():
     k = pmg.Solver(2, 3, 896, device=0, kron_residual=1, precision=pmg.FP32_IN_FP64)
     s = pmg.Solver(2, 3, 896, device=0, kron_residual=0, precision=pmg.FP32_IN_FP64)
     assert k.info.residual_layout == 2 and s.info.residual_layout == 1
+    assert k.info.resid_rows == 4 and s.info.resid_rows == 4
     print("four rows per thread: n", k.n, flush=True)
     g = torch.Generator(device="cpu").manual_seed(896)
     xh = torch.rand(k.n, generator=g, dtype=torch.float64) * 2 - 1

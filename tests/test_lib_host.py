@@ -110,6 +110,9 @@ def test_info_sizes_and_bytes():
     j = P.Solver(3, 3, 8, device=-1, kron_residual=0).info
     assert j.residual_layout == 0 and j.bytes_spmv == 12 * j.nnz_a + 4 * (j.n + 1) + 24 * j.n
     assert P.Solver(3, 3, 8, device=-1).info.residual_layout == 2
+    # a residual thread takes one row on these small grids (four only where
+    # that still leaves three waves per SIMD of the 256 CUs); none with CSR
+    assert i.resid_rows == 1 and k.resid_rows == 1 and j.resid_rows == 0
 
 
 def test_status_codes_host():
