@@ -226,7 +226,7 @@ __device__ __forceinline__ double kron3(double Kx, double Mx, double Ky, double 
 // bit.  The row's x-factors stay in registers; the y- and z-factors are
 // loaded per offset line (the same for the lanes of one grid line).
 template <typename T, int DIM, bool PLAIN, int WX, int RB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void kron_resid(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void kron_resid(
     int n, int nx, int p, const double* __restrict__ kK, const double* __restrict__ kM, const T* __restrict__ x,
     const T* __restrict__ b, T* __restrict__ r, double* __restrict__ partial) {
   const int ny = nx;
@@ -259,16 +259,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
           const int dx = k - WX / 2;
           xx[k] = xr[dx >= dx0 && dx <= dx1 ? dx : 0];
         }
+        // the y-factors of every row of the thread for this line, loaded with
+        // the line (clamped in range; unused where the line is not a neighbour)
+        double Ky[RB], My[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const int iy = min(iy0 + q, ny - 1), ky = min(max(y - iy0 - q + p, 0), WX - 1);
+          Ky[q] = kK[iy * WX + ky];
+          My[q] = kM[iy * WX + ky];
+        }
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
           const int dy = y - iy0 - q;
           if (q < nr && dy >= -p && dy <= p) {
-            const int iy = iy0 + q;
-            const double Ky = kK[iy * WX + dy + p], My = kM[iy * WX + dy + p];
 #pragma unroll
             for (int k = 0; k < WX; ++k) {
               const int dx = k - WX / 2;
-              const T c = (T)(DIM == 3 ? kron3(Kx[k], Mx[k], Ky, My, Kz, Mz) : kron2(Kx[k], Mx[k], Ky, My));
+              const T c = (T)(DIM == 3 ? kron3(Kx[k], Mx[k], Ky[q], My[q], Kz, Mz) : kron2(Kx[k], Mx[k], Ky[q], My[q]));
               acc[q] += (dx >= dx0 && dx <= dx1 ? c : (T)0) * xx[k];
             }
           }
