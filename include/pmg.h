@@ -215,6 +215,9 @@ typedef struct {
   int32_t transfer_layout;    /* the same for the p-transfers R and P */
   int32_t resid_rows;         /* rows in y that one thread of the residual kernels takes (4 on
                                  grids that still fill the device that way, else 1; 0 with CSR) */
+  int32_t coarse_kron_levels; /* 2-D degree-1 levels whose tiled smoothing forms the operator's
+                                 values from the 1-D stiffness and mass of the level (unit box,
+                                 Poisson, pmg_options.kron_residual) instead of reading them */
 } pmg_info;
 
 /* ILUT ordering (Section 3, "Smoother": the factorisation follows a

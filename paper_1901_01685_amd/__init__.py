@@ -75,7 +75,8 @@ class Info(C.Structure):
                 ("bytes_prolong", C.c_int64), ("bytes_coarse", C.c_int64), ("device_bytes", C.c_int64),
                 ("t_assembly", C.c_double), ("t_ilut", C.c_double), ("t_upload", C.c_double),
                 ("t_schedule", C.c_double), ("ilut_on_device", C.c_int32), ("residual_layout", C.c_int32),
-                ("transfer_layout", C.c_int32), ("resid_rows", C.c_int32)]
+                ("transfer_layout", C.c_int32), ("resid_rows", C.c_int32),
+                ("coarse_kron_levels", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -789,8 +789,11 @@ __device__ __forceinline__ TileBox tile_box(int nc, int tcb, int halo) {
 }
 
 // The stencil sum of grid_dot for node (ix, iy), neighbours from the LDS tile.
-__device__ __forceinline__ double tile_dot(const GridLevel& L, int ix, int iy, const double* el, const TileBox& B,
-                                           bool skip_centre, double* centre) {
+// KRON: the coefficients formed from the level's 1-D bands (kron2, the
+// assembly's products and sums), equal to the stored values bit for bit.
+template <bool KRON>
+__device__ __forceinline__ double tile_dot_t(const GridLevel& L, int ix, int iy, const double* el, const TileBox& B,
+                                             bool skip_centre, double* centre) {
   const int c = (ix & 1) | ((iy & 1) << 1);
   const int mx = (L.nx - (c & 1) + 1) / 2;
   const int t = (iy >> 1) * mx + (ix >> 1);
@@ -798,6 +801,16 @@ __device__ __forceinline__ double tile_dot(const GridLevel& L, int ix, int iy, c
   const double* vc = L.v + L.voff[c];
   const int nx = L.nx;
   const double* x = el + (iy - B.oy) * B.w + (ix - B.ox);
+  double Kx[3], Mx[3], Ky[3], My[3];
+  if constexpr (KRON) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      Kx[u] = L.kK[ix * 3 + u];
+      Mx[u] = L.kM[ix * 3 + u];
+      Ky[u] = L.kK[iy * 3 + u];
+      My[u] = L.kM[iy * 3 + u];
+    }
+  }
   double acc = 0.0;
   int k = 0;
 #pragma unroll
@@ -805,7 +818,7 @@ __device__ __forceinline__ double tile_dot(const GridLevel& L, int ix, int iy, c
 #pragma unroll
     for (int dx = -1; dx <= 1; ++dx, ++k) {
       const bool ok = ix + dx >= 0 && ix + dx < nx && iy + dy >= 0 && iy + dy < nx;
-      const double a = vc[(size_t)k * cnt + t];
+      const double a = KRON ? kron2(Kx[dx + 1], Mx[dx + 1], Ky[dy + 1], My[dy + 1]) : vc[(size_t)k * cnt + t];
       if (dx == 0 && dy == 0 && skip_centre) {
         *centre = a;
       } else {
@@ -816,6 +829,11 @@ __device__ __forceinline__ double tile_dot(const GridLevel& L, int ix, int iy, c
       }
     }
   return acc;
+}
+__device__ __forceinline__ double tile_dot(const GridLevel& L, int ix, int iy, const double* el, const TileBox& B,
+                                           bool skip_centre, double* centre) {
+  return L.kK ? tile_dot_t<true>(L, ix, iy, el, B, skip_centre, centre)
+              : tile_dot_t<false>(L, ix, iy, el, B, skip_centre, centre);
 }
 
 // Colour phases of nsweep sweeps; after them the nodes within `hend` of the

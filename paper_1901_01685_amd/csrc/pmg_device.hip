@@ -463,7 +463,8 @@ pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, b
 // h-multigrid kernels).  Leaves G empty, so the CSR path is taken, unless
 // every level's operator couples nodes only within {-1, 0, 1}^d and the
 // levels halve (nx_l = 2 nx_{l+1} + 1).
-pmg_status upload_grid_levels(pmgdev::DevArena& mem, const pmg::HostOps& H, int dim, std::vector<pmg::GridLevel>& G) {
+pmg_status upload_grid_levels(pmgdev::DevArena& mem, const pmg::HostOps& H, int dim, bool kron,
+                              std::vector<pmg::GridLevel>& G) {
   G.clear();
   if (H.nlev < 1) return PMG_OK;  // no degree-1 hierarchy (indirect projection)
   const int nl = H.nlev - 1;  // levels with smoothing (the last is solved directly)
@@ -513,6 +514,14 @@ pmg_status upload_grid_levels(pmgdev::DevArena& mem, const pmg::HostOps& H, int 
     pmg_status s = mem.upload(&d, vals[l].data(), vals[l].size());
     if (s) return s;
     out[l].v = d;
+    // 2-D Kronecker levels: the tiled kernels form the values from the bands
+    if (kron && dim == 2 && l < (int)H.k1K.size() && H.k1K[l].size() == (size_t)3 * out[l].nx) {
+      double *k, *m;
+      if ((s = mem.upload(&k, H.k1K[l].data(), H.k1K[l].size()))) return s;
+      if ((s = mem.upload(&m, H.k1M[l].data(), H.k1M[l].size()))) return s;
+      out[l].kK = k;
+      out[l].kM = m;
+    }
   }
   G = out;
   return PMG_OK;
@@ -1859,7 +1868,9 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
         if ((s = m.upload(&h->color_rows[l][c], lists[c].data(), lists[c].size()))) return s;
       }
     }
-    if ((s = upload_grid_levels(m, H, prob->dim, h->grid))) return s;
+    if ((s = upload_grid_levels(m, H, prob->dim, o.kron_residual != 0, h->grid))) return s;
+    h->info.coarse_kron_levels = 0;
+    for (const pmg::GridLevel& L : h->grid) h->info.coarse_kron_levels += L.kK != nullptr;
     if (!h->grid.empty() && tiled_gs(h.get())) {
       const size_t dn = tile_lds_bytes(30, h->colors, pmg::kTileMaxSweeps, true);
       const size_t up = tile_lds_bytes(30, h->colors, pmg::kTileMaxSweeps, false);

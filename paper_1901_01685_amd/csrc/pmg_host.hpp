@@ -56,6 +56,11 @@ struct HostOps {
   int nlev = 0;
   std::vector<int> lnel, ln;   // elements / unknowns per degree-1 level
   std::vector<Csr> A1;         // rediscretised degree-1 operators
+  // Poisson on the unit box: A1[l] = K1 (x) M1 + M1 (x) K1 (+ the third term
+  // in 3-D) from the level's 1-D degree-1 stiffness and mass, as bands of
+  // their interior rows (3 entries per row, 0 outside the grid); empty
+  // vectors for other problems.
+  std::vector<std::vector<double>> k1K, k1M;
   std::vector<Csr> Ph, Rh;     // canonical prolongation level l <- l+1, and transpose
   std::vector<double> coarse_inv;  // dense inverse of the coarsest A1 (row-major)
   int n_coarse = 0;

@@ -895,6 +895,8 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
   // ---- degree-1 hierarchy by rediscretisation
   int ne = nel;
   H.A1.clear();
+  H.k1K.clear();
+  H.k1M.clear();
   H.Ph.clear();
   H.Rh.clear();
   H.lnel.clear();
@@ -911,6 +913,8 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
   for (;;) {
     H.lnel.push_back(ne);
     H.ln.push_back((int)ipow(ne - 1, dim));
+    H.k1K.emplace_back();
+    H.k1M.emplace_back();
     if (sp.geom == 0 && sp.pde == 1) {
       const CdrTerms c = cdr_terms(1, ne, 2);
       H.A1.push_back(kron_assemble(dim, c.terms(), th));
@@ -923,6 +927,18 @@ int assemble_all(const SetupParams& sp, HostOps& H, std::string& msg) {
         t1.push_back(t);
       }
       H.A1.push_back(kron_assemble(dim, t1, th));
+      // the 1-D factors as bands of the interior rows (interior index i is
+      // full index i + 1)
+      const int nk = ne - 1;
+      std::vector<double>&bK = H.k1K.back(), &bM = H.k1M.back();
+      bK.assign((size_t)nk * 3, 0.0);
+      bM.assign((size_t)nk * 3, 0.0);
+      for (int i = 0; i < nk; ++i)
+        for (int d = -1; d <= 1; ++d)
+          if (i + d >= 0 && i + d < nk) {
+            bK[(size_t)i * 3 + d + 1] = K1.get(i + 1, i + d + 1);
+            bM[(size_t)i * 3 + d + 1] = M1.get(i + 1, i + d + 1);
+          }
     } else {
       H.A1.push_back(element_assemble_2d(1, 0, 1, 1, ne, 2, th));
     }

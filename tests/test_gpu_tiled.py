@@ -1,6 +1,8 @@
 """Tiled smoothing on 2-D degree-1 levels (gs_tile_down / gs_tile_up) gives
 exactly what the launch-per-colour and launch-per-transfer kernels give
-(stated tolerance: bitwise; the same per-node arithmetic in the same order).
+(stated tolerance: bitwise; the same per-node arithmetic in the same order),
+also where the tiled kernels form the level's values from its 1-D Kronecker
+factors (2-D unit box, Poisson).
 Cases cover ragged last blocks, a one-node last block (the 511-node coarse
 level of h = 1/1024 in blocks of 30), two sweeps, and a 3-D problem (which
 always takes the launch-per-phase path)."""
@@ -38,6 +40,10 @@ def test_tiled_coarse_and_vcycles_match_per_phase(case):
     dim, p, nel, g, kw = case
     st = pmg.Solver(dim, p, nel, geometry=g, rhs_kind=g, device=0, tiled_gs=1, **kw)
     sp = pmg.Solver(dim, p, nel, geometry=g, rhs_kind=g, device=0, tiled_gs=0, **kw)
+    # on the 2-D unit box (Poisson) the tiled kernels form every level's
+    # values from the level's 1-D factors, the per-phase kernels read them
+    kron = dim == 2 and g == 0 and kw.get("pde", 0) == 0
+    assert (st.info.coarse_kron_levels > 0) == kron
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(11)
     # the coarse solve alone (two h-multigrid cycles on the degree-1 problem)
