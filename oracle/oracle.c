@@ -20,10 +20,10 @@
  *   basis, quadrature, geometry, assembly, lumping, transfers, P1 hierarchy,
  *   smoother algebra, V-cycle identities, CG, BiCGSTAB,
  *   the CDR operator and right-hand side of benchmark 2 .... pinned
- *   ILUT with tau = 1e-12, m = 1 (values) ........... parity unpinned: only
- *     invariants and the exact-LU limit (tau = 0, unlimited fill) are fixed
- *     by the paper and by mathematics; the values for the paper's constants
- *     are the oracle's own reading of the two dropping rules.
+ *   ILUT .... pinned by the exact-LU limit (tau = 0, unlimited fill) and by
+ *     hand-worked examples of each dropping rule (tests/golden/ilut_hand.json);
+ *     for the paper's constants tau = 1e-12, m = 1 on the full problems no
+ *     published values exist, so those values rest on the rules so pinned.
  */
 #include <math.h>
 #include <stdint.h>
