@@ -459,6 +459,28 @@ pmg_status upload_stencil(pmgdev::DevArena& mem, const pmg::HostOps& H, int S, b
   return PMG_OK;
 }
 
+// Whether the degree-1 levels take the structured kernels: the levels halve
+// (nx_l = 2 nx_{l+1} + 1) and every smoothed level's operator couples nodes
+// only within {-1, 0, 1}^d.
+bool grid_levels_structured(const pmg::HostOps& H, int dim) {
+  if (H.nlev < 2) return false;
+  for (int l = 0; l + 1 < H.nlev; ++l)
+    if (H.lnel[l] != 2 * H.lnel[l + 1]) return false;
+  for (int l = 0; l + 1 < H.nlev; ++l) {
+    const pmg::Csr& A = H.A1[l];
+    const int64_t nx = H.lnel[l] - 1;
+    for (int64_t i = 0; i < A.nrows; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int64_t j = A.ci[k];
+        for (int a = 0; a < dim; ++a) {
+          const int64_t s = a == 0 ? 1 : a == 1 ? nx : nx * nx;
+          if (std::abs((j / s) % nx - (i / s) % nx) > 1) return false;
+        }
+      }
+  }
+  return true;
+}
+
 // Degree-1 levels in colour-major stencil layout (see the structured
 // h-multigrid kernels).  Leaves G empty, so the CSR path is taken, unless
 // every level's operator couples nodes only within {-1, 0, 1}^d and the
@@ -1783,17 +1805,25 @@ static pmg_status setup_impl(const pmg_problem* prob, const pmg_options* opt, co
     I.bytes_prolong = (h->x_kron ? 8 * (int64_t)nxp * wp : sp ? 8 * sp * n : 12 * I.nnz_p + 4 * (n + 1)) +
                       8 * n1 + 24 * n;
   }
+  // degree-1 levels by the layout their kernels read: the 1-D bands (2-D
+  // box, tiled), the stencil slots (structured levels, canonical transfers
+  // without storage) or CSR
   int64_t bc = 0;
+  const bool structured = grid_levels_structured(H, prob->dim);
   for (int l = 0; l < H.nlev; ++l) {
-    const int64_t nl = H.ln[l];
+    const int64_t nl = H.ln[l], nc = l + 1 < H.nlev ? H.ln[l + 1] : 0;
     if (l == H.nlev - 1) {
       bc += 8 * (int64_t)H.n_coarse * H.n_coarse + 16 * nl;
       continue;
     }
-    const int64_t a1 = H.A1[l].nnz() * 12 + 4 * (nl + 1);
+    const bool bands = structured && o.kron_residual && tiled_gs(h.get()) && l < (int)H.k1K.size() &&
+                       !H.k1K[l].empty();
+    const int64_t a1 = bands ? 2 * 8 * (int64_t)H.k1K[l].size()
+                       : structured ? 8 * (prob->dim == 2 ? 9 : 27) * nl
+                                    : H.A1[l].nnz() * 12 + 4 * (nl + 1);
+    const int64_t rt = structured ? 0 : 12 * H.Rh[l].nnz(), pt = structured ? 0 : 12 * H.Ph[l].nnz();
     const int64_t sweeps = o.nu1 + o.nu2;
-    bc += sweeps * (a1 + 24 * nl) + (a1 + 24 * nl) + (12 * H.Rh[l].nnz() + 8 * nl + 8 * H.ln[l + 1]) +
-          (12 * H.Ph[l].nnz() + 16 * nl + 8 * H.ln[l + 1]) + 8 * H.ln[l + 1];
+    bc += sweeps * (a1 + 24 * nl) + (a1 + 24 * nl) + (rt + 8 * nl + 8 * nc) + (pt + 16 * nl + 8 * nc) + 8 * nc;
   }
   I.bytes_coarse = o.coarse_cycles * bc + 8 * n1;
   I.bytes_vcycle = (o.nu1 + o.nu2 + (n1 > 0 ? 1 : 0)) * I.bytes_spmv +
