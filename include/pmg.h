@@ -205,7 +205,8 @@ typedef struct {
   int32_t chunk_levels_l, chunk_levels_u; /* depth of their chunk dependency graphs */
   int64_t bytes_vcycle;       /* algorithmic HBM bytes of one FP64 V-cycle */
   int64_t bytes_spmv, bytes_trisolve_l, bytes_trisolve_u, bytes_restrict, bytes_prolong,
-      bytes_coarse;
+      bytes_coarse;           /* per step, each operator counted in the layout its kernels read
+                                 (1-D factors, stencil slots or CSR) and every vector once */
   int64_t device_bytes;       /* device memory held by the handle */
   double t_assembly, t_ilut, t_upload; /* setup phase times, seconds */
   double t_schedule;          /* triangular-solve schedules and sliced layouts (host), seconds */
